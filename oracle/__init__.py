@@ -1,0 +1,149 @@
+"""CPU oracle for the arbitrary-shape-surface Fresnel sum -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's ``cpu_baseline``
+leg may import this package.  The GPU path shares no code with it.
+
+``direct`` evaluates Eq. (7) of Shimobaba, Masuda and Ito (Sec. 2) -- the
+Fourier-form Fresnel sum from an arbitrary source surface, with the Fresnel
+expansion of Eq. (4), r^2 ~ z0^2 in the amplitude, the output chirp of Eq. (6)
+and the normal plane-wave incidence u_I = exp(i k d1) -- as the plain FP64 direct
+sum over source points, one sincos per term, at any set of destination pixels.
+It is written in C (``asf_oracle.c``) and parallel over pixels with OpenMP.
+
+``mp_direct`` is the same definition at 50 significant digits with mpmath, for
+tiny inputs only: it checks the FP64 rounding of ``direct``, not its formula.
+The formula itself is pinned by the tests in ``tests/test_oracle_pins.py``
+(centred DFT, textbook Gaussian-beam propagation, shift theorem, separable
+matrix form, invariants).
+
+Readings of the paper taken here: the x1.x2 term carries a minus sign (Eq. (4),
+(5), (9); Eq. (7) prints a plus); unit quadrature weights; destination pixel
+(ix, iy) at X = p2x (ix - mx // 2), Y = p2y (iy - my // 2).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "asf_oracle.c")
+_LIB = os.path.join(_HERE, "_asf_oracle.so")
+_lib = None
+
+INCIDENT = {"plane": 0, "none": 1}
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (FP64, no fast-math) into ``_asf_oracle.so``."""
+    global _lib
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+               "-fno-fast-math", "-ffp-contract=off", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+        _lib = None
+    return _LIB
+
+
+def load_library(path: str):
+    """Open a compiled oracle library (the built one, or a test's own variant)."""
+    lib = ctypes.CDLL(path)
+    lib.asf_oracle_direct.restype = ctypes.c_int
+    lib.asf_oracle_direct.argtypes = [
+        ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+    lib.asf_oracle_threads.restype = ctypes.c_int
+    lib.asf_oracle_threads.argtypes = [ctypes.c_int32]
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        _lib = load_library(_LIB)
+    return _lib
+
+
+def threads(requested: int = 0) -> int:
+    """Threads the oracle uses for ``requested`` (0 = OpenMP default)."""
+    return int(_load().asf_oracle_threads(int(requested)))
+
+
+def direct(x, y, d, u, lam, z0, p2x, p2y, mx, my, ix, iy, incident="plane", nthreads=0,
+           lib=None):
+    """u2 at destination pixels (ix[e], iy[e]) by the direct FP64 sum of Eq. (7).
+
+    x, y, d: float64 [n] source coordinates and displacement (m); u: complex [n]
+    source field (complex64 input is promoted exactly to complex128); ix, iy: int [n_eval].
+    Returns complex128 [n_eval].  Raises ValueError if some z0 - d <= 0.
+    ``lib`` selects another compiled variant (tests only); default: the built oracle.
+    """
+    lib = _load() if lib is None else lib
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.complex128)
+    ix = np.ascontiguousarray(ix, dtype=np.int32).reshape(-1)
+    iy = np.ascontiguousarray(iy, dtype=np.int32).reshape(-1)
+    n = x.shape[0]
+    if not (y.shape[0] == n and d.shape[0] == n and u.shape[0] == n):
+        raise ValueError("x, y, d, u must have equal length")
+    if ix.shape != iy.shape:
+        raise ValueError("ix and iy must have equal length")
+    out = np.empty(2 * ix.shape[0], dtype=np.float64)
+    rc = lib.asf_oracle_direct(
+        n, x.ctypes.data, y.ctypes.data, d.ctypes.data, u.ctypes.data,
+        float(lam), float(z0), float(p2x), float(p2y), int(mx), int(my),
+        INCIDENT[incident], ix.shape[0], ix.ctypes.data, iy.ctypes.data,
+        out.ctypes.data, int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle: invalid arguments or r0 = z0 - d1 <= 0")
+    return out.view(np.complex128)
+
+
+def direct_grid(x, y, d, u, lam, z0, p2x, p2y, mx, my, ix_range=None, iy_range=None,
+                incident="plane", nthreads=0, lib=None):
+    """u2 on the rectangle ix_range x iy_range (default: the whole grid), shape (rows, cols)."""
+    ixs = np.arange(mx) if ix_range is None else np.asarray(list(ix_range))
+    iys = np.arange(my) if iy_range is None else np.asarray(list(iy_range))
+    gx, gy = np.meshgrid(ixs, iys)
+    vals = direct(x, y, d, u, lam, z0, p2x, p2y, mx, my, gx.reshape(-1), gy.reshape(-1),
+                  incident, nthreads, lib)
+    return vals.reshape(len(iys), len(ixs))
+
+
+def mp_direct(x, y, d, u, lam, z0, p2x, p2y, mx, my, ix, iy, incident="plane", dps=50):
+    """The same sum as ``direct`` in mpmath at ``dps`` digits (tiny inputs only).
+
+    The FP64 inputs are taken as exact binary values (u as complex128).
+    """
+    import mpmath as mp
+
+    with mp.workdps(dps):
+        k = 2 * mp.pi / mp.mpf(lam)
+        z0m = mp.mpf(z0)
+        lamm = mp.mpf(lam)
+        out = []
+        for e in range(len(ix)):
+            X = mp.mpf(p2x) * (int(ix[e]) - int(mx) // 2)
+            Y = mp.mpf(p2y) * (int(iy[e]) - int(my) // 2)
+            s = mp.mpc(0)
+            for j in range(len(x)):
+                xj, yj, dj = mp.mpf(float(x[j])), mp.mpf(float(y[j])), mp.mpf(float(d[j]))
+                r0 = z0m - dj
+                arg = k * (-dj + (xj * xj + yj * yj) / (2 * r0) - (xj * X + yj * Y) / r0)
+                if incident == "plane":
+                    arg += k * dj
+                uj = complex(np.complex128(u[j]))
+                s += mp.mpc(uj.real, uj.imag) * mp.expj(arg)
+            post = mp.expj(k * (z0m + (X * X + Y * Y) / (2 * z0m))) / (mp.mpc(0, 1) * lamm * z0m)
+            out.append(complex(post * s))
+        return np.array(out, dtype=np.complex128)

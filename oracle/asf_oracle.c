@@ -1,0 +1,97 @@
+/*
+ * CPU oracle for the arbitrary-shape-surface Fresnel sum.  TEST INFRASTRUCTURE
+ * ONLY: tests, the smoke check and the benchmark's CPU-baseline leg call it; the
+ * product (GPU) path never links, loads or calls anything in this directory.
+ *
+ * What it computes (Shimobaba, Masuda, Ito, "Arbitrary shape surface Fresnel
+ * diffraction", Sec. 2): the Fourier-form Fresnel diffraction from a source
+ * surface displaced by d1(x1) onto a planar destination, Eq. (7), which comes
+ * from the Huygens integral on the surface (Eq. (2)-(3)) through the Fresnel
+ * expansion of r about r0 = z0 - d1 (Eq. (4)), the amplitude approximation
+ * r^2 ~ z0^2 and the output-chirp approximation r0 -> z0 (Eq. (6)).  The
+ * incident wave is a normal plane wave u_I = exp(i k d1) (the paper's choice
+ * for its experiments) or u_I = 1.
+ *
+ * The integral over the non-uniform samples is a plain sum with unit weights;
+ * callers fold any area element into u1.  The sign of the x1.x2 term is taken
+ * as minus, as in Eq. (4), Eq. (5) and the transform kernel of Eq. (9) (Eq. (7)
+ * prints a plus; with it, d1 = 0 would not reduce to the ordinary Fresnel
+ * transform).  The destination pixel (ix, iy) sits at
+ * X = p2x (ix - mx/2), Y = p2y (iy - my/2) (integer division).
+ *
+ *   u2(X, Y) = exp(i k (z0 + (X^2 + Y^2) / (2 z0))) / (i lambda z0)
+ *            * sum_j u_j u_I,j exp(i k [ -d_j + (x_j^2 + y_j^2) / (2 r0_j)
+ *                                          - (x_j X + y_j Y) / r0_j ])
+ *
+ * Everything is FP64; each term's phase is one real argument passed to sincos.
+ * The loop is the plain direct sum, O(points x pixels), parallel over pixels.
+ */
+#define _GNU_SOURCE
+#include <math.h>
+#include <stdint.h>
+#include <omp.h>
+
+#define ORACLE_INCIDENT_PLANE 0
+#define ORACLE_INCIDENT_NONE 1
+
+/* Returns the number of OpenMP threads a parallel region will use. */
+int asf_oracle_threads(int32_t requested)
+{
+    if (requested > 0) return requested;
+    return omp_get_max_threads();
+}
+
+/*
+ * n          number of source samples
+ * x, y, d    FP64 [n]: source position x1 = (x, y) and displacement d1 (m)
+ * u          FP64 [2n]: complex source field, interleaved (re, im)
+ * lambda, z0 wavelength and source-to-destination distance (m)
+ * p2x, p2y   destination pitch (m); mx, my destination grid size
+ * incident   0: plane wave exp(i k d1); 1: u_I = 1
+ * n_eval     number of destination pixels to evaluate
+ * ix, iy     int32 [n_eval]: pixel column and row
+ * out        FP64 [2 n_eval]: complex u2 at those pixels, interleaved
+ * threads    OpenMP threads (<= 0: default)
+ * Returns 0, or -1 if some r0 = z0 - d1 <= 0 or an argument is invalid.
+ */
+int asf_oracle_direct(int64_t n, const double *x, const double *y, const double *d,
+                      const double *u, double lambda, double z0, double p2x, double p2y,
+                      int32_t mx, int32_t my, int32_t incident, int64_t n_eval,
+                      const int32_t *ix, const int32_t *iy, double *out, int32_t threads)
+{
+    if (n < 0 || n_eval < 0 || !(lambda > 0.0) || !(z0 > 0.0)) return -1;
+    for (int64_t j = 0; j < n; ++j)
+        if (!(z0 - d[j] > 0.0)) return -1;
+
+    const double pi = 3.14159265358979323846;
+    const double k = 2.0 * pi / lambda;
+    const int nthr = asf_oracle_threads(threads);
+
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
+    for (int64_t e = 0; e < n_eval; ++e) {
+        const double X = p2x * (double)(ix[e] - mx / 2);
+        const double Y = p2y * (double)(iy[e] - my / 2);
+        double sr = 0.0, si = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double r0 = z0 - d[j];
+            double arg = k * (-d[j] + (x[j] * x[j] + y[j] * y[j]) / (2.0 * r0)
+                              - (x[j] * X + y[j] * Y) / r0);
+            if (incident == ORACLE_INCIDENT_PLANE) arg += k * d[j];
+            double s, c;
+            sincos(arg, &s, &c);
+            const double ur = u[2 * j], ui = u[2 * j + 1];
+            sr += ur * c - ui * s;
+            si += ur * s + ui * c;
+        }
+        /* exp(i k (z0 + (X^2 + Y^2) / (2 z0))) * S */
+        double s2, c2;
+        sincos(k * (z0 + (X * X + Y * Y) / (2.0 * z0)), &s2, &c2);
+        const double tr = c2 * sr - s2 * si;
+        const double ti = c2 * si + s2 * sr;
+        /* 1 / (i lambda z0) = -i / (lambda z0) */
+        const double a = 1.0 / (lambda * z0);
+        out[2 * e] = a * ti;
+        out[2 * e + 1] = -a * tr;
+    }
+    return 0;
+}

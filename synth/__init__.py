@@ -1,0 +1,173 @@
+"""Seeded synthetic source surfaces for the arbitrary-shape-surface Fresnel sum.
+
+This module only draws inputs: sample positions (x1, y1), the surface
+displacement d1(x1, y1) and the complex source field u1, plus the optical
+parameters they come with.  It holds none of the diffraction arithmetic, so
+both the CPU oracle's tests and the GPU path's tests and benchmark can use it
+without sharing any of the method's code.
+
+Conventions (shared by every generator here):
+  * a source grid has ``nx`` columns and ``ny`` rows; arrays are flattened in
+    row-major (iy, ix) order with ix fastest;
+  * nominal positions are symmetric about the optical axis,
+    ``x = pitch * (ix - (nx - 1) / 2)`` (and likewise for y), plus a uniform
+    jitter drawn per point and per axis;
+  * the random draws happen in a fixed order -- jitter_x, jitter_y, amplitude
+    (or mask), phase -- each of shape (ny, nx), from
+    ``numpy.random.default_rng(seed)`` (PCG64);
+  * d1 is evaluated at the jittered position;
+  * u1 is cast to complex64 once; every consumer uses that same array.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "Workload",
+    "jittered_grid",
+    "sinusoidal_relief",
+    "spherical_cap",
+    "random_field",
+    "config",
+    "CONFIG_NAMES",
+    "sample_pixels",
+]
+
+
+@dataclass
+class Workload:
+    """One synthetic problem: source samples, optics and destination grid."""
+
+    name: str
+    x: np.ndarray          # float64 [n]  source x1 (m)
+    y: np.ndarray          # float64 [n]  source y1 (m)
+    d: np.ndarray          # float64 [n]  surface displacement d1(x1) (m)
+    u: np.ndarray          # complex64 [n] source field u1
+    lam: float             # wavelength (m)
+    z0: float              # source-to-destination distance (m)
+    p2x: float             # destination pitch along x (m)
+    p2y: float             # destination pitch along y (m)
+    mx: int                # destination columns
+    my: int                # destination rows
+    tol: float = 1e-5      # requested accuracy (relative L2)
+    incident: str = "plane"  # "plane": u_I = exp(i k d1); "none": u_I = 1
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+
+def jittered_grid(rng: np.random.Generator, nx: int, ny: int, pitch: float,
+                  jitter: float, pitch_y: float | None = None):
+    """Positions of an nx-by-ny grid with uniform jitter in [-jitter, jitter).
+
+    Draws jitter_x then jitter_y, each of shape (ny, nx).  Returns flattened
+    float64 arrays (x, y) in row-major order.
+    """
+    py = pitch if pitch_y is None else pitch_y
+    jx = rng.uniform(-jitter, jitter, size=(ny, nx)) if jitter > 0 else np.zeros((ny, nx))
+    jy = rng.uniform(-jitter, jitter, size=(ny, nx)) if jitter > 0 else np.zeros((ny, nx))
+    ix = np.arange(nx, dtype=np.float64)
+    iy = np.arange(ny, dtype=np.float64)
+    x = pitch * (ix[None, :] - (nx - 1) / 2.0) + jx
+    y = py * (iy[:, None] - (ny - 1) / 2.0) + jy
+    return x.reshape(-1).astype(np.float64), y.reshape(-1).astype(np.float64)
+
+
+def sinusoidal_relief(x: np.ndarray, y: np.ndarray, amplitude: float, period: float) -> np.ndarray:
+    """d1 = A sin(2 pi x / period) cos(2 pi y / period)."""
+    return amplitude * np.sin(2.0 * np.pi * x / period) * np.cos(2.0 * np.pi * y / period)
+
+
+def spherical_cap(x: np.ndarray, y: np.ndarray, radius: float) -> np.ndarray:
+    """d1 = R - sqrt(R^2 - x^2 - y^2): sag of a sphere of radius R (R > |x|)."""
+    return radius - np.sqrt(radius * radius - x * x - y * y)
+
+
+def random_field(rng: np.random.Generator, nx: int, ny: int, amplitude: str = "uniform") -> np.ndarray:
+    """Complex64 source field: amplitude then phase U[0, 2 pi), each (ny, nx).
+
+    amplitude = "uniform" draws U[0, 1); "binary" draws a Bernoulli(0.5) mask in {0, 1}.
+    """
+    if amplitude == "uniform":
+        amp = rng.uniform(0.0, 1.0, size=(ny, nx))
+    elif amplitude == "binary":
+        amp = (rng.uniform(0.0, 1.0, size=(ny, nx)) < 0.5).astype(np.float64)
+    else:
+        raise ValueError(f"unknown amplitude kind {amplitude!r}")
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=(ny, nx))
+    u = amp * np.exp(1j * phase)
+    return u.reshape(-1).astype(np.complex64)
+
+
+# ---------------------------------------------------------------------------
+# The three benchmark surfaces.  Each takes a ``side`` override so tests can run
+# the same geometry family at a size the CPU oracle finishes quickly; the
+# destination grid follows the source side unless given.
+# ---------------------------------------------------------------------------
+
+def _sinusoid_128(seed: int = 0, side: int = 128, out: int | None = None) -> Workload:
+    """128^2 sinusoidal relief: 8 um pitch, +-2.4 um jitter, A = 50 um, period 1 mm,
+    uniform amplitude and phase, lambda = 532 nm, z0 = 0.1 m, 8 um destination pitch."""
+    rng = np.random.default_rng(seed)
+    p = 8e-6
+    x, y = jittered_grid(rng, side, side, p, 2.4e-6)
+    d = sinusoidal_relief(x, y, 50e-6, 1e-3)
+    u = random_field(rng, side, side, "uniform")
+    m = side if out is None else out
+    return Workload("sinusoid_128", x, y, d, u, 532e-9, 0.1, p, p, m, m, 1e-5, "plane",
+                    {"side": side, "seed": seed})
+
+
+def _cap_2048(seed: int = 0, side: int = 2048, out: int | None = None) -> Workload:
+    """2048^2 spherical cap R = 50 mm: 8 um pitch, +-0.3 pitch jitter, binary amplitude
+    mask with uniform phase, lambda = 532 nm, z0 = 0.2 m, 8 um destination pitch."""
+    rng = np.random.default_rng(seed)
+    p = 8e-6
+    x, y = jittered_grid(rng, side, side, p, 0.3 * p)
+    d = spherical_cap(x, y, 50e-3)
+    u = random_field(rng, side, side, "binary")
+    m = side if out is None else out
+    return Workload("cap_2048", x, y, d, u, 532e-9, 0.2, p, p, m, m, 1e-5, "plane",
+                    {"side": side, "seed": seed})
+
+
+def _sinusoid_4096(seed: int = 0, side: int = 4096, out: int | None = None) -> Workload:
+    """4096^2 sinusoidal relief: 4 um pitch, +-0.3 pitch jitter, A = 30 um, period 0.5 mm,
+    uniform amplitude and phase, lambda = 633 nm, z0 = 0.3 m, 4 um destination pitch."""
+    rng = np.random.default_rng(seed)
+    p = 4e-6
+    x, y = jittered_grid(rng, side, side, p, 0.3 * p)
+    d = sinusoidal_relief(x, y, 30e-6, 0.5e-3)
+    u = random_field(rng, side, side, "uniform")
+    m = side if out is None else out
+    return Workload("sinusoid_4096", x, y, d, u, 633e-9, 0.3, p, p, m, m, 1e-5, "plane",
+                    {"side": side, "seed": seed})
+
+
+_CONFIGS = {
+    "sinusoid_128": _sinusoid_128,
+    "cap_2048": _cap_2048,
+    "sinusoid_4096": _sinusoid_4096,
+}
+CONFIG_NAMES = tuple(_CONFIGS)
+
+
+def config(name: str, seed: int = 0, side: int | None = None, out: int | None = None) -> Workload:
+    """Build a named benchmark surface (optionally at a reduced side length)."""
+    fn = _CONFIGS[name]
+    kw = {"seed": seed, "out": out}
+    if side is not None:
+        kw["side"] = side
+    return fn(**kw)
+
+
+def sample_pixels(mx: int, my: int, count: int, seed: int = 1):
+    """Distinct random destination pixels (ix, iy) as int32 arrays, sorted by flat index."""
+    rng = np.random.default_rng(seed)
+    flat = rng.choice(mx * my, size=min(count, mx * my), replace=False)
+    flat.sort()
+    return (flat % mx).astype(np.int32), (flat // mx).astype(np.int32)

@@ -1,0 +1,221 @@
+"""Pins of the CPU oracle against results the mathematics fixes on its own.
+
+Each pin reduces Eq. (7) (Sec. 2) to a case whose answer does not come from
+re-typing the oracle's formula, and returns (error, bound):
+
+* ``centred_dft_*``: a uniform source grid at constant height with the matching
+  destination pitch p2 = lambda r0 / (N p1) turns the sum into a centred DFT
+  (numpy.fft) -- pins the cross term's sign, its 1/r0 scaling, the pixel
+  centring and the axis assignment;
+* ``gaussian_*``: a sampled Gaussian source turns the sum (times the cell area)
+  into a Riemann sum of the Fresnel integral, whose value is the textbook
+  paraxial Gaussian beam (waist, radius of curvature, Gouy phase) -- pins the
+  prefactor, the output chirp, the source chirp with r0 = z0 - d1 and the
+  -k d1 term; a tilt must land the beam at +alpha r0 (Fresnel shift theorem),
+  anisotropic waists on non-square grids pin x against y;
+* ``two_heights``: two patches at different heights superpose their closed
+  forms, each with its own r0 -- pins the per-point r0;
+* ``separable``: column-only x jitter and row-only y jitter make the sum a
+  product of two dense matrices;
+* ``plane_identity``: u_I = exp(i k d1) equals folding exp(i k d1) into u1;
+* ``single_point``: |u2| = |u1| / (lambda z0) everywhere.
+
+Every function takes an optional ``lib`` (an oracle variant) so that
+``test_planted_mistakes`` can show each planted error fails some pin.
+"""
+import numpy as np
+
+import oracle
+import synth
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# ---------------------------------------------------------------------------
+# Textbook paraxial Gaussian beam, exp(+i k r) convention, written per axis so
+# anisotropic waists factor: a 2D beam is exp(i k z) times the product of two
+# 1D factors sqrt(w0/w) exp(-X^2/w^2) exp(i k X^2 / (2 R)) exp(-i zeta / 2),
+# with w = w0 sqrt(1 + (z/zR)^2), 1/R = z / (z^2 + zR^2), zeta = atan(z/zR),
+# zR = pi w0^2 / lambda.
+# ---------------------------------------------------------------------------
+
+def beam_1d(X, w0, lam, z):
+    zr = np.pi * w0 * w0 / lam
+    w = w0 * np.sqrt(1.0 + (z / zr) ** 2)
+    inv_r = z / (z * z + zr * zr)
+    zeta = np.arctan(z / zr)
+    k = 2.0 * np.pi / lam
+    return np.sqrt(w0 / w) * np.exp(-X * X / (w * w)) * np.exp(1j * (k * X * X * inv_r / 2.0 - zeta / 2.0))
+
+
+def beam_2d(X, Y, w0x, w0y, lam, z, tilt=(0.0, 0.0)):
+    """Propagation over z of exp(-x^2/w0x^2 - y^2/w0y^2) exp(i k (ax x + ay y)).
+
+    A linear phase tilt shifts the beam to X - ax z and multiplies it by
+    exp(i k (ax X - ax^2 z / 2)), per axis (Fresnel shift theorem).
+    """
+    k = 2.0 * np.pi / lam
+    ax, ay = tilt
+    tx = np.exp(1j * k * (ax * X - ax * ax * z / 2.0))
+    ty = np.exp(1j * k * (ay * Y - ay * ay * z / 2.0))
+    return (np.exp(1j * k * z) * beam_1d(X - ax * z, w0x, lam, z) * tx
+            * beam_1d(Y - ay * z, w0y, lam, z) * ty)
+
+
+def flat_surface_factor(X, Y, z0, r0, lam):
+    """F with (Eq. 7 sum for a flat source at height c, u_I = 1) * area = F * U(r0).
+
+    For a flat source at height c (r0 = z0 - c) the Fourier-form sum is the
+    Fresnel propagation U over r0 times r0 / z0 (amplitude 1/(lambda z0), not
+    1/(lambda r0)) and times exp(i k |X|^2 (1/(2 z0) - 1/(2 r0))) (the output
+    chirp of Eq. (6) instead of the exact one); exp(i k z0) exp(-i k c) is
+    exp(i k r0).
+    """
+    k = 2.0 * np.pi / lam
+    return (r0 / z0) * np.exp(1j * k * (X * X + Y * Y) * (1.0 / (2.0 * z0) - 1.0 / (2.0 * r0)))
+
+
+def grid_axis(n, p, centre=0.0):
+    return centre + p * (np.arange(n) - n / 2.0)
+
+
+def gaussian_source(nx, ny, p1x, p1y, w0x, w0y, centre=(0.0, 0.0), tilt=(0.0, 0.0), lam=532e-9):
+    k = 2.0 * np.pi / lam
+    X, Y = np.meshgrid(grid_axis(nx, p1x, centre[0]), grid_axis(ny, p1y, centre[1]))
+    u = np.exp(-((X - centre[0]) / w0x) ** 2 - ((Y - centre[1]) / w0y) ** 2)
+    u = u * np.exp(1j * k * (tilt[0] * X + tilt[1] * Y))
+    return X.reshape(-1), Y.reshape(-1), u.reshape(-1)
+
+
+def dest_xy(mx, my, p2x, p2y):
+    ix, iy = np.meshgrid(np.arange(mx), np.arange(my))
+    return p2x * (ix.reshape(-1) - mx // 2), p2y * (iy.reshape(-1) - my // 2)
+
+
+# ---------------------------------------------------------------------------
+# pins
+# ---------------------------------------------------------------------------
+
+def centred_dft(c, incident, lib=None):
+    lam, z0 = 532e-9, 0.1
+    nx, ny, p1x, p1y = 16, 12, 8e-6, 6e-6
+    r0 = z0 - c
+    p2x, p2y = lam * r0 / (nx * p1x), lam * r0 / (ny * p1y)
+    X1, Y1 = np.meshgrid(p1x * (np.arange(nx) - nx // 2), p1y * (np.arange(ny) - ny // 2))
+    rng = np.random.default_rng(3)
+    u = (rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))).astype(np.complex64)
+    got = oracle.direct_grid(X1.reshape(-1), Y1.reshape(-1), np.full(nx * ny, c), u.reshape(-1),
+                             lam, z0, p2x, p2y, nx, ny, incident=incident, lib=lib)
+    k = 2 * np.pi / lam
+    g = u.astype(np.complex128) * np.exp(1j * k * (-c + (X1 ** 2 + Y1 ** 2) / (2 * r0)))
+    if incident == "plane":
+        g = g * np.exp(1j * k * c)
+    S = np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(g)))
+    X, Y = dest_xy(nx, ny, p2x, p2y)
+    post = np.exp(1j * k * (z0 + (X ** 2 + Y ** 2) / (2 * z0))) / (1j * lam * z0)
+    return rel_l2(got, (post * S.reshape(-1)).reshape(ny, nx)), 1e-11
+
+
+def gaussian_on_axis(lib=None):
+    lam, z0, p1, w0, n = 532e-9, 0.1, 8e-6, 100e-6, 128
+    x, y, u = gaussian_source(n, n, p1, p1, w0, w0, lam=lam)
+    got = oracle.direct_grid(x, y, np.zeros_like(x), u, lam, z0, p1, p1, n, n,
+                             incident="none", lib=lib) * p1 * p1
+    X, Y = dest_xy(n, n, p1, p1)
+    # k z0 ~ 1.2e6 rad is formed in FP64 on both sides: ~2e-10 rad of rounding
+    return rel_l2(got, beam_2d(X, Y, w0, w0, lam, z0).reshape(n, n)), 1e-9
+
+
+def gaussian_tilted_anisotropic(c, lib=None):
+    lam, z0 = 532e-9, 0.1
+    r0 = z0 - c
+    tilt = (5e-4, -8e-4)
+    x, y, u = gaussian_source(128, 160, 8e-6, 6.4e-6, 80e-6, 100e-6, tilt=tilt, lam=lam)
+    mx, my, p2x, p2y = 100, 80, 10e-6, 12e-6
+    got = oracle.direct_grid(x, y, np.full_like(x, c), u, lam, z0, p2x, p2y, mx, my,
+                             incident="none", lib=lib) * 8e-6 * 6.4e-6
+    X, Y = dest_xy(mx, my, p2x, p2y)
+    want = flat_surface_factor(X, Y, z0, r0, lam) * beam_2d(X, Y, 80e-6, 100e-6, lam, r0, tilt)
+    return rel_l2(got, want.reshape(my, mx)), 1e-9
+
+
+def two_heights(lib=None):
+    lam, z0, p1 = 633e-9, 0.25, 8e-6
+    parts = [((-200e-6, 40e-6), 15e-6, 70e-6), ((180e-6, -60e-6), -40e-6, 90e-6)]
+    xs, ys, ds, us = [], [], [], []
+    for centre, c, w0 in parts:
+        x, y, u = gaussian_source(112, 112, p1, p1, w0, w0, centre=centre, lam=lam)
+        xs.append(x); ys.append(y); us.append(u); ds.append(np.full_like(x, c))
+    x, y, d, u = map(np.concatenate, (xs, ys, ds, us))
+    mx = my = 96
+    p2 = 12e-6
+    got = oracle.direct_grid(x, y, d, u, lam, z0, p2, p2, mx, my, incident="none", lib=lib) * p1 * p1
+    X, Y = dest_xy(mx, my, p2, p2)
+    want = np.zeros_like(X, dtype=np.complex128)
+    for centre, c, w0 in parts:
+        r0 = z0 - c
+        # propagation is shift-invariant: a source centred at s gives U(X - s)
+        want += flat_surface_factor(X, Y, z0, r0, lam) * beam_2d(
+            X - centre[0], Y - centre[1], w0, w0, lam, r0)
+    return rel_l2(got, want.reshape(my, mx)), 1e-9
+
+
+def separable(lib=None):
+    lam, z0 = 532e-9, 0.1
+    nx, ny, mx, my = 20, 14, 18, 10
+    rng = np.random.default_rng(11)
+    xs = 8e-6 * (np.arange(nx) - (nx - 1) / 2) + rng.uniform(-2e-6, 2e-6, nx)
+    ys = 7e-6 * (np.arange(ny) - (ny - 1) / 2) + rng.uniform(-2e-6, 2e-6, ny)
+    X1, Y1 = np.meshgrid(xs, ys)
+    u = synth.random_field(rng, nx, ny).reshape(ny, nx)
+    p2x, p2y = 9e-6, 11e-6
+    got = oracle.direct_grid(X1.reshape(-1), Y1.reshape(-1), np.zeros(nx * ny), u.reshape(-1),
+                             lam, z0, p2x, p2y, mx, my, incident="none", lib=lib)
+    k = 2 * np.pi / lam
+    Xd = p2x * (np.arange(mx) - mx // 2)
+    Yd = p2y * (np.arange(my) - my // 2)
+    G = u.astype(np.complex128) * np.exp(1j * k * (X1 ** 2 + Y1 ** 2) / (2 * z0))
+    Ax = np.exp(-1j * k * np.outer(Xd, xs) / z0)   # (mx, nx)
+    Ay = np.exp(-1j * k * np.outer(Yd, ys) / z0)   # (my, ny)
+    post = np.exp(1j * k * (z0 + (Xd[None, :] ** 2 + Yd[:, None] ** 2) / (2 * z0))) / (1j * lam * z0)
+    return rel_l2(got, post * (Ay @ G @ Ax.T)), 1e-12
+
+
+def plane_identity(lib=None):
+    w = synth.config("sinusoid_128", side=24, out=16)
+    k = 2 * np.pi / w.lam
+    ix, iy = synth.sample_pixels(w.mx, w.my, 40)
+    a = oracle.direct(w.x, w.y, w.d, w.u, w.lam, w.z0, w.p2x, w.p2y, w.mx, w.my, ix, iy,
+                      "plane", lib=lib)
+    folded = w.u.astype(np.complex128) * np.exp(1j * k * w.d)
+    b = oracle.direct(w.x, w.y, w.d, folded, w.lam, w.z0, w.p2x, w.p2y, w.mx, w.my, ix, iy,
+                      "none", lib=lib)
+    # phases up to k (d + |x|^2 / 2 r0) ~ 1e3 rad, formed in two different ways
+    return rel_l2(b, a), 1e-12
+
+
+def single_point(lib=None):
+    lam, z0 = 532e-9, 0.2
+    x, y, d = np.array([37e-6]), np.array([-12e-6]), np.array([4e-6])
+    u = np.array([0.6 - 0.3j], dtype=np.complex64)
+    got = oracle.direct_grid(x, y, d, u, lam, z0, 8e-6, 8e-6, 16, 16, lib=lib)
+    want = abs(complex(u[0])) / (lam * z0)
+    return float(np.max(np.abs(np.abs(got) - want)) / want), 1e-12
+
+
+PINS = {
+    "centred_dft_flat_none": lambda lib=None: centred_dft(0.0, "none", lib),
+    "centred_dft_raised_none": lambda lib=None: centred_dft(20e-6, "none", lib),
+    "centred_dft_raised_plane": lambda lib=None: centred_dft(20e-6, "plane", lib),
+    "gaussian_on_axis": gaussian_on_axis,
+    "gaussian_tilted_raised": lambda lib=None: gaussian_tilted_anisotropic(20e-6, lib),
+    "gaussian_tilted_lowered": lambda lib=None: gaussian_tilted_anisotropic(-35e-6, lib),
+    "two_heights": two_heights,
+    "separable": separable,
+    "plane_identity": plane_identity,
+    "single_point": single_point,
+}
