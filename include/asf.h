@@ -1,0 +1,177 @@
+/*
+ * asf.h -- C ABI of the MI355X (gfx950) arbitrary-shape-surface Fresnel library.
+ *
+ * The library evaluates the Fourier-form Fresnel diffraction from a curved
+ * source surface onto a uniform planar destination grid (Shimobaba, Masuda and
+ * Ito, "Arbitrary shape surface Fresnel diffraction", Sec. 2, Eq. (7)-(9)):
+ *
+ *   u2(X, Y) = exp(i k (z0 + (X^2 + Y^2) / (2 z0))) / (i lambda z0)
+ *            * sum_j u1_j u_I,j exp(i k [ -d_j + |x_j|^2 / (2 r0_j) - x_j . X / r0_j ])
+ *
+ * with k = 2 pi / lambda, r0_j = z0 - d_j, u_I,j = exp(i k d_j) (normal plane
+ * wave, the default) or 1, and the destination pixel (ix, iy) at
+ * X = p2x (ix - mx/2), Y = p2y (iy - my/2).  The sum is a 2D type-1
+ * (non-uniform to uniform) Fourier transform of Eq. (9) with per-point
+ * frequencies x_j / (lambda r0_j) (Eq. (8)); the library computes it as a
+ * non-uniform FFT: an exponential-of-semicircle spreading onto a 2x oversampled
+ * grid, a uniform FFT and a deconvolution (the "interpolation + uniform FFT"
+ * scheme the paper relies on, Sec. 2).  The integral is a plain sum with unit
+ * weights: fold any area element into u1.
+ *
+ * Memory: every array argument is a DEVICE pointer (hipMalloc'd or a torch
+ * CUDA/HIP tensor's data pointer) unless stated otherwise.  The caller owns all
+ * memory, including the workspace; the plan keeps pointers into the workspace
+ * and never allocates device memory itself.  Streams are hipStream_t values
+ * passed as void* (NULL = the default stream); all GPU work of a call is
+ * enqueued on that stream.
+ *
+ * Errors: functions return ASF_OK (0) or a negative ASF_E* code; the message of
+ * the calling thread's last failure is available from asf_last_error().
+ * A plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef ASF_H
+#define ASF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------------- */
+#define ASF_OK 0
+#define ASF_EINVAL (-1)   /* null pointer, bad size, non-finite or non-positive parameter */
+#define ASF_EDOMAIN (-2)  /* some r0 = z0 - d1 <= 0, or non-finite x1, y1, d1 (found on the GPU) */
+#define ASF_ENOMEM (-3)   /* workspace smaller than asf_workspace_bytes() */
+#define ASF_EHIP (-4)     /* a HIP runtime call failed */
+#define ASF_ESIZE (-5)    /* unsupported destination grid size */
+#define ASF_ENOSYS (-6)   /* operation not implemented */
+
+/* ---- flags ----------------------------------------------------------------- */
+#define ASF_FFT_FP32 0u             /* FFT stages: FP32 products on MFMA, FP32 accumulation */
+#define ASF_FFT_SPLIT_FP16 1u       /* FFT stages: FP16 hi+lo split products on MFMA, FP32 accumulation */
+#define ASF_FFT_MASK 1u
+#define ASF_INCIDENT_NONE 2u        /* u_I = 1 instead of the plane wave exp(i k d1) */
+
+typedef struct asf_plan_s *asf_plan_t;
+
+/*
+ * Optical and grid parameters.
+ *   lambda    wavelength (m), > 0
+ *   z0        source-to-destination distance (m), > 0 (Eq. (2)-(3))
+ *   p2x, p2y  destination pitch (m), > 0
+ *   mx, my    destination grid columns and rows: each a power of two in [16, 8192]
+ *             (the 2x oversampled FFT length 2m must be 16^a * {1,2,4,8})
+ *   tol       requested relative L2 accuracy in [1e-7, 1e-1]; sets the spreading
+ *             width w = ceil(log10(1/tol)) + 2 (7 at 1e-5), capped to [2, 16]
+ *   flags     ASF_FFT_* | ASF_INCIDENT_NONE
+ */
+typedef struct {
+    double lambda, z0, p2x, p2y;
+    int32_t mx, my;
+    double tol;
+    uint32_t flags;
+} asf_params;
+
+/* Read-only description of a plan (sizes the kernels run at). */
+typedef struct {
+    int64_t n_src;        /* source points */
+    int32_t mx, my;       /* destination grid */
+    int32_t nfx, nfy;     /* oversampled (fine) grid, 2 mx by 2 my */
+    int32_t w;            /* spreading width in fine cells */
+    double beta;          /* exponential-of-semicircle shape, 2.30 w */
+    int32_t tile;         /* spreading tile edge in fine cells */
+    int32_t ntiles;       /* tiles in the fine grid */
+    int64_t slot_cap;     /* capacity of the binned point list (4 n_src) */
+    int32_t col_batch;    /* columns per workgroup in the first FFT pass */
+    uint32_t flags;
+    /* byte offsets into the workspace of buffers tests may inspect */
+    size_t off_status, off_tile_start, off_cell, off_frac, off_phase, off_perm, off_fine, off_mid;
+    size_t ws_bytes;
+} asf_info;
+
+/*
+ * Bytes of device workspace a plan for n_src points with parameters *p needs.
+ * Pure host computation.  Returns 0 if the arguments are invalid (see
+ * asf_last_error()).
+ */
+size_t asf_workspace_bytes(int64_t n_src, const asf_params *p);
+
+/*
+ * Create a plan and bin the geometry (Sec. 2: the pre-phase of Eq. (8) and the
+ * per-point frequencies of Eq. (9)).
+ *   out        receives the plan handle (host pointer to a handle)
+ *   n_src      number of source points, >= 1
+ *   x1, y1, d1 FP64 [n_src] device arrays: sample positions and surface
+ *              displacement d1(x1) (m); read during the call only
+ *   p          host pointer to parameters (copied)
+ *   workspace  device buffer of ws_bytes >= asf_workspace_bytes(n_src, p),
+ *              256-byte aligned, owned by the caller, kept alive until asf_destroy
+ *   stream     hipStream_t as void*
+ * Builds the FP64 host tables, uploads them, runs the geometry kernels and
+ * synchronises the stream once to read the device status word.
+ * Returns ASF_OK, ASF_EINVAL, ASF_ESIZE, ASF_ENOMEM, ASF_EHIP, or ASF_EDOMAIN
+ * when some r0 <= 0 or a coordinate is non-finite (then *out is NULL).
+ */
+int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
+             const double *d1, const asf_params *p, void *workspace, size_t ws_bytes,
+             void *stream);
+
+/*
+ * Re-bin a new geometry of the same n_src into an existing plan, asynchronously
+ * (same kernels as asf_plan; no synchronisation, no host tables rebuilt).
+ * Domain errors are latched in the device status word: read them with
+ * asf_status().  Returns ASF_OK, ASF_EINVAL or ASF_EHIP.
+ */
+int asf_setpts(asf_plan_t plan, const double *x1, const double *y1, const double *d1,
+               void *stream);
+
+/*
+ * Synchronise `stream` and read the plan's status word.  Returns ASF_OK, or
+ * ASF_EDOMAIN if the last geometry had some r0 <= 0 or a non-finite coordinate
+ * (those points were left out), or ASF_EHIP.
+ */
+int asf_status(asf_plan_t plan, void *stream);
+
+/*
+ * Forward transform, Eq. (8): u2 = A u1.
+ *   u1  complex64 [n_src] device array (interleaved re, im), aligned with x1, y1, d1
+ *   u2  complex64 [my][mx] device array, row-major; pixel (ix, iy) at
+ *       X = p2x (ix - mx/2), Y = p2y (iy - my/2)
+ * Asynchronous on `stream`; never synchronises.  NaN in u1 propagates.
+ * Returns ASF_OK, ASF_EINVAL or ASF_EHIP.
+ */
+int asf_forward(asf_plan_t plan, const void *u1, void *u2, void *stream);
+
+/*
+ * Adjoint transform g1 = A^H g2 (type-2 interpolation), for gradients.
+ *   g2  complex64 [my][mx] device array; g1 complex64 [n_src] device array.
+ * Not implemented yet: returns ASF_ENOSYS.
+ */
+int asf_adjoint(asf_plan_t plan, const void *g2, void *g1, void *stream);
+
+/* Fill *info (host pointer) with the plan's sizes.  Returns ASF_OK or ASF_EINVAL. */
+int asf_plan_info(asf_plan_t plan, asf_info *info);
+
+/*
+ * Per-stage timing with HIP events recorded on the forward's stream.
+ * asf_set_timing(plan, 1) makes later asf_setpts/asf_forward calls record an
+ * event pair around each stage; asf_stage_times synchronises on the last pair
+ * and writes up to n durations (ms, host array) in the order
+ * [count, scan, scatter, spread, fft_pass1, fft_pass2], returning how many it
+ * wrote (negative on error).  Timing adds a few microseconds per stage.
+ */
+int asf_set_timing(asf_plan_t plan, int enable);
+int asf_stage_times(asf_plan_t plan, double *ms, int n);
+
+/* Release the plan (host memory and events; the workspace stays the caller's). */
+int asf_destroy(asf_plan_t plan);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char *asf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ASF_H */

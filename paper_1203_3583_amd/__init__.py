@@ -1,0 +1,10 @@
+"""MI355X (gfx950) arbitrary-shape-surface Fresnel diffraction.
+
+The forward transform of Shimobaba, Masuda and Ito, "Arbitrary shape surface
+Fresnel diffraction" (Sec. 2, Eq. (7)-(9)) as a 2D type-1 non-uniform FFT in
+hand-written HIP kernels behind the C ABI of include/asf.h.  ``asf.Plan`` is the
+Python handle; ``csrc/build.py`` builds ``libasf.so``.
+"""
+from .asf import AsfError, Plan, STAGES, lib, last_error, make_params, workspace_bytes  # noqa: F401
+
+__all__ = ["AsfError", "Plan", "STAGES", "lib", "last_error", "make_params", "workspace_bytes"]

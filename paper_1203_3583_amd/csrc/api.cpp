@@ -1,0 +1,543 @@
+// Host side of the library: parameter checks, workspace layout, FP64 tables and
+// the extern "C" entry points declared in include/asf.h.
+//
+// Tables built here in FP64 and rounded once to complex64:
+//   Dx[ix] = exp(i k z0) / (i lambda z0) * exp(i k X^2 / (2 z0)) / psi_hat_x(m),
+//   Dy[iy] = exp(i k Y^2 / (2 z0)) / psi_hat_y(n),
+// with X = p2x m, m = ix - mx/2 (Eq. (7)/(8): the post-phase of the destination,
+// whose chirp uses z0 by the approximation of Eq. (6)), and psi_hat the Fourier
+// transform of the spreading kernel at mode m on the fine grid, by
+// Gauss-Legendre quadrature; twiddles exp(-2 pi i e / L) of both FFT lengths and
+// the 16-point DFT roots.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "asf.h"
+#include "asf_internal.h"
+
+using asf::FftShape;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(ASF_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr size_t kAlign = 256;
+constexpr int kTileMax = 64;
+constexpr int kQuadNodes = 200;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int log2i(int v) {
+    int s = 0;
+    while ((1 << s) < v) ++s;
+    return s;
+}
+
+struct Layout {
+    int64_t n;
+    int mx, my, nfx, nfy, w, tile, ntx, nty, ntiles;
+    double beta;
+    int64_t slot_cap;
+    size_t off_status, off_tile_start, off_cursor, off_cell, off_frac, off_phase, off_perm;
+    size_t off_fine, off_mid, off_dx, off_dy, off_twx, off_twy, off_w16, total;
+};
+
+int check_params(int64_t n, const asf_params *p) {
+    if (!p) return fail(ASF_EINVAL, "params is NULL");
+    if (n < 1 || n > (int64_t(1) << 30)) return fail(ASF_EINVAL, "n_src must be in [1, 2^30], got %lld", (long long)n);
+    const double v[4] = {p->lambda, p->z0, p->p2x, p->p2y};
+    const char *names[4] = {"lambda", "z0", "p2x", "p2y"};
+    for (int i = 0; i < 4; ++i)
+        if (!std::isfinite(v[i]) || !(v[i] > 0.0)) return fail(ASF_EINVAL, "%s must be finite and > 0", names[i]);
+    if (!std::isfinite(p->tol) || p->tol < 1e-7 || p->tol > 1e-1) return fail(ASF_EINVAL, "tol must be in [1e-7, 1e-1]");
+    if (p->flags & ~(ASF_FFT_MASK | ASF_INCIDENT_NONE)) return fail(ASF_EINVAL, "unknown flag bits 0x%x", p->flags);
+    if (!is_pow2(p->mx) || !is_pow2(p->my) || p->mx < 16 || p->my < 16 || p->mx > 8192 || p->my > 8192)
+        return fail(ASF_ESIZE, "mx, my must be powers of two in [16, 8192], got %d x %d", p->mx, p->my);
+    return ASF_OK;
+}
+
+int spread_width(double tol) {
+    int w = (int)std::ceil(-std::log10(tol) - 1e-9) + 2;
+    if (w < 2) w = 2;
+    if (w > 16) w = 16;
+    return w;
+}
+
+int make_layout(int64_t n, const asf_params *p, Layout &L) {
+    int rc = check_params(n, p);
+    if (rc) return rc;
+    L.n = n;
+    L.mx = p->mx;
+    L.my = p->my;
+    L.nfx = 2 * p->mx;
+    L.nfy = 2 * p->my;
+    L.w = spread_width(p->tol);
+    L.beta = 2.30 * L.w;
+    L.tile = kTileMax;
+    if (L.nfx < L.tile) L.tile = L.nfx;
+    if (L.nfy < L.tile) L.tile = L.nfy;
+    L.ntx = L.nfx / L.tile;
+    L.nty = L.nfy / L.tile;
+    L.ntiles = L.ntx * L.nty;
+    L.slot_cap = 4 * n;
+    size_t o = 0;
+    auto take = [&o](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.off_status = take(kAlign);
+    L.off_tile_start = take(sizeof(uint32_t) * (L.ntiles + 1));
+    L.off_cursor = take(sizeof(uint32_t) * L.ntiles);
+    L.off_cell = take(sizeof(uint32_t) * L.slot_cap);
+    L.off_frac = take(sizeof(float2) * L.slot_cap);
+    L.off_phase = take(sizeof(float2) * L.slot_cap);
+    L.off_perm = take(sizeof(uint32_t) * L.slot_cap);
+    L.off_fine = take(sizeof(float2) * (size_t)L.nfx * L.nfy);
+    L.off_mid = take(sizeof(float2) * (size_t)L.my * L.nfx);
+    L.off_dx = take(sizeof(float2) * L.mx);
+    L.off_dy = take(sizeof(float2) * L.my);
+    L.off_twx = take(sizeof(float2) * L.nfx);
+    L.off_twy = take(sizeof(float2) * L.nfy);
+    L.off_w16 = take(sizeof(float2) * 16);
+    L.total = o;
+    return ASF_OK;
+}
+
+// Stockham shape of one FFT length with `batch` transforms per workgroup.
+FftShape fft_shape(int len, int batch) {
+    FftShape s;
+    s.L = len;
+    const int e = log2i(len);
+    s.n16 = e / 4;
+    s.r0 = 1 << (e % 4);
+    s.lq = len / 16;
+    s.batch = batch;
+    const int unit = s.lq > 16 ? s.lq : 16;
+    s.stride = len + (len / unit) * 16;
+    const int total = batch * len / 256;   // 16-instance blocks per stage
+    if (total <= 8) {
+        s.waves = total;
+        s.bpw = 1;
+    } else if (total <= 32) {
+        s.waves = 8;
+        s.bpw = total / 8;
+    } else {
+        s.waves = 16;
+        s.bpw = total / 16;
+    }
+    return s;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_n).
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &wq) {
+    x.assign(n, 0.0);
+    wq.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+        double pp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p1 = 1.0, p2 = 0.0;
+            for (int j = 1; j <= n; ++j) {
+                const double p3 = p2;
+                p2 = p1;
+                p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+            }
+            pp = n * (z * p1 - p2) / (z * z - 1.0);
+            const double dz = p1 / pp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        wq[i] = wq[n - 1 - i] = 2.0 / ((1.0 - z * z) * pp * pp);
+    }
+}
+
+// Fourier transform of psi(z) = exp(beta (sqrt(1 - (2z/w)^2) - 1)) at mode m of an nf grid:
+// int psi(z) exp(-2 pi i m z / nf) dz = (w/2) int_{-1}^{1} es(u) cos(pi m w u / nf) du.
+std::vector<double> psi_hat(int nmodes_half, int nf, int w, double beta) {
+    std::vector<double> xq, wq;
+    gauss_legendre(kQuadNodes, xq, wq);
+    std::vector<double> es(kQuadNodes);
+    for (int q = 0; q < kQuadNodes; ++q) es[q] = std::exp(beta * (std::sqrt(1.0 - xq[q] * xq[q]) - 1.0));
+    std::vector<double> out(nmodes_half + 1);
+    for (int m = 0; m <= nmodes_half; ++m) {
+        double s = 0.0;
+        for (int q = 0; q < kQuadNodes; ++q) s += wq[q] * es[q] * std::cos(kPi * m * w * xq[q] / nf);
+        out[m] = 0.5 * w * s;
+    }
+    return out;
+}
+
+// Reduce a phase argument (rad) to [-pi, pi] in FP64.
+double reduce(double a) { return std::remainder(a, 2.0 * kPi); }
+
+}  // namespace
+
+struct asf_plan_s {
+    Layout lay;
+    asf_params prm;
+    char *ws;
+    asf::Binned bin;
+    asf::GeoParams geo;
+    asf::SpreadParams sp;
+    FftShape sh1, sh2;
+    float2 *fine, *mid, *dx, *dy, *twx, *twy, *w16;
+    int timing;
+    bool events;
+    hipEvent_t ev[2 * asf::NSTAGES];
+    bool recorded[asf::NSTAGES];
+};
+
+namespace {
+
+int ensure_events(asf_plan_s *p) {
+    if (p->events) return ASF_OK;
+    for (int i = 0; i < 2 * asf::NSTAGES; ++i) {
+        hipError_t e = hipEventCreate(&p->ev[i]);
+        if (e != hipSuccess) {
+            for (int j = 0; j < i; ++j) (void)hipEventDestroy(p->ev[j]);
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    p->events = true;
+    return ASF_OK;
+}
+
+struct StageMark {
+    asf_plan_s *p;
+    int stage;
+    hipStream_t s;
+    StageMark(asf_plan_s *p_, int st, hipStream_t s_) : p(p_), stage(st), s(s_) {
+        if (p->timing) (void)hipEventRecord(p->ev[2 * stage], s);
+    }
+    ~StageMark() {
+        if (p->timing) {
+            (void)hipEventRecord(p->ev[2 * stage + 1], s);
+            p->recorded[stage] = true;
+        }
+    }
+};
+
+int run_geometry(asf_plan_s *p, const double *x, const double *y, const double *d, hipStream_t s) {
+    hipError_t e;
+    {
+        StageMark m(p, asf::STAGE_COUNT, s);
+        e = asf::launch_bin_reset(p->bin, p->lay.ntiles, s);
+        if (e != hipSuccess) return hip_fail(e, "bin_reset launch");
+        e = asf::launch_bin_count(p->geo, p->bin, p->lay.n, x, y, d, s);
+        if (e != hipSuccess) return hip_fail(e, "bin_count launch");
+    }
+    {
+        StageMark m(p, asf::STAGE_SCAN, s);
+        e = asf::launch_bin_scan(p->bin, p->lay.ntiles, s);
+        if (e != hipSuccess) return hip_fail(e, "bin_scan launch");
+    }
+    {
+        StageMark m(p, asf::STAGE_SCATTER, s);
+        e = asf::launch_bin_scatter(p->geo, p->bin, p->lay.n, x, y, d, s);
+        if (e != hipSuccess) return hip_fail(e, "bin_scatter launch");
+    }
+    return ASF_OK;
+}
+
+int upload_tables(asf_plan_s *p, hipStream_t s) {
+    const Layout &L = p->lay;
+    const asf_params &q = p->prm;
+    const double k = 2.0 * kPi / q.lambda;
+    std::vector<float2> dx(L.mx), dy(L.my), twx(L.nfx), twy(L.nfy), w16(16);
+    const std::vector<double> phx = psi_hat(L.mx / 2, L.nfx, L.w, L.beta);
+    const std::vector<double> phy = psi_hat(L.my / 2, L.nfy, L.w, L.beta);
+    // exp(i k z0) / (i lambda z0) = -i exp(i k z0) / (lambda z0)
+    const double a0 = reduce(k * q.z0);
+    const double c0r = std::sin(a0) / (q.lambda * q.z0), c0i = -std::cos(a0) / (q.lambda * q.z0);
+    for (int ix = 0; ix < L.mx; ++ix) {
+        const int m = ix - L.mx / 2;
+        const double X = q.p2x * m;
+        const double ch = reduce(k * X * X / (2.0 * q.z0));
+        const double inv = 1.0 / phx[m < 0 ? -m : m];
+        const double er = std::cos(ch) * inv, ei = std::sin(ch) * inv;
+        dx[ix] = make_float2((float)(er * c0r - ei * c0i), (float)(er * c0i + ei * c0r));
+    }
+    for (int iy = 0; iy < L.my; ++iy) {
+        const int n = iy - L.my / 2;
+        const double Y = q.p2y * n;
+        const double ch = reduce(k * Y * Y / (2.0 * q.z0));
+        const double inv = 1.0 / phy[n < 0 ? -n : n];
+        dy[iy] = make_float2((float)(std::cos(ch) * inv), (float)(std::sin(ch) * inv));
+    }
+    for (int e = 0; e < L.nfx; ++e) {
+        const double a = 2.0 * kPi * e / L.nfx;
+        twx[e] = make_float2((float)std::cos(a), (float)-std::sin(a));
+    }
+    for (int e = 0; e < L.nfy; ++e) {
+        const double a = 2.0 * kPi * e / L.nfy;
+        twy[e] = make_float2((float)std::cos(a), (float)-std::sin(a));
+    }
+    for (int e = 0; e < 16; ++e) {
+        const double a = 2.0 * kPi * e / 16.0;
+        w16[e] = make_float2((float)std::cos(a), (float)-std::sin(a));
+    }
+    struct { void *dst; const void *src; size_t n; } copies[] = {
+        {p->dx, dx.data(), dx.size() * sizeof(float2)},
+        {p->dy, dy.data(), dy.size() * sizeof(float2)},
+        {p->twx, twx.data(), twx.size() * sizeof(float2)},
+        {p->twy, twy.data(), twy.size() * sizeof(float2)},
+        {p->w16, w16.data(), w16.size() * sizeof(float2)},
+    };
+    for (auto &c : copies) {
+        hipError_t e = hipMemcpyAsync(c.dst, c.src, c.n, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "table upload");
+    }
+    // the host vectors die here: wait for the copies
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return ASF_OK;
+}
+
+int read_status(asf_plan_s *p, hipStream_t s) {
+    uint32_t st = 0;
+    hipError_t e = hipMemcpyAsync(&st, p->bin.status, sizeof st, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "status read");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (st & 1u) return fail(ASF_EDOMAIN, "some point has r0 = z0 - d1 <= 0 or a non-finite coordinate");
+    if (st & 2u) return fail(ASF_EHIP, "internal error: tile bin overflow");
+    return ASF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *asf_last_error(void) { return g_err.c_str(); }
+
+size_t asf_workspace_bytes(int64_t n_src, const asf_params *p) {
+    Layout L;
+    if (make_layout(n_src, p, L) != ASF_OK) return 0;
+    return L.total;
+}
+
+int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1, const double *d1,
+             const asf_params *p, void *workspace, size_t ws_bytes, void *stream) {
+    if (!out) return fail(ASF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!x1 || !y1 || !d1 || !workspace) return fail(ASF_EINVAL, "x1, y1, d1 and workspace must be non-NULL");
+    Layout L;
+    int rc = make_layout(n_src, p, L);
+    if (rc) return rc;
+    if (ws_bytes < L.total)
+        return fail(ASF_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(ASF_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+
+    asf_plan_s *pl = new (std::nothrow) asf_plan_s();
+    if (!pl) return fail(ASF_EINVAL, "out of host memory");
+    pl->lay = L;
+    pl->prm = *p;
+    pl->ws = static_cast<char *>(workspace);
+    char *w = pl->ws;
+    pl->bin.status = reinterpret_cast<uint32_t *>(w + L.off_status);
+    pl->bin.tile_start = reinterpret_cast<uint32_t *>(w + L.off_tile_start);
+    pl->bin.cursor = reinterpret_cast<uint32_t *>(w + L.off_cursor);
+    pl->bin.cell = reinterpret_cast<uint32_t *>(w + L.off_cell);
+    pl->bin.frac = reinterpret_cast<float2 *>(w + L.off_frac);
+    pl->bin.phase = reinterpret_cast<float2 *>(w + L.off_phase);
+    pl->bin.perm = reinterpret_cast<uint32_t *>(w + L.off_perm);
+    pl->fine = reinterpret_cast<float2 *>(w + L.off_fine);
+    pl->mid = reinterpret_cast<float2 *>(w + L.off_mid);
+    pl->dx = reinterpret_cast<float2 *>(w + L.off_dx);
+    pl->dy = reinterpret_cast<float2 *>(w + L.off_dy);
+    pl->twx = reinterpret_cast<float2 *>(w + L.off_twx);
+    pl->twy = reinterpret_cast<float2 *>(w + L.off_twy);
+    pl->w16 = reinterpret_cast<float2 *>(w + L.off_w16);
+
+    const double k = 2.0 * kPi / p->lambda;
+    pl->geo.k = k;
+    pl->geo.inv_lambda = 1.0 / p->lambda;
+    pl->geo.z0 = p->z0;
+    pl->geo.p2x = p->p2x;
+    pl->geo.p2y = p->p2y;
+    pl->geo.nfx = L.nfx;
+    pl->geo.nfy = L.nfy;
+    pl->geo.w = L.w;
+    pl->geo.tile = L.tile;
+    pl->geo.ntx = L.ntx;
+    pl->geo.nty = L.nty;
+    pl->geo.plane = (p->flags & ASF_INCIDENT_NONE) ? 0 : 1;
+
+    // FFT shapes: pass 1 holds `panel` columns of length nfy per workgroup
+    const int lds_max = asf::fft_max_lds_bytes();
+    const int budget = lds_max < 81920 ? lds_max : 81920;
+    int panel = 1;
+    while (panel * 2 <= 16 && panel * 2 <= L.tile &&
+           fft_shape(L.nfy, panel * 2).stride * (size_t)panel * 2 * sizeof(float2) <= (size_t)budget)
+        panel *= 2;
+    while (panel * L.nfy < 256) panel *= 2;
+    pl->sh1 = fft_shape(L.nfy, panel);
+    if (asf::fft_lds_bytes(pl->sh1) > (size_t)lds_max) {
+        delete pl;
+        return fail(ASF_ESIZE, "column FFT of length %d does not fit in LDS (%d bytes)", L.nfy, lds_max);
+    }
+    int rows = 1;
+    while (rows * L.nfx < 256) rows *= 2;
+    pl->sh2 = fft_shape(L.nfx, rows);
+    if (asf::fft_lds_bytes(pl->sh2) > (size_t)lds_max) {
+        delete pl;
+        return fail(ASF_ESIZE, "row FFT of length %d does not fit in LDS (%d bytes)", L.nfx, lds_max);
+    }
+
+    pl->sp.n = L.n;
+    pl->sp.nfx = L.nfx;
+    pl->sp.nfy = L.nfy;
+    pl->sp.w = L.w;
+    pl->sp.tile = L.tile;
+    pl->sp.ntx = L.ntx;
+    pl->sp.nty = L.nty;
+    pl->sp.panel = panel;
+    pl->sp.beta_log2e = (float)(L.beta * 1.4426950408889634);
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = upload_tables(pl, s);
+    if (!rc) rc = run_geometry(pl, x1, y1, d1, s);
+    if (!rc) rc = read_status(pl, s);
+    if (rc) {
+        if (pl->events)
+            for (int i = 0; i < 2 * asf::NSTAGES; ++i) (void)hipEventDestroy(pl->ev[i]);
+        delete pl;
+        return rc;
+    }
+    *out = pl;
+    return ASF_OK;
+}
+
+int asf_setpts(asf_plan_t plan, const double *x1, const double *y1, const double *d1, void *stream) {
+    if (!plan || !x1 || !y1 || !d1) return fail(ASF_EINVAL, "plan, x1, y1, d1 must be non-NULL");
+    return run_geometry(plan, x1, y1, d1, static_cast<hipStream_t>(stream));
+}
+
+int asf_status(asf_plan_t plan, void *stream) {
+    if (!plan) return fail(ASF_EINVAL, "plan is NULL");
+    return read_status(plan, static_cast<hipStream_t>(stream));
+}
+
+int asf_forward(asf_plan_t plan, const void *u1, void *u2, void *stream) {
+    if (!plan || !u1 || !u2) return fail(ASF_EINVAL, "plan, u1, u2 must be non-NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    asf_plan_s *p = plan;
+    const int split = (p->prm.flags & ASF_FFT_MASK) == ASF_FFT_SPLIT_FP16;
+    hipError_t e;
+    {
+        StageMark m(p, asf::STAGE_SPREAD, s);
+        e = asf::launch_spread(p->sp, p->bin, static_cast<const float2 *>(u1), p->fine, s);
+        if (e != hipSuccess) return hip_fail(e, "spread launch");
+    }
+    {
+        StageMark m(p, asf::STAGE_FFT1, s);
+        e = asf::launch_fft_pass1(p->sh1, split, p->fine, p->mid, p->twy, p->w16, p->lay.nfx, p->lay.my, s);
+        if (e != hipSuccess) return hip_fail(e, "fft pass 1 launch");
+    }
+    {
+        StageMark m(p, asf::STAGE_FFT2, s);
+        e = asf::launch_fft_pass2(p->sh2, split, p->mid, static_cast<float2 *>(u2), p->twx, p->w16,
+                                  p->dx, p->dy, p->lay.mx, p->lay.my, s);
+        if (e != hipSuccess) return hip_fail(e, "fft pass 2 launch");
+    }
+    return ASF_OK;
+}
+
+int asf_adjoint(asf_plan_t plan, const void *g2, void *g1, void *stream) {
+    (void)plan; (void)g2; (void)g1; (void)stream;
+    return fail(ASF_ENOSYS, "asf_adjoint is not implemented");
+}
+
+int asf_plan_info(asf_plan_t plan, asf_info *info) {
+    if (!plan || !info) return fail(ASF_EINVAL, "plan and info must be non-NULL");
+    const Layout &L = plan->lay;
+    std::memset(info, 0, sizeof *info);
+    info->n_src = L.n;
+    info->mx = L.mx;
+    info->my = L.my;
+    info->nfx = L.nfx;
+    info->nfy = L.nfy;
+    info->w = L.w;
+    info->beta = L.beta;
+    info->tile = L.tile;
+    info->ntiles = L.ntiles;
+    info->slot_cap = L.slot_cap;
+    info->col_batch = plan->sh1.batch;
+    info->flags = plan->prm.flags;
+    info->off_status = L.off_status;
+    info->off_tile_start = L.off_tile_start;
+    info->off_cell = L.off_cell;
+    info->off_frac = L.off_frac;
+    info->off_phase = L.off_phase;
+    info->off_perm = L.off_perm;
+    info->off_fine = L.off_fine;
+    info->off_mid = L.off_mid;
+    info->ws_bytes = L.total;
+    return ASF_OK;
+}
+
+int asf_set_timing(asf_plan_t plan, int enable) {
+    if (!plan) return fail(ASF_EINVAL, "plan is NULL");
+    if (enable) {
+        int rc = ensure_events(plan);
+        if (rc) return rc;
+    }
+    plan->timing = enable ? 1 : 0;
+    for (int i = 0; i < asf::NSTAGES; ++i) plan->recorded[i] = false;
+    return ASF_OK;
+}
+
+int asf_stage_times(asf_plan_t plan, double *ms, int n) {
+    if (!plan || !ms || n < 0) return fail(ASF_EINVAL, "plan and ms must be non-NULL");
+    if (!plan->events) return fail(ASF_EINVAL, "timing was never enabled");
+    int k = 0;
+    for (; k < n && k < asf::NSTAGES; ++k) {
+        ms[k] = -1.0;
+        if (!plan->recorded[k]) continue;
+        hipError_t e = hipEventSynchronize(plan->ev[2 * k + 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, plan->ev[2 * k], plan->ev[2 * k + 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        ms[k] = t;
+    }
+    return k;
+}
+
+int asf_destroy(asf_plan_t plan) {
+    if (!plan) return fail(ASF_EINVAL, "plan is NULL");
+    if (plan->events)
+        for (int i = 0; i < 2 * asf::NSTAGES; ++i) (void)hipEventDestroy(plan->ev[i]);
+    delete plan;
+    return ASF_OK;
+}
+
+}  // extern "C"

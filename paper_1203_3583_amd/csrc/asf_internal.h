@@ -1,0 +1,77 @@
+// Internal declarations shared by the host plan code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "asf.h"
+
+namespace asf {
+
+// Binned point list: one slot per (point, fine-grid tile its footprint touches).
+struct Binned {
+    uint32_t *status;      // [1] bit 0: domain error, bit 1: bin overflow
+    uint32_t *tile_start;  // [ntiles + 1] exclusive scan of slot counts per tile
+    uint32_t *cursor;      // [ntiles] counts, then insertion cursors
+    uint32_t *cell;        // [slot_cap] first footprint cell, l0x | l0y << 16
+    float2 *frac;          // [slot_cap] (gx - l0x - (w-1)/2, gy - l0y - (w-1)/2), in (-1/2, 1/2]
+    float2 *phase;         // [slot_cap] exp(i phi_j), the pre-phase of Eq. (8)
+    uint32_t *perm;        // [slot_cap] index j of the point in the caller's order
+};
+
+// Scalars the geometry kernels need (all FP64 where the paper's phases live).
+struct GeoParams {
+    double k;          // 2 pi / lambda
+    double inv_lambda; // 1 / lambda
+    double z0;
+    double p2x, p2y;
+    int nfx, nfy;      // fine grid
+    int w;             // spreading width (cells)
+    int tile;          // tile edge (cells)
+    int ntx, nty;      // tiles per axis
+    int plane;         // 1: u_I = exp(i k d1) (cancels the -k d1 term exactly)
+};
+
+struct SpreadParams {
+    int64_t n;         // source points (bound on the gathered index)
+    int nfx, nfy, w, tile, ntx, nty;
+    int panel;         // fine-grid panel width (columns stored contiguously per row)
+    float beta_log2e;  // ES shape beta times log2(e), for exp2
+};
+
+// One batch of same-length FFTs.  In the first pass (along y) a workgroup
+// transforms `batch` adjacent fine-grid columns; in the second pass (along x)
+// it transforms `batch` rows of the intermediate array.
+struct FftShape {
+    int L;          // transform length (16^a * r0)
+    int r0;         // first radix (1, 2, 4 or 8), done on the vector ALU
+    int n16;        // number of radix-16 stages
+    int lq;         // L / 16
+    int batch;      // transforms per workgroup
+    int stride;     // LDS complex elements per transform (with padding)
+    int waves;      // waves per workgroup
+    int bpw;        // 16-instance MFMA blocks per wave per stage
+};
+
+enum { STAGE_COUNT = 0, STAGE_SCAN, STAGE_SCATTER, STAGE_SPREAD, STAGE_FFT1, STAGE_FFT2, NSTAGES };
+
+// ---- launchers (one per kernel family) ---------------------------------------
+hipError_t launch_bin_reset(const Binned &b, int ntiles, hipStream_t s);
+hipError_t launch_bin_count(const GeoParams &g, const Binned &b, int64_t n, const double *x,
+                            const double *y, const double *d, hipStream_t s);
+hipError_t launch_bin_scan(const Binned &b, int ntiles, hipStream_t s);
+hipError_t launch_bin_scatter(const GeoParams &g, const Binned &b, int64_t n, const double *x,
+                              const double *y, const double *d, hipStream_t s);
+hipError_t launch_spread(const SpreadParams &p, const Binned &b, const float2 *u1, float2 *fine,
+                         hipStream_t s);
+// pass 1: columns of the fine grid (panel layout) -> mid[my][nfx]
+hipError_t launch_fft_pass1(const FftShape &sh, int split16, const float2 *fine, float2 *mid,
+                            const float2 *tw, const float2 *w16, int nfx, int my, hipStream_t s);
+// pass 2: rows of mid -> u2[my][mx] with the deconvolution and destination phase
+hipError_t launch_fft_pass2(const FftShape &sh, int split16, const float2 *mid, float2 *u2,
+                            const float2 *tw, const float2 *w16, const float2 *dx,
+                            const float2 *dy, int mx, int my, hipStream_t s);
+size_t fft_lds_bytes(const FftShape &sh);
+int fft_max_lds_bytes();
+
+}  // namespace asf

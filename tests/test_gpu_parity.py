@@ -1,0 +1,197 @@
+"""GPU parity: the HIP forward path against the FP64 CPU oracle.
+
+Every case runs the whole path (geometry kernels, spreading, both FFT passes
+with the fused deconvolution) through the C ABI and compares u2 with the
+oracle's direct sum element by element.  Bars: relative L2 <= 1e-5 with FP32
+FFT stages and <= 1e-4 with split-FP16 FFT stages, per evaluation set.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import eval_sets, gpu_forward, oracle_at, rel_l2, to_dev, torch_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "split_fp16": 1e-4}
+ORACLE_THREADS = min(16, os.cpu_count() or 1)
+
+
+def _oracle(w, ix, iy):
+    import oracle
+    return oracle.direct(w.x, w.y, w.d, w.u, w.lam, w.z0, w.p2x, w.p2y, w.mx, w.my, ix, iy,
+                         incident=w.incident, nthreads=ORACLE_THREADS)
+
+
+def _full_grid(w):
+    gx, gy = np.meshgrid(np.arange(w.mx), np.arange(w.my))
+    return _oracle(w, gx.reshape(-1), gy.reshape(-1)).reshape(w.my, w.mx)
+
+
+def _custom(nx, ny, pitch, jitter, mx, my, p2x, p2y, lam=532e-9, z0=0.1, amp=20e-6, period=0.8e-3,
+            seed=4, incident="plane", tol=1e-5):
+    rng = np.random.default_rng(seed)
+    x, y = synth.jittered_grid(rng, nx, ny, pitch, jitter)
+    d = synth.sinusoidal_relief(x, y, amp, period)
+    u = synth.random_field(rng, nx, ny)
+    return synth.Workload("custom", x, y, d, u, lam, z0, p2x, p2y, mx, my, tol, incident)
+
+
+@pytest.mark.parametrize("fft", ["fp32", "split_fp16"])
+def test_sinusoid_128_full_grid(fft):
+    w = synth.config("sinusoid_128")
+    got, info = gpu_forward(w, fft)
+    want = _full_grid(w)
+    err = rel_l2(got, want)
+    print(f"sinusoid_128 {fft}: rel-L2 {err:.3e} (w={info['w']}, tiles={info['ntiles']})")
+    assert err <= TOL[fft]
+
+
+@pytest.mark.parametrize("fft", ["fp32", "split_fp16"])
+def test_ragged_nonsquare_no_incident(fft):
+    """N = 37 x 53 (not a multiple of any block size), 64 x 32 output, p2x != p2y, u_I = 1."""
+    w = _custom(37, 53, 8e-6, 2e-6, 64, 32, 9e-6, 7e-6, incident="none")
+    got, _ = gpu_forward(w, fft)
+    err = rel_l2(got, _full_grid(w))
+    print(f"ragged {fft}: {err:.3e}")
+    assert err <= TOL[fft]
+
+
+@pytest.mark.parametrize("fft", ["fp32", "split_fp16"])
+def test_wrapping_frequencies(fft):
+    """Large destination pitch: x / (lambda r0) p2 spans more than one period and wraps."""
+    w = _custom(96, 80, 8e-6, 2.4e-6, 128, 128, 80e-6, 70e-6, z0=0.1)
+    k_t = w.p2x * np.abs(w.x).max() / (w.lam * (w.z0 - w.d.max()))
+    assert k_t > 0.5   # cycles per destination pixel beyond half a period: both signs wrap
+    got, _ = gpu_forward(w, fft)
+    err = rel_l2(got, _full_grid(w))
+    print(f"wrap {fft}: {err:.3e}")
+    assert err <= TOL[fft]
+
+
+@pytest.mark.parametrize("tol,bar", [(1e-3, 1e-3), (1e-6, 1e-5)])
+def test_tolerance_sets_width(tol, bar):
+    w = _custom(64, 64, 8e-6, 2e-6, 64, 64, 8e-6, 8e-6, tol=tol)
+    got, info = gpu_forward(w, "fp32", tol=tol)
+    err = rel_l2(got, _full_grid(w))
+    print(f"tol {tol}: w={info['w']} err {err:.3e}")
+    assert err <= bar
+
+
+def test_single_point():
+    w = _custom(1, 1, 8e-6, 3e-6, 32, 32, 8e-6, 8e-6)
+    got, _ = gpu_forward(w)
+    assert rel_l2(got, _full_grid(w)) <= 1e-5
+
+
+def test_hot_tile_all_points_in_one_cell_block():
+    """5000 points within a few fine cells: one tile holds every point."""
+    rng = np.random.default_rng(9)
+    n = 5000
+    x = rng.uniform(-4e-6, 4e-6, n)
+    y = rng.uniform(-4e-6, 4e-6, n)
+    d = rng.uniform(0, 10e-6, n)
+    u = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
+    w = synth.Workload("hot", x, y, d, u, 532e-9, 0.1, 8e-6, 8e-6, 64, 64)
+    got, _ = gpu_forward(w)
+    assert rel_l2(got, _full_grid(w)) <= 1e-5
+
+
+@pytest.mark.parametrize("fft", ["fp32", "split_fp16"])
+def test_cap_2048_full_size(fft):
+    """The 2048^2 spherical cap at full size on crops and random pixels."""
+    w = synth.config("cap_2048")
+    got, info = gpu_forward(w, fft)
+    for name, (ix, iy) in eval_sets(w, n_random=256, crop=16).items():
+        err = rel_l2(got[iy, ix], _oracle(w, ix, iy))
+        print(f"cap_2048 {fft} {name}: {err:.3e}")
+        assert err <= TOL[fft], name
+
+
+@pytest.mark.parametrize("fft", ["fp32", "split_fp16"])
+def test_sinusoid_4096_full_size(fft):
+    """The 4096^2 sinusoidal relief at full size on small crops and random pixels."""
+    w = synth.config("sinusoid_4096")
+    got, info = gpu_forward(w, fft)
+    for name, (ix, iy) in eval_sets(w, n_random=128, crop=8).items():
+        err = rel_l2(got[iy, ix], _oracle(w, ix, iy))
+        print(f"sinusoid_4096 {fft} {name}: {err:.3e}")
+        assert err <= TOL[fft], name
+
+
+def test_linearity_and_repeat():
+    torch = torch_gpu()
+    import paper_1203_3583_amd as asf
+
+    w = synth.config("cap_2048", side=256)
+    x, y, d, u = to_dev(torch, w)
+    rng = np.random.default_rng(2)
+    v = torch.from_numpy(synth.random_field(rng, 256, 256)).cuda()
+    plan = asf.Plan(x, y, d, w.lam, w.z0, w.p2x, w.p2y, w.mx, w.my)
+    a, b = 0.7 - 0.2j, -0.3 + 1.1j
+    fu = plan.forward(u).cpu().numpy()
+    fv = plan.forward(v).cpu().numpy()
+    fuv = plan.forward((a * u + b * v).to(torch.complex64)).cpu().numpy()
+    fu2 = plan.forward(u).cpu().numpy()
+    plan.close()
+    assert rel_l2(fuv, a * fu + b * fv) <= 1e-6
+    # LDS float atomics make the summation order vary between runs
+    assert rel_l2(fu2, fu) <= 1e-6
+
+
+def test_setpts_matches_new_plan():
+    torch = torch_gpu()
+    import paper_1203_3583_amd as asf
+
+    w1 = synth.config("sinusoid_128", seed=0)
+    w2 = synth.config("sinusoid_128", seed=3)
+    x1, y1, d1, u1 = to_dev(torch, w1)
+    x2, y2, d2, u2 = to_dev(torch, w2)
+    plan = asf.Plan(x1, y1, d1, w1.lam, w1.z0, w1.p2x, w1.p2y, w1.mx, w1.my)
+    plan.setpts(x2, y2, d2)
+    plan.status()
+    got = plan.forward(u2).cpu().numpy()
+    plan.close()
+    fresh, _ = gpu_forward(w2)
+    assert rel_l2(got, fresh) <= 1e-6
+
+
+def test_domain_errors_raise():
+    torch = torch_gpu()
+    import paper_1203_3583_amd as asf
+
+    w = synth.config("sinusoid_128", side=16, out=16)
+    x, y, d, _ = to_dev(torch, w)
+    bad = d.clone()
+    bad[5] = w.z0 + 1e-3              # r0 < 0
+    with pytest.raises(asf.AsfError) as e:
+        asf.Plan(x, y, bad, w.lam, w.z0, w.p2x, w.p2y, w.mx, w.my)
+    assert e.value.code == asf.asf.ASF_EDOMAIN
+    xn = x.clone()
+    xn[3] = float("nan")
+    with pytest.raises(asf.AsfError) as e:
+        asf.Plan(xn, y, d, w.lam, w.z0, w.p2x, w.p2y, w.mx, w.my)
+    assert e.value.code == asf.asf.ASF_EDOMAIN
+    # a valid plan then a bad geometry through setpts: reported by status()
+    plan = asf.Plan(x, y, d, w.lam, w.z0, w.p2x, w.p2y, w.mx, w.my)
+    plan.setpts(x, y, bad)
+    with pytest.raises(asf.AsfError) as e:
+        plan.status()
+    assert e.value.code == asf.asf.ASF_EDOMAIN
+    plan.close()
+
+
+def test_adjoint_not_implemented():
+    torch = torch_gpu()
+    import paper_1203_3583_amd as asf
+
+    w = synth.config("sinusoid_128", side=16, out=16)
+    x, y, d, _ = to_dev(torch, w)
+    plan = asf.Plan(x, y, d, w.lam, w.z0, w.p2x, w.p2y, w.mx, w.my)
+    g2 = torch.zeros((16, 16), dtype=torch.complex64, device="cuda")
+    with pytest.raises(asf.AsfError) as e:
+        plan.adjoint(g2)
+    assert e.value.code == asf.asf.ASF_ENOSYS
+    plan.close()
