@@ -64,7 +64,7 @@ typedef struct asf_plan_s *asf_plan_t;
  *   mx, my    destination grid columns and rows: each a power of two in [16, 8192]
  *             (the 2x oversampled FFT length 2m must be 16^a * {1,2,4,8})
  *   tol       requested relative L2 accuracy in [1e-7, 1e-1]; sets the spreading
- *             width w = ceil(log10(1/tol)) + 2 (7 at 1e-5), capped to [2, 16]
+ *             width w = ceil(log10(1/tol)) + 2 (7 at 1e-5, so 3..9)
  *   flags     ASF_FFT_* | ASF_INCIDENT_NONE
  */
 typedef struct {
@@ -81,7 +81,7 @@ typedef struct {
     int32_t nfx, nfy;     /* oversampled (fine) grid, 2 mx by 2 my */
     int32_t w;            /* spreading width in fine cells */
     double beta;          /* exponential-of-semicircle shape, 2.30 w */
-    int32_t tile;         /* spreading tile edge in fine cells */
+    int32_t tile_x, tile_y; /* spreading tile edges in fine cells */
     int32_t ntiles;       /* tiles in the fine grid */
     int64_t slot_cap;     /* capacity of the binned point list (4 n_src) */
     int32_t col_batch;    /* columns per workgroup in the first FFT pass */
@@ -139,7 +139,8 @@ int asf_status(asf_plan_t plan, void *stream);
  *   u1  complex64 [n_src] device array (interleaved re, im), aligned with x1, y1, d1
  *   u2  complex64 [my][mx] device array, row-major; pixel (ix, iy) at
  *       X = p2x (ix - mx/2), Y = p2y (iy - my/2)
- * Asynchronous on `stream`; never synchronises.  NaN in u1 propagates.
+ * Asynchronous on `stream`; never synchronises.  u1 must be finite (the spreading
+ * accumulates in fixed point; non-finite input gives an unspecified result).
  * Returns ASF_OK, ASF_EINVAL or ASF_EHIP.
  */
 int asf_forward(asf_plan_t plan, const void *u1, void *u2, void *stream);

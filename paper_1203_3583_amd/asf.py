@@ -45,7 +45,8 @@ class Params(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("n_src", ctypes.c_int64), ("mx", ctypes.c_int32), ("my", ctypes.c_int32),
                 ("nfx", ctypes.c_int32), ("nfy", ctypes.c_int32), ("w", ctypes.c_int32),
-                ("beta", ctypes.c_double), ("tile", ctypes.c_int32), ("ntiles", ctypes.c_int32),
+                ("beta", ctypes.c_double), ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("ntiles", ctypes.c_int32),
                 ("slot_cap", ctypes.c_int64), ("col_batch", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("off_status", ctypes.c_size_t), ("off_tile_start", ctypes.c_size_t),
                 ("off_cell", ctypes.c_size_t), ("off_frac", ctypes.c_size_t),

@@ -44,7 +44,8 @@ int hip_fail(hipError_t e, const char *what) {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kAlign = 256;
-constexpr int kTileMax = 64;
+constexpr int kTileXMax = 64;   // spreading tile: 64 x 32 fine cells
+constexpr int kTileYMax = 32;
 constexpr int kQuadNodes = 200;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -59,7 +60,7 @@ int log2i(int v) {
 
 struct Layout {
     int64_t n;
-    int mx, my, nfx, nfy, w, tile, ntx, nty, ntiles;
+    int mx, my, nfx, nfy, w, tile_x, tile_y, ntx, nty, ntiles;
     double beta;
     int64_t slot_cap;
     size_t off_status, off_tile_start, off_cursor, off_cell, off_frac, off_phase, off_perm;
@@ -83,7 +84,7 @@ int check_params(int64_t n, const asf_params *p) {
 int spread_width(double tol) {
     int w = (int)std::ceil(-std::log10(tol) - 1e-9) + 2;
     if (w < 2) w = 2;
-    if (w > 16) w = 16;
+    if (w > 9) w = 9;
     return w;
 }
 
@@ -97,11 +98,10 @@ int make_layout(int64_t n, const asf_params *p, Layout &L) {
     L.nfy = 2 * p->my;
     L.w = spread_width(p->tol);
     L.beta = 2.30 * L.w;
-    L.tile = kTileMax;
-    if (L.nfx < L.tile) L.tile = L.nfx;
-    if (L.nfy < L.tile) L.tile = L.nfy;
-    L.ntx = L.nfx / L.tile;
-    L.nty = L.nfy / L.tile;
+    L.tile_x = L.nfx < kTileXMax ? L.nfx : kTileXMax;
+    L.tile_y = L.nfy < kTileYMax ? L.nfy : kTileYMax;
+    L.ntx = L.nfx / L.tile_x;
+    L.nty = L.nfy / L.tile_y;
     L.ntiles = L.ntx * L.nty;
     L.slot_cap = 4 * n;
     size_t o = 0;
@@ -386,7 +386,8 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
     pl->geo.nfx = L.nfx;
     pl->geo.nfy = L.nfy;
     pl->geo.w = L.w;
-    pl->geo.tile = L.tile;
+    pl->geo.tile_x = L.tile_x;
+    pl->geo.tile_y = L.tile_y;
     pl->geo.ntx = L.ntx;
     pl->geo.nty = L.nty;
     pl->geo.plane = (p->flags & ASF_INCIDENT_NONE) ? 0 : 1;
@@ -395,7 +396,7 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
     const int lds_max = asf::fft_max_lds_bytes();
     const int budget = lds_max < 81920 ? lds_max : 81920;
     int panel = 1;
-    while (panel * 2 <= 16 && panel * 2 <= L.tile &&
+    while (panel * 2 <= 16 && panel * 2 <= L.tile_x &&
            fft_shape(L.nfy, panel * 2).stride * (size_t)panel * 2 * sizeof(float2) <= (size_t)budget)
         panel *= 2;
     while (panel * L.nfy < 256) panel *= 2;
@@ -416,7 +417,8 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
     pl->sp.nfx = L.nfx;
     pl->sp.nfy = L.nfy;
     pl->sp.w = L.w;
-    pl->sp.tile = L.tile;
+    pl->sp.tile_x = L.tile_x;
+    pl->sp.tile_y = L.tile_y;
     pl->sp.ntx = L.ntx;
     pl->sp.nty = L.nty;
     pl->sp.panel = panel;
@@ -487,7 +489,8 @@ int asf_plan_info(asf_plan_t plan, asf_info *info) {
     info->nfy = L.nfy;
     info->w = L.w;
     info->beta = L.beta;
-    info->tile = L.tile;
+    info->tile_x = L.tile_x;
+    info->tile_y = L.tile_y;
     info->ntiles = L.ntiles;
     info->slot_cap = L.slot_cap;
     info->col_batch = plan->sh1.batch;

@@ -27,14 +27,14 @@ struct GeoParams {
     double p2x, p2y;
     int nfx, nfy;      // fine grid
     int w;             // spreading width (cells)
-    int tile;          // tile edge (cells)
+    int tile_x, tile_y; // tile edges (cells)
     int ntx, nty;      // tiles per axis
     int plane;         // 1: u_I = exp(i k d1) (cancels the -k d1 term exactly)
 };
 
 struct SpreadParams {
     int64_t n;         // source points (bound on the gathered index)
-    int nfx, nfy, w, tile, ntx, nty;
+    int nfx, nfy, w, tile_x, tile_y, ntx, nty;
     int panel;         // fine-grid panel width (columns stored contiguously per row)
     float beta_log2e;  // ES shape beta times log2(e), for exp2
 };

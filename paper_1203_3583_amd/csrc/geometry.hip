@@ -67,8 +67,8 @@ __device__ inline PointTiles point_tiles(const GeoParams &g, double x, double y,
     axis_cell(g.p2x * x * s, g.nfx, g.w, p.l0x, p.fx);
     axis_cell(g.p2y * y * s, g.nfy, g.w, p.l0y, p.fy);
     int tx[2], ty[2];
-    const int nx = axis_tiles(p.l0x, g.nfx, g.w, g.tile, tx);
-    const int ny = axis_tiles(p.l0y, g.nfy, g.w, g.tile, ty);
+    const int nx = axis_tiles(p.l0x, g.nfx, g.w, g.tile_x, tx);
+    const int ny = axis_tiles(p.l0y, g.nfy, g.w, g.tile_y, ty);
     for (int a = 0; a < ny; ++a)
         for (int b = 0; b < nx; ++b) p.key[p.n++] = ty[a] * g.ntx + tx[b];
     return p;

@@ -136,9 +136,9 @@ def test_linearity_and_repeat():
     fuv = plan.forward((a * u + b * v).to(torch.complex64)).cpu().numpy()
     fu2 = plan.forward(u).cpu().numpy()
     plan.close()
-    assert rel_l2(fuv, a * fu + b * fv) <= 1e-6
-    # LDS float atomics make the summation order vary between runs
-    assert rel_l2(fu2, fu) <= 1e-6
+    assert rel_l2(fuv, a * fu + b * fv) <= 3e-6
+    # the spread accumulates in integers, so a repeat is bitwise identical
+    assert np.array_equal(fu2, fu)
 
 
 def test_setpts_matches_new_plan():
