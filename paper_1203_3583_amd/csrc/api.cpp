@@ -417,11 +417,12 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
     pl->sp.nfx = L.nfx;
     pl->sp.nfy = L.nfy;
     pl->sp.w = L.w;
-    pl->sp.tile_x = L.tile_x;
-    pl->sp.tile_y = L.tile_y;
+    pl->sp.log_tile_x = log2i(L.tile_x);
+    pl->sp.log_tile_y = log2i(L.tile_y);
+    pl->sp.log_ntx = log2i(L.ntx);
     pl->sp.ntx = L.ntx;
     pl->sp.nty = L.nty;
-    pl->sp.panel = panel;
+    pl->sp.log_panel = log2i(panel);
     pl->sp.beta_log2e = (float)(L.beta * 1.4426950408889634);
 
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -34,8 +34,9 @@ struct GeoParams {
 
 struct SpreadParams {
     int64_t n;         // source points (bound on the gathered index)
-    int nfx, nfy, w, tile_x, tile_y, ntx, nty;
-    int panel;         // fine-grid panel width (columns stored contiguously per row)
+    int nfx, nfy, w, ntx, nty;
+    int log_tile_x, log_tile_y, log_ntx;   // tile edges and tiles per row, as powers of two
+    int log_panel;     // fine-grid panel width (columns stored contiguously per row), log2
     float beta_log2e;  // ES shape beta times log2(e), for exp2
 };
 

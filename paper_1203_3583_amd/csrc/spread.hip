@@ -10,18 +10,29 @@
 // only its own cells -- every fine cell is written exactly once with plain
 // stores, no global atomics and no separate clear of the fine grid.
 //
-// Accumulation is in 64-bit fixed point with LDS integer atomics.  On gfx950 an
-// LDS float atomic add is executed about one lane at a time while the integer
-// ones run at full LDS rate.  Each term is formed exactly as an integer:
-//   A = round(Re/Im(c_j) psi_y 2^a)   (|A| <= 2^22, per point and row)
-//   K = round(psi_x 2^22)             (per point and column)
-//   A K                               (48-bit product: v_mul_i32_i24 + v_mul_hi_i32_i24)
-// and added with ds_add_u64.  The exponent a is set per tile from
-// M = max over its points of |Re u1| + |Im u1|, so 2^a M <= 2^22: the rounding of
-// A and K is 2^-22 of the tile's largest point and of the kernel peak, about
-// the size of FP32 rounding, whatever the number of points in the tile.  Sums
-// stay below 2^62 for tiles of up to 2^18 points (a is lowered beyond that).
+// Accumulation is in fixed point with LDS integer atomics: on gfx950 an LDS
+// float atomic add runs about one lane at a time, the integer ones at full LDS
+// rate.  A term t is made an integer by y = fma(a, k, 1.5 * 2^23): for
+// |t| <= 2^22 the float y lies in [2^23, 2^24), where floats are the integers,
+// so the FMA rounds the exact product to the nearest integer (ties to even:
+// unbiased, which matters because a bias per term would add up coherently over
+// ~1e9 terms at the lowest modes) and the bit pattern of y is
+// 0x4B400000 + round(t).  One 64-bit integer add of a constant then removes the
+// 0x4B400000 offsets.  The scale 2^e is set per tile as the largest e with
+// 2^e M <= 2^22, M = max over the tile's points of |Re u1| + |Im u1| (a bound on
+// |c_j|), so the rounding step is M 2^-22.  Two ways of holding a cell, chosen
+// per tile from K = w^2 times the largest number of footprints that start in
+// one cell (an upper bound on the terms any cell receives):
+//   packed:  if K <= 511 no cell sum can leave int32 (511 * 2^22 < 2^31), and
+//            one 64-bit word holds Re + 2^32 Im, so a single ds_add_u64 adds
+//            both parts of a term (the carry of the low half into the high
+//            half is undone exactly at unpacking);
+//   split:   otherwise (dense tiles) Re and Im are separate 64-bit sums,
+//            accumulated in two sweeps over the same LDS array.
 // Integer addition is associative, so the spread is bitwise deterministic.
+//
+// Each thread keeps the global loads of several slots in flight at once; on
+// this path the time goes to memory latency, not to the LDS atomics.
 //
 // The fine grid is stored in panels of `panel` adjacent columns: element
 // (gx, gy) lives at ((gx / panel) * nfy + gy) * panel + gx % panel, so that the
@@ -34,32 +45,57 @@ namespace {
 constexpr int kTileXMax = 64;
 constexpr int kTileYMax = 32;
 constexpr int kThreads = 512;
+constexpr int kBatch = 4;   // slots per thread with loads in flight together
 
 __device__ inline float es_kernel(float z, float beta_log2e) {
     const float a = fmaxf(0.f, 1.f - z * z);
-    return __builtin_amdgcn_exp2f(beta_log2e * (__builtin_sqrtf(a) - 1.f));
+    return __builtin_amdgcn_exp2f(beta_log2e * (__builtin_amdgcn_sqrtf(a) - 1.f));
 }
 
-// round to nearest, ties to even: unbiased for either sign (a round-half-up
-// conversion would add a positive bias to every term, which piles up at the
-// low modes)
-__device__ inline int round_even(float x) { return (int)__builtin_rintf(x); }
+constexpr float kMagic = 12582912.f;             // 1.5 * 2^23
+constexpr unsigned kMagicBits = 0x4B400000u;      // bit pattern of kMagic
 
-// exact product of two values known to fit in 24 signed bits
-__device__ inline unsigned long long mul24_wide(int a, int k) {
-    const int as = (a << 8) >> 8, ks = (k << 8) >> 8;
-    return (unsigned long long)((long long)as * (long long)ks);
+constexpr unsigned long long kMagic1 = kMagicBits;
+constexpr unsigned long long kMagic2 = ((unsigned long long)kMagicBits << 32) | kMagicBits;
+
+// round(a k) as a 64-bit two's-complement integer, for |a k| <= 2^22
+__device__ inline unsigned long long term1(float a, float k) {
+    return (unsigned long long)__float_as_uint(__builtin_fmaf(a, k, kMagic)) - kMagic1;
+}
+
+// round(re) + 2^32 round(im) modulo 2^64, for |re|, |im| <= 2^22
+__device__ inline unsigned long long term(float ar, float ai, float k) {
+    const float yr = __builtin_fmaf(ar, k, kMagic);
+    const float yi = __builtin_fmaf(ai, k, kMagic);
+    return (((unsigned long long)__float_as_uint(yi) << 32) | __float_as_uint(yr)) - kMagic2;
+}
+
+__device__ inline void unpack2(unsigned long long v, int &re, int &im) {
+    re = (int)(unsigned)(v & 0xffffffffull);
+    im = (int)(unsigned)((v - (unsigned long long)(long long)re) >> 32);
 }
 
 __device__ inline float block_max(float v, float *scratch) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) scratch[wave] = v;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
     __syncthreads();
     float s = 0.f;
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s = fmaxf(s, scratch[i]);
     return s;
+}
+
+// padded start position of a point in this tile, or false if it does not touch it
+__device__ inline bool local_start(uint32_t cell, int x0, int y0, int pad, int hix, int hiy,
+                                   int nfx, int nfy, int &px, int &py) {
+    px = (int)(cell & 0xffffu) - x0 + pad;
+    if (px < 0) px += nfx;
+    else if (px > hix) px -= nfx;
+    py = (int)(cell >> 16) - y0 + pad;
+    if (py < 0) py += nfy;
+    else if (py > hiy) py -= nfy;
+    return px >= 0 && px <= hix && py >= 0 && py <= hiy;
 }
 
 template <int W>
@@ -68,108 +104,153 @@ __global__ void __launch_bounds__(kThreads) spread_kernel(SpreadParams p, Binned
                                                           float2 *__restrict__ fine) {
     constexpr int PAD = W - 1;
     constexpr int CELLS = (kTileXMax + 2 * PAD) * (kTileYMax + 2 * PAD);
-    __shared__ unsigned long long acc_re[CELLS];
-    __shared__ unsigned long long acc_im[CELLS];
+    constexpr int STARTS = (kTileXMax + PAD) * (kTileYMax + PAD);
+    constexpr int B = kBatch;
+    __shared__ unsigned long long acc[CELLS];
+    __shared__ int starts[STARTS];                 // footprint starts per padded cell
     __shared__ float scratch[kThreads / 64];
 
     const int t = blockIdx.x;
-    const int ty = t / p.ntx, tx = t - ty * p.ntx;
-    const int tsx = p.tile_x, tsy = p.tile_y;
-    const int x0 = tx * tsx, y0 = ty * tsy;
+    const int ty = t >> p.log_ntx, tx = t & ((1 << p.log_ntx) - 1);
+    const int tsx = 1 << p.log_tile_x, tsy = 1 << p.log_tile_y;
+    const int x0 = tx << p.log_tile_x, y0 = ty << p.log_tile_y;
     const int pwx = tsx + 2 * PAD, pwy = tsy + 2 * PAD;   // padded tile; pwx = LDS row stride
-    for (int i = threadIdx.x; i < pwx * pwy; i += blockDim.x) {
-        acc_re[i] = 0ull;
-        acc_im[i] = 0ull;
-    }
+    const int swx = tsx + PAD, swy = tsy + PAD;           // start positions per axis
+    const int hix = swx - 1, hiy = swy - 1;
+    const int nt = blockDim.x;
+    for (int i = threadIdx.x; i < pwx * pwy; i += nt) acc[i] = 0ull;
+    for (int i = threadIdx.x; i < swx * swy; i += nt) starts[i] = 0;
+    __syncthreads();
 
-    // fixed-point exponent from the largest |Re u1| + |Im u1| among the tile's points
+    // pass 1: largest |Re u1| + |Im u1| and the count of footprint starts per
+    // position; B slots per thread have their loads in flight together
     const uint32_t s0 = b.tile_start[t], s1 = b.tile_start[t + 1];
     float big = 0.f;
-#pragma unroll 4
-    for (uint32_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
-        const uint32_t j = b.perm[s];
-        if (j < p.n) {
-            const float2 u = u1[j];
-            big = fmaxf(big, fabsf(u.x) + fabsf(u.y));
+    for (uint32_t base = s0 + threadIdx.x; base < s1; base += B * nt) {
+        uint32_t j[B], cell[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const uint32_t s = base + k * nt;
+            const bool in = s < s1;
+            j[k] = in ? b.perm[s] : 0xffffffffu;
+            cell[k] = in ? b.cell[s] : 0u;
         }
-    }
-    big = block_max(big, scratch);
-    int em = 0;
-    if (big > 0.f) frexpf(big, &em);                     // big <= 2^em
-    int cnt_bits = 0;
-    while (cnt_bits < 31 && (1u << cnt_bits) < (s1 - s0)) ++cnt_bits;
-    int a = 22 - em - (cnt_bits > 18 ? cnt_bits - 18 : 0);
-    a = max(-100, min(a, 100));
-    const float scale_a = ldexpf(1.f, a);
-    const double unscale = ldexp(1.0, -(a + 22));
-
-    constexpr float kz = 2.f / (float)W;
-    constexpr float half = 0.5f * (float)(W - 1);
-    const int hix = tsx + PAD - 1, hiy = tsy + PAD - 1;   // largest valid padded start
-    for (uint32_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
-        const uint32_t j = b.perm[s];
-        if (j >= p.n) continue;   // never gather outside u1, whatever a slot holds
-        const uint32_t cell = b.cell[s];
-        int px = (int)(cell & 0xffffu) - x0 + PAD;
-        if (px < 0) px += p.nfx;
-        else if (px > hix) px -= p.nfx;
-        int py = (int)(cell >> 16) - y0 + PAD;
-        if (py < 0) py += p.nfy;
-        else if (py > hiy) py -= p.nfy;
-        if (px < 0 || px > hix || py < 0 || py > hiy) continue;
-        const float2 fr = b.frac[s];
-        const float2 ph = b.phase[s];
-        const float2 u = u1[j];
-        const float cr = (u.x * ph.x - u.y * ph.y) * scale_a;
-        const float ci = (u.x * ph.y + u.y * ph.x) * scale_a;
-        int kx[W];
+        float2 u[B];
 #pragma unroll
-        for (int i = 0; i < W; ++i)
-            kx[i] = round_even(es_kernel(((float)i - half - fr.x) * kz, p.beta_log2e) * 4194304.f);
-        unsigned long long *rre = acc_re + py * pwx + px;
-        unsigned long long *rim = acc_im + py * pwx + px;
+        for (int k = 0; k < B; ++k) u[k] = j[k] < p.n ? u1[j[k]] : make_float2(0.f, 0.f);
 #pragma unroll
-        for (int jy = 0; jy < W; ++jy) {
-            const float ky = es_kernel(((float)jy - half - fr.y) * kz, p.beta_log2e);
-            const int ar = round_even(cr * ky), ai = round_even(ci * ky);
-#pragma unroll
-            for (int i = 0; i < W; ++i) {
-                atomicAdd(rre + jy * pwx + i, mul24_wide(ar, kx[i]));
-                atomicAdd(rim + jy * pwx + i, mul24_wide(ai, kx[i]));
+        for (int k = 0; k < B; ++k) {
+            int px, py;
+            if (j[k] < p.n && local_start(cell[k], x0, y0, PAD, hix, hiy, p.nfx, p.nfy, px, py)) {
+                big = fmaxf(big, fabsf(u[k].x) + fabsf(u[k].y));
+                atomicAdd(&starts[py * swx + px], 1);
             }
         }
     }
-    __syncthreads();
+    big = block_max(big, scratch);   // contains a barrier: starts[] is complete
+    int most = 0;                    // most footprint starts in one cell
+    for (int i = threadIdx.x; i < swx * swy; i += nt) most = max(most, starts[i]);
+    const float kbound = (float)(W * W) * block_max((float)most, scratch);
+    int e = 0;
+    if (big > 0.f) {
+        int em;
+        frexpf(big, &em);                   // big <= 2^em
+        e = 22 - em;
+    }
+    const bool packed = kbound <= 511.f;
+    e = max(-120, min(e, 120));
+    const float scale = ldexpf(1.f, e);
+    const double unscale = ldexp(1.0, -e);
 
-    // write the tile's own cells, panel by panel; on axes where the whole grid
-    // is narrower than the padded tile, fold the wrapped halo back in
+    // pass 2: accumulate every footprint.  Packed tiles need one sweep; split
+    // (dense) tiles sweep twice over one 64-bit array, Re first, then Im.
+    constexpr float kz = 2.f / (float)W;
+    constexpr float half = 0.5f * (float)(W - 1);
     const bool fold_x = p.nfx < pwx, fold_y = p.nfy < pwy;
-    const int C = p.panel;
-    const int n = tsx * tsy;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int c = i % C;
-        const int rest = i / C;
-        const int ly = rest % tsy;
-        const int q = rest / tsy;
-        const int lx = q * C + c;
-        long long sr = 0, si = 0;
-        if (!fold_x && !fold_y) {
-            const int at = (ly + PAD) * pwx + lx + PAD;
-            sr = (long long)acc_re[at];
-            si = (long long)acc_im[at];
-        } else {
-            for (int oy = ly + PAD - 2 * p.nfy; oy < pwy; oy += p.nfy) {
-                if (oy < 0 || (!fold_y && oy != ly + PAD)) continue;
-                for (int ox = lx + PAD - 2 * p.nfx; ox < pwx; ox += p.nfx) {
-                    if (ox < 0 || (!fold_x && ox != lx + PAD)) continue;
-                    sr += (long long)acc_re[oy * pwx + ox];
-                    si += (long long)acc_im[oy * pwx + ox];
+    const int C = 1 << p.log_panel;
+    const int ncell = tsx * tsy;
+    const int sweeps = packed ? 1 : 2;
+    for (int sweep = 0; sweep < sweeps; ++sweep) {
+        for (uint32_t base = s0 + threadIdx.x; base < s1; base += B * nt) {
+            uint32_t j[B], cell[B];
+            float2 fr[B], ph[B];
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                const uint32_t s = base + k * nt;
+                const bool in = s < s1;
+                j[k] = in ? b.perm[s] : 0xffffffffu;
+                cell[k] = in ? b.cell[s] : 0u;
+                fr[k] = in ? b.frac[s] : make_float2(0.f, 0.f);
+                ph[k] = in ? b.phase[s] : make_float2(0.f, 0.f);
+            }
+            float2 u[B];
+#pragma unroll
+            for (int k = 0; k < B; ++k) u[k] = j[k] < p.n ? u1[j[k]] : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                int px, py;
+                if (!(j[k] < p.n && local_start(cell[k], x0, y0, PAD, hix, hiy, p.nfx, p.nfy, px, py))) continue;
+                const float cr = (u[k].x * ph[k].x - u[k].y * ph[k].y) * scale;
+                const float ci = (u[k].x * ph[k].y + u[k].y * ph[k].x) * scale;
+                // split sweep 0 adds Re, sweep 1 adds Im, each into the low half
+                const float c0 = packed ? cr : (sweep == 0 ? cr : ci);
+                float kx[W];
+#pragma unroll
+                for (int i = 0; i < W; ++i) kx[i] = es_kernel(((float)i - half - fr[k].x) * kz, p.beta_log2e);
+                unsigned long long *row = acc + py * pwx + px;
+#pragma unroll
+                for (int jy = 0; jy < W; ++jy) {
+                    const float ky = es_kernel(((float)jy - half - fr[k].y) * kz, p.beta_log2e);
+                    const float ar = c0 * ky, ai = ci * ky;
+                    if (packed) {
+#pragma unroll
+                        for (int i = 0; i < W; ++i) atomicAdd(row + jy * pwx + i, term(ar, ai, kx[i]));
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < W; ++i) atomicAdd(row + jy * pwx + i, term1(ar, kx[i]));
+                    }
                 }
             }
         }
-        const int gx = x0 + lx, gy = y0 + ly;
-        fine[((size_t)(gx / C) * p.nfy + gy) * C + c] =
-            make_float2((float)((double)sr * unscale), (float)((double)si * unscale));
+        __syncthreads();
+
+        // read back the tile's own cells (in the order they are written out);
+        // on axes where the whole grid is narrower than the padded tile, fold
+        // the wrapped halo back in
+        for (int i = threadIdx.x; i < ncell; i += nt) {
+            const int c = i & (C - 1);
+            const int rest = i >> p.log_panel;
+            const int ly = rest & (tsy - 1);
+            const int q = rest >> p.log_tile_y;
+            const int lx = (q << p.log_panel) + c;
+            unsigned long long v = 0ull;
+            if (!fold_x && !fold_y) {
+                v = acc[(ly + PAD) * pwx + lx + PAD];
+            } else {
+                for (int oy = ly + PAD - 2 * p.nfy; oy < pwy; oy += p.nfy) {
+                    if (oy < 0 || (!fold_y && oy != ly + PAD)) continue;
+                    for (int ox = lx + PAD - 2 * p.nfx; ox < pwx; ox += p.nfx) {
+                        if (ox < 0 || (!fold_x && ox != lx + PAD)) continue;
+                        v += acc[oy * pwx + ox];
+                    }
+                }
+            }
+            const int gx = x0 + lx, gy = y0 + ly;
+            float2 *dst = fine + ((((size_t)(gx >> p.log_panel) * p.nfy + gy) << p.log_panel) + c);
+            if (packed) {
+                int sr, si;
+                unpack2(v, sr, si);
+                *dst = make_float2((float)((double)sr * unscale), (float)((double)si * unscale));
+            } else {
+                // split tiles: sweep 0 writes the real part, sweep 1 the imaginary part
+                reinterpret_cast<float *>(dst)[sweep] = (float)((double)(long long)v * unscale);
+            }
+        }
+        if (sweep + 1 < sweeps) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < pwx * pwy; i += nt) acc[i] = 0ull;
+            __syncthreads();
+        }
     }
 }
 
@@ -185,7 +266,7 @@ hipError_t launch_w(const SpreadParams &p, const Binned &b, const float2 *u1, fl
 
 hipError_t launch_spread(const SpreadParams &p, const Binned &b, const float2 *u1, float2 *fine,
                          hipStream_t s) {
-    if (p.tile_x > kTileXMax || p.tile_y > kTileYMax) return hipErrorInvalidValue;
+    if ((1 << p.log_tile_x) > kTileXMax || (1 << p.log_tile_y) > kTileYMax) return hipErrorInvalidValue;
     switch (p.w) {
         case 2: return launch_w<2>(p, b, u1, fine, s);
         case 3: return launch_w<3>(p, b, u1, fine, s);
