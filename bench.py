@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Throughput of the arbitrary-shape-surface Fresnel forward on one MI355X.
+
+Workload: the 2048 x 2048 spherical-cap surface (R = 50 mm, 8 um pitch with
++-0.3 pitch jitter, binary amplitude mask with uniform phase, lambda = 532 nm,
+z0 = 0.2 m, 2048 x 2048 destination at 8 um, sigma = 2, w = 7, tol 1e-5).
+One step is the whole hot path over one batch of synthetic input already
+resident in HBM: the FP64 pre-phase and tile binning (asf_setpts) and the
+spreading plus both FFT passes with the fused deconvolution (asf_forward).
+
+Prints one JSON line.  ``value`` is NU points/s (source points per second of
+whole-step time).  Both FFT precisions are timed; the headline is the faster
+one, the other is reported under ``variants``.  ``roofline`` covers the
+dominant kernel, timed with HIP events on the stream it runs on;
+``cpu_baseline`` times the CPU oracle on a bounded sample of destination pixels
+and compares the GPU output with it there.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "spread_cap_2048_traffic.txt")
+SPREAD_SOURCE = os.path.join(ROOT, "paper_1203_3583_amd", "csrc", "spread.hip")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cpu-pixels", type=int, default=2048, help="oracle sample size (pixels)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (for counter calibration)")
+    return ap.parse_args()
+
+
+def algorithmic_spread_bytes(n_points, nfx, nfy):
+    """Per launch: 32 B per source point (u1 8 B gathered, binned record 24 B:
+    cell 4, offsets 8, pre-phase 8, index 4) plus 8 B per fine-grid cell written."""
+    return 32 * n_points + 8 * nfx * nfy
+
+
+def stored_traffic():
+    """HBM bytes per spread launch from the committed counter summary, if it was
+    taken on the current spread source (else None)."""
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    fields = {}
+    for line in open(PROFILE_TRAFFIC):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    digest = hashlib.sha256(open(SPREAD_SOURCE, "rb").read()).hexdigest()
+    if fields.get("spread_source_sha256") != digest:
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_steps(torch, plan, x, y, d, u, out, steps, warmup, stage_events):
+    for _ in range(warmup):
+        plan.setpts(x, y, d)
+        plan.forward(u, out=out)
+    torch.cuda.synchronize()
+    plan.set_timing(stage_events)
+    stage_sum = {}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.setpts(x, y, d)
+        plan.forward(u, out=out)
+        if stage_events:
+            for k, v in plan.stage_times().items():
+                stage_sum[k] = stage_sum.get(k, 0.0) + v
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    plan.set_timing(False)
+    return dt / steps, {k: v / steps for k, v in stage_sum.items()}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the forward is "
+              "linear in the points, so a multi-GPU run would shard points and sum-reduce u2 -- "
+              "that path is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_1203_3583_amd as asf
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    w = synth.config("cap_2048")
+    x = torch.from_numpy(w.x).to(dev)
+    y = torch.from_numpy(w.y).to(dev)
+    d = torch.from_numpy(w.d).to(dev)
+    u = torch.from_numpy(w.u).to(dev)
+    out = torch.empty((w.my, w.mx), dtype=torch.complex64, device=dev)
+
+    results = {}
+    for fft in ("fp32", "split_fp16"):
+        plan = asf.Plan(x, y, d, w.lam, w.z0, w.p2x, w.p2y, w.mx, w.my, tol=w.tol, fft=fft)
+        info = plan.info()
+        sec, _ = time_steps(torch, plan, x, y, d, u, out, args.steps, args.warmup, False)
+        _, stages = time_steps(torch, plan, x, y, d, u, out, args.steps, 0, True)
+        plan.forward(u, out=out)
+        torch.cuda.synchronize()
+        results[fft] = {"sec": sec, "stages": stages, "info": info,
+                        "u2": out.cpu().numpy().astype(np.complex128)}
+        plan.close()
+
+    if args.copy_calibration:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    head = min(results, key=lambda k: results[k]["sec"])
+    r = results[head]
+    n = w.n
+    info = r["info"]
+    spread_ms = r["stages"].get("spread")
+    alg = algorithmic_spread_bytes(n, info["nfx"], info["nfy"])
+    achieved = alg / (spread_ms * 1e-3) / 1e9 if spread_ms else None
+    line = {
+        "metric": "NU points/s, 2D forward at rel-L2<=1e-5 vs FP64 oracle",
+        "value": n / r["sec"],
+        "unit": "NU points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["sec"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head == "fp32" else "f16x2-split+f32",
+        "data": "synthetic",
+        "config": {"workload": "spherical cap R=50mm, 2048x2048 source at 8um (+-0.3 pitch jitter), "
+                               "binary-mask u1, lambda=532nm, z0=0.2m, 2048x2048 output at 8um",
+                   "n_points": n, "fine_grid": [info["nfy"], info["nfx"]], "w": info["w"],
+                   "sigma": 2, "fft": head, "step": "setpts(prephase+bin) + forward(spread+fft+deconv)"},
+        "stages_ms": {k: round(v, 4) for k, v in r["stages"].items()},
+        "variants": {k: {"ms_per_step": v["sec"] * 1e3, "value": n / v["sec"],
+                         "stages_ms": {s: round(t, 4) for s, t in v["stages"].items()}}
+                     for k, v in results.items()},
+        "roofline": {
+            "kernel": "spread",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": stored_traffic(),
+            "algorithmic_bytes": alg,
+            "avg_launch_ms": spread_ms,
+        },
+        "cpu_baseline": None,
+    }
+
+    if not args.no_cpu:
+        import oracle  # CPU baseline leg only
+
+        ix, iy = synth.sample_pixels(w.mx, w.my, args.cpu_pixels, seed=11)
+        threads = min(16, os.cpu_count() or 1)
+        t0 = time.perf_counter()
+        ref = oracle.direct(w.x, w.y, w.d, w.u, w.lam, w.z0, w.p2x, w.p2y, w.mx, w.my, ix, iy,
+                            incident=w.incident, nthreads=threads)
+        t_cpu = time.perf_counter() - t0
+        t_full = t_cpu * (w.mx * w.my) / len(ix)
+        line["cpu_baseline"] = {
+            "value": n / t_full,
+            "unit": "NU points/s",
+            "cores": oracle.threads(threads),
+            "kind": "oracle",
+            "sample": f"{len(ix)} random destination pixels of the 2048x2048 grid, each a direct FP64 "
+                      f"sum over all {n} points ({t_cpu:.1f} s), extrapolated to the full grid",
+        }
+        line["rel_l2_vs_oracle_sample"] = {
+            k: float(np.linalg.norm(v["u2"][iy, ix] - ref) / np.linalg.norm(ref)) for k, v in results.items()}
+
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()
