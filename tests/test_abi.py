@@ -1,0 +1,115 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry point,
+and the host-only paths (parameter checks, workspace sizing, error codes) behave
+as include/asf.h documents.  No GPU call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "asf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(asf_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def asf():
+    import paper_1203_3583_amd as pkg
+
+    if not os.path.exists(pkg.asf.LIB_PATH):
+        pytest.skip("libasf.so not built")
+    pkg.lib()
+    return pkg
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("asf_plan", "asf_forward", "asf_adjoint", "asf_destroy", "asf_workspace_bytes",
+                     "asf_last_error", "asf_setpts", "asf_status"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(asf):
+    lib = ctypes.CDLL(asf.asf.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_workspace_bytes_layout(asf):
+    p = asf.make_params(532e-9, 0.2, 8e-6, 8e-6, 2048, 2048)
+    n = 2048 * 2048
+    b = asf.workspace_bytes(n, p)
+    nf = 4096
+    # binned records (24 B per slot, 4 slots per point) + fine grid + mid array dominate
+    lower = 24 * 4 * n + 8 * nf * nf + 8 * 2048 * nf
+    assert lower <= b <= lower + (1 << 20)
+    assert b % 256 == 0
+    # more points need more space; the grid size alone sets the FFT buffers
+    assert asf.workspace_bytes(2 * n, p) > b
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(lam=-1.0), "EINVAL"),
+    (dict(z0=0.0), "EINVAL"),
+    (dict(p2x=float("nan")), "EINVAL"),
+    (dict(tol=1e-9), "EINVAL"),
+    (dict(mx=100), "ESIZE"),
+    (dict(my=8), "ESIZE"),
+    (dict(mx=16384), "ESIZE"),
+])
+def test_bad_parameters_rejected(asf, kw, code):
+    args = dict(lam=532e-9, z0=0.2, p2x=8e-6, p2y=8e-6, mx=64, my=64, tol=1e-5)
+    args.update(kw)
+    p = asf.asf.Params(args["lam"], args["z0"], args["p2x"], args["p2y"], args["mx"], args["my"],
+                       args["tol"], 0)
+    assert asf.lib().asf_workspace_bytes(100, ctypes.byref(p)) == 0
+    msg = asf.last_error()
+    assert msg
+    # the plan entry point reports the same failure with the matching code
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(256)
+    rc = asf.lib().asf_plan(ctypes.byref(h), 100, dummy, dummy, dummy, ctypes.byref(p), dummy,
+                            1 << 30, None)
+    assert rc == getattr(asf.asf, "ASF_" + code)
+    assert not h.value
+
+
+def test_null_pointers_and_small_workspace(asf):
+    lib = asf.lib()
+    p = asf.make_params(532e-9, 0.2, 8e-6, 8e-6, 64, 64)
+    h = ctypes.c_void_p()
+    assert lib.asf_plan(None, 10, 1, 1, 1, ctypes.byref(p), 256, 1 << 20, None) == asf.asf.ASF_EINVAL
+    assert lib.asf_plan(ctypes.byref(h), 10, None, 1, 1, ctypes.byref(p), 256, 1 << 20, None) == asf.asf.ASF_EINVAL
+    need = asf.workspace_bytes(10, p)
+    rc = lib.asf_plan(ctypes.byref(h), 10, 256, 256, 256, ctypes.byref(p), 256, need - 1, None)
+    assert rc == asf.asf.ASF_ENOMEM
+    assert "workspace" in asf.last_error()
+    rc = lib.asf_plan(ctypes.byref(h), 10, 256, 256, 256, ctypes.byref(p), 257, need, None)
+    assert rc == asf.asf.ASF_EINVAL   # misaligned workspace
+    assert lib.asf_plan(ctypes.byref(h), 0, 256, 256, 256, ctypes.byref(p), 256, need, None) == asf.asf.ASF_EINVAL
+    for fn in ("asf_forward", "asf_adjoint"):
+        assert getattr(lib, fn)(None, None, None, None) in (asf.asf.ASF_EINVAL, asf.asf.ASF_ENOSYS)
+    assert lib.asf_destroy(None) == asf.asf.ASF_EINVAL
+    assert lib.asf_setpts(None, None, None, None, None) == asf.asf.ASF_EINVAL
+
+
+def test_width_from_tolerance(asf):
+    # w = ceil(log10(1/tol)) + 2, visible through the workspace of a tiny problem only via the
+    # plan; here check the documented mapping indirectly: all tolerances in range are accepted
+    for tol in (1e-7, 1e-6, 1e-5, 1e-3, 1e-1):
+        p = asf.make_params(532e-9, 0.2, 8e-6, 8e-6, 64, 64, tol=tol)
+        assert asf.workspace_bytes(10, p) > 0
+
+
+def test_binding_fails_loudly_without_gpu(asf):
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    x = torch.zeros(4, dtype=torch.float64)
+    with pytest.raises(TypeError):
+        asf.Plan(x, x, x, 532e-9, 0.2, 8e-6, 8e-6, 16, 16)
