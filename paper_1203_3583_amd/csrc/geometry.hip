@@ -16,8 +16,10 @@
 //
 // Binning: each point is listed once in every tile its w x w footprint touches
 // (1, 2 or 4 tiles), so the spreading kernel can own its tile outright and write
-// it with plain stores.  Counting and scattering use wavefront-aggregated
-// atomics on the per-tile counters (one atomic per distinct tile per wave).
+// it with plain stores.  Counting and scattering aggregate per wavefront: the
+// lanes are grouped by tile without memory traffic, then one lane per group
+// issues the atomic -- all groups' atomics in the same instruction, so a wave
+// waits for one round trip rather than one per tile.
 #include "asf_internal.h"
 
 namespace asf {
@@ -74,23 +76,35 @@ __device__ inline PointTiles point_tiles(const GeoParams &g, double x, double y,
     return p;
 }
 
-// All lanes of the wave must call this together.  Active lanes with equal keys
-// share one atomicAdd on counters[key]; each gets base + its rank among them.
-__device__ inline uint32_t wave_rank(uint32_t *counters, int key, bool active) {
+// Group the active lanes of a wave by key (no memory traffic).  Every lane gets
+// the lane id of its group's leader (the lowest lane with that key) and its
+// rank within the group; leaders also get the group size.  All lanes of the
+// wave must call this together.
+struct WaveGroup {
+    int leader;
+    uint32_t rank;
+    uint32_t size;   // meaningful on leaders
+};
+
+__device__ inline WaveGroup wave_group(int key, bool active) {
     const int lane = __lane_id();
     uint64_t todo = __ballot(active);
-    uint32_t result = 0;
+    WaveGroup g;
+    g.leader = lane;
+    g.rank = 0u;
+    g.size = 0u;
     while (todo) {
         const int leader = __ffsll((unsigned long long)todo) - 1;
         const int lkey = __shfl(key, leader);
         const uint64_t mask = __ballot(active && key == lkey) & todo;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&counters[lkey], (uint32_t)__popcll(mask));
-        base = __shfl(base, leader);
-        if ((mask >> lane) & 1ull) result = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+        if ((mask >> lane) & 1ull) {
+            g.leader = leader;
+            g.rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+            if (lane == leader) g.size = (uint32_t)__popcll(mask);
+        }
         todo &= ~mask;
     }
-    return result;
+    return g;
 }
 
 __global__ void __launch_bounds__(256) bin_reset_kernel(Binned b, int ntiles) {
@@ -110,9 +124,11 @@ __global__ void __launch_bounds__(256) bin_count_kernel(GeoParams g, Binned b, i
         p = point_tiles(g, x[j], y[j], d[j]);
         if (p.n == 0) atomicOr(b.status, 1u);
     }
+    // one non-returning atomic per distinct tile per wave and replica
     for (int r = 0; r < 4; ++r) {
         const bool act = r < p.n;
-        wave_rank(b.cursor, act ? p.key[r] : 0, act);
+        const WaveGroup grp = wave_group(act ? p.key[r] : 0, act);
+        if (act && grp.leader == __lane_id()) atomicAdd(&b.cursor[p.key[r]], grp.size);
     }
 }
 
@@ -166,10 +182,20 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(GeoParams g, Binned b,
         }
     }
     const uint32_t cell = (uint32_t)p.l0x | ((uint32_t)p.l0y << 16);
+    // group the four replica keys first, then let the leaders reserve their
+    // groups' slots with atomics that are all in flight at once
+    WaveGroup grp[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) grp[r] = wave_group(r < p.n ? p.key[r] : 0, r < p.n);
+    uint32_t base[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        base[r] = (r < p.n && grp[r].leader == __lane_id()) ? atomicAdd(&b.cursor[p.key[r]], grp[r].size) : 0u;
+#pragma unroll
     for (int r = 0; r < 4; ++r) {
         const bool act = r < p.n;
         const int key = act ? p.key[r] : 0;
-        const uint32_t slot = wave_rank(b.cursor, key, act);
+        const uint32_t slot = __shfl(base[r], grp[r].leader) + grp[r].rank;
         if (act) {
             if (slot < b.tile_start[key + 1]) {
                 b.cell[slot] = cell;
