@@ -121,36 +121,11 @@ int make_layout(int64_t n, const asf_params *p, Layout &L) {
     L.off_mid = take(sizeof(float2) * (size_t)L.my * L.nfx);
     L.off_dx = take(sizeof(float2) * L.mx);
     L.off_dy = take(sizeof(float2) * L.my);
-    L.off_twx = take(sizeof(float2) * L.nfx);
-    L.off_twy = take(sizeof(float2) * L.nfy);
+    L.off_twx = take(sizeof(float2) * asf::fft_twiddle_entries(L.nfx));
+    L.off_twy = take(sizeof(float2) * asf::fft_twiddle_entries(L.nfy));
     L.off_w16 = take(sizeof(float2) * 16);
     L.total = o;
     return ASF_OK;
-}
-
-// Stockham shape of one FFT length with `batch` transforms per workgroup.
-FftShape fft_shape(int len, int batch) {
-    FftShape s;
-    s.L = len;
-    const int e = log2i(len);
-    s.n16 = e / 4;
-    s.r0 = 1 << (e % 4);
-    s.lq = len / 16;
-    s.batch = batch;
-    const int unit = s.lq > 16 ? s.lq : 16;
-    s.stride = len + (len / unit) * 16;
-    const int total = batch * len / 256;   // 16-instance blocks per stage
-    if (total <= 8) {
-        s.waves = total;
-        s.bpw = 1;
-    } else if (total <= 32) {
-        s.waves = 8;
-        s.bpw = total / 8;
-    } else {
-        s.waves = 16;
-        s.bpw = total / 16;
-    }
-    return s;
 }
 
 // Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_n).
@@ -192,6 +167,28 @@ std::vector<double> psi_hat(int nmodes_half, int nf, int w, double beta) {
         out[m] = 0.5 * w * s;
     }
     return out;
+}
+
+// Twiddle tables of the radix-16 Stockham stages of a length-len FFT, in the
+// order the kernels read them: for each stage with span ns > 1 (ns = r0 16^s),
+// entry (k, g, i) = exp(-2 pi i r k / (16 ns)) with r = g + 4 i, k < ns, g, i < 4.
+std::vector<float2> stage_twiddles(int len) {
+    const int log = log2i(len);
+    const int r0 = 1 << (log % 4), n16 = log / 4;
+    std::vector<float2> t;
+    t.reserve(asf::fft_twiddle_entries(len));
+    for (int s = 0; s < n16; ++s) {
+        const int ns = r0 << (4 * s);
+        if (ns <= 1) continue;
+        for (int k = 0; k < ns; ++k)
+            for (int g = 0; g < 4; ++g)
+                for (int i = 0; i < 4; ++i) {
+                    const int r = g + 4 * i;
+                    const double a = 2.0 * kPi * (double)(r * k) / (16.0 * ns);
+                    t.push_back(make_float2((float)std::cos(a), (float)-std::sin(a)));
+                }
+    }
+    return t;
 }
 
 // Reduce a phase argument (rad) to [-pi, pi] in FP64.
@@ -270,7 +267,8 @@ int upload_tables(asf_plan_s *p, hipStream_t s) {
     const Layout &L = p->lay;
     const asf_params &q = p->prm;
     const double k = 2.0 * kPi / q.lambda;
-    std::vector<float2> dx(L.mx), dy(L.my), twx(L.nfx), twy(L.nfy), w16(16);
+    std::vector<float2> dx(L.mx), dy(L.my), w16(16);
+    const std::vector<float2> twx = stage_twiddles(L.nfx), twy = stage_twiddles(L.nfy);
     const std::vector<double> phx = psi_hat(L.mx / 2, L.nfx, L.w, L.beta);
     const std::vector<double> phy = psi_hat(L.my / 2, L.nfy, L.w, L.beta);
     // exp(i k z0) / (i lambda z0) = -i exp(i k z0) / (lambda z0)
@@ -290,14 +288,6 @@ int upload_tables(asf_plan_s *p, hipStream_t s) {
         const double ch = reduce(k * Y * Y / (2.0 * q.z0));
         const double inv = 1.0 / phy[n < 0 ? -n : n];
         dy[iy] = make_float2((float)(std::cos(ch) * inv), (float)(std::sin(ch) * inv));
-    }
-    for (int e = 0; e < L.nfx; ++e) {
-        const double a = 2.0 * kPi * e / L.nfx;
-        twx[e] = make_float2((float)std::cos(a), (float)-std::sin(a));
-    }
-    for (int e = 0; e < L.nfy; ++e) {
-        const double a = 2.0 * kPi * e / L.nfy;
-        twy[e] = make_float2((float)std::cos(a), (float)-std::sin(a));
     }
     for (int e = 0; e < 16; ++e) {
         const double a = 2.0 * kPi * e / 16.0;
@@ -392,25 +382,19 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
     pl->geo.nty = L.nty;
     pl->geo.plane = (p->flags & ASF_INCIDENT_NONE) ? 0 : 1;
 
-    // FFT shapes: pass 1 holds `panel` columns of length nfy per workgroup
+    // FFT shapes: pass 1 holds `panel` adjacent columns of length nfy per workgroup
+    // (the fine grid is stored in panels of that width), pass 2 whole rows
     const int lds_max = asf::fft_max_lds_bytes();
-    const int budget = lds_max < 81920 ? lds_max : 81920;
-    int panel = 1;
-    while (panel * 2 <= 16 && panel * 2 <= L.tile_x &&
-           fft_shape(L.nfy, panel * 2).stride * (size_t)panel * 2 * sizeof(float2) <= (size_t)budget)
-        panel *= 2;
-    while (panel * L.nfy < 256) panel *= 2;
-    pl->sh1 = fft_shape(L.nfy, panel);
-    if (asf::fft_lds_bytes(pl->sh1) > (size_t)lds_max) {
+    const int panel = asf::fft_batch_pass1(L.nfy);
+    pl->sh1.L = L.nfy;
+    pl->sh1.batch = panel;
+    pl->sh2.L = L.nfx;
+    pl->sh2.batch = asf::fft_batch_pass2(L.nfx);
+    if (panel > L.tile_x || L.nfx % panel != 0 || L.my % pl->sh2.batch != 0 ||
+        asf::fft_lds_bytes(L.nfy, panel) > (size_t)lds_max ||
+        asf::fft_lds_bytes(L.nfx, pl->sh2.batch) > (size_t)lds_max) {
         delete pl;
-        return fail(ASF_ESIZE, "column FFT of length %d does not fit in LDS (%d bytes)", L.nfy, lds_max);
-    }
-    int rows = 1;
-    while (rows * L.nfx < 256) rows *= 2;
-    pl->sh2 = fft_shape(L.nfx, rows);
-    if (asf::fft_lds_bytes(pl->sh2) > (size_t)lds_max) {
-        delete pl;
-        return fail(ASF_ESIZE, "row FFT of length %d does not fit in LDS (%d bytes)", L.nfx, lds_max);
+        return fail(ASF_ESIZE, "FFT of %d x %d does not fit this device's LDS (%d bytes)", L.nfx, L.nfy, lds_max);
     }
 
     pl->sp.n = L.n;

@@ -44,14 +44,8 @@ struct SpreadParams {
 // transforms `batch` adjacent fine-grid columns; in the second pass (along x)
 // it transforms `batch` rows of the intermediate array.
 struct FftShape {
-    int L;          // transform length (16^a * r0)
-    int r0;         // first radix (1, 2, 4 or 8), done on the vector ALU
-    int n16;        // number of radix-16 stages
-    int lq;         // L / 16
+    int L;          // transform length, a power of two in [32, 16384]
     int batch;      // transforms per workgroup
-    int stride;     // LDS complex elements per transform (with padding)
-    int waves;      // waves per workgroup
-    int bpw;        // 16-instance MFMA blocks per wave per stage
 };
 
 enum { STAGE_COUNT = 0, STAGE_SCAN, STAGE_SCATTER, STAGE_SPREAD, STAGE_FFT1, STAGE_FFT2, NSTAGES };
@@ -72,7 +66,10 @@ hipError_t launch_fft_pass1(const FftShape &sh, int split16, const float2 *fine,
 hipError_t launch_fft_pass2(const FftShape &sh, int split16, const float2 *mid, float2 *u2,
                             const float2 *tw, const float2 *w16, const float2 *dx,
                             const float2 *dy, int mx, int my, hipStream_t s);
-size_t fft_lds_bytes(const FftShape &sh);
+int fft_batch_pass1(int len);          // columns per workgroup in pass 1 (fine-grid panel width)
+int fft_batch_pass2(int len);          // rows per workgroup in pass 2
+size_t fft_lds_bytes(int len, int batch);
+size_t fft_twiddle_entries(int len);   // complex entries of one length's stage twiddle tables
 int fft_max_lds_bytes();
 
 }  // namespace asf

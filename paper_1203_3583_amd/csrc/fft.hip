@@ -10,16 +10,21 @@
 //           Dx[ix] Dy[iy] (1/psi-hat, the destination chirp of Eq. (6)/(7) and
 //           the prefactor exp(i k z0)/(i lambda z0)) and write u2[iy][ix].
 // A workgroup holds `batch` whole transforms in LDS.  Each transform of length
-// L = r0 * 16^a runs as Stockham stages: one radix-r0 stage (r0 in {1,2,4,8})
-// on the vector ALU, then a radix-16 stages.  In a radix-16 stage the 16-point
-// DFTs of 16 transform instances form one small GEMM
+// L = r0 * 16^a (a compile-time constant here, so every index is a shift or a
+// constant offset) runs as Stockham stages: one radix-r0 stage (r0 in
+// {1,2,4,8}) on the vector ALU, then a radix-16 stages.  In a radix-16 stage
+// the 16-point DFTs of 16 transform instances form one small GEMM
 //     [Re Y; Im Y] (32 x 16) = W16 (32 x 32 real form of the DFT matrix) x [Re X; Im X] (32 x 16)
-// run on the matrix cores, either with FP32 products (v_mfma_f32_16x16x4_f32,
-// 8 K-steps per output half) or with FP16 hi+lo split products
-// (v_mfma_f32_16x16x32_f16: W_hi X_hi + W_hi X_lo + W_lo X_hi with FP32
-// accumulation, X scaled per instance by a power of two so the split stays in
-// FP16 range).  Twiddles are applied in FP32 on the vector ALU before each
-// stage's DFT, from an FP64-computed table.
+// on the matrix cores, either with FP32 products (v_mfma_f32_16x16x4_f32, 8
+// K-steps per output half) or with FP16 hi+lo split products
+// (v_mfma_f32_16x16x32_f16: W_hi X_hi + W_hi X_lo + W_lo X_hi, FP32
+// accumulation).  For the split products the workgroup scales its data once,
+// at load, by a power of two that brings the largest |Re|, |Im| to at most 1:
+// FP16 carries its own exponent, so the scale only guards the range, and a
+// transform of length L grows values by at most L <= 16384 < 65504.
+// Twiddles are applied in FP32 on the vector ALU before each stage's DFT, from
+// FP64-computed tables laid out [k][lane group][4] so that a lane fetches its
+// four twiddles with two 16-byte loads.
 //
 // Lane layout of one 16-instance block (wave64): lane = 16 g + jj holds instance
 // jj's inputs r = g, g+4, g+8, g+12 and, after the MFMAs, its outputs
@@ -34,23 +39,32 @@ namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef _Float16 v2h __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
 
 __device__ inline float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// LDS position of element e of a transform: the low 4 bits are XOR-swizzled by
-// bits 4..7 and 16 slots of padding follow every 2^pad_shift elements, which
-// keeps the stage reads and writes of a half-wave on distinct banks.
-__device__ inline int lds_pos(int e, int pad_shift) {
-    return (e ^ ((e >> 4) & 15)) + ((e >> pad_shift) << 4);
-}
-
-struct Stage {
-    int L, r0, n16, lq, lq_shift, batch, stride, pad_shift;
+// Compile-time shape of one transform length.
+template <int LOGL>
+struct Len {
+    static constexpr int L = 1 << LOGL;
+    static constexpr int N16 = LOGL / 4;          // radix-16 stages
+    static constexpr int R0 = 1 << (LOGL % 4);    // first (vector ALU) radix
+    static constexpr int LQ = L / 16;
+    static constexpr int LOGLQ = LOGL - 4;
+    static constexpr int PS = LQ > 16 ? LOGLQ : 4;            // one pad of 16 per 2^PS elements
+    static constexpr int STRIDE = L + (L >> PS) * 16;          // LDS elements per transform
 };
 
-// A-operand (DFT matrix) fragments for this lane, built from w16[q] = exp(-2 pi i q / 16).
+// LDS position of element e: low 4 bits XOR-swizzled by bits 4..7, plus 16 slots
+// of padding every 2^PS elements (keeps a half-wave's accesses on distinct banks).
+template <int PS>
+__device__ inline int lds_pos(int e) {
+    return (e ^ ((e >> 4) & 15)) + ((e >> PS) << 4);
+}
+
 struct Dft16F32 {
     float are[8], aim[8];
     __device__ void init(const float2 *w16, int g, int jj) {
@@ -93,22 +107,19 @@ struct Dft16Split16 {
             im_lo[e] = (_Float16)(b - (float)bh);
         }
     }
+    // inputs already scaled into FP16 range by the workgroup's scale
     __device__ void run(float2 (&v)[4]) const {
-        float m = 0.f;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) m = fmaxf(m, fmaxf(fabsf(v[i].x), fabsf(v[i].y)));
-        m = fmaxf(m, __shfl_xor(m, 16));
-        m = fmaxf(m, __shfl_xor(m, 32));
-        int ex = 0;
-        if (m > 0.f) frexpf(m, &ex);
-        const float inv = ldexpf(1.f, -ex), sc = ldexpf(1.f, ex);
         v8h bh, bl;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float val = ((e & 1) ? v[e >> 1].y : v[e >> 1].x) * inv;
-            const _Float16 h = (_Float16)val;
-            bh[e] = h;
-            bl[e] = (_Float16)(val - (float)h);
+        for (int i = 0; i < 4; ++i) {
+            const v2f x = {v[i].x, v[i].y};
+            const v2h h = __builtin_convertvector(x, v2h);
+            const v2f r = x - __builtin_convertvector(h, v2f);
+            const v2h l = __builtin_convertvector(r, v2h);
+            bh[2 * i] = h.x;
+            bh[2 * i + 1] = h.y;
+            bl[2 * i] = l.x;
+            bl[2 * i + 1] = l.y;
         }
         v4f accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
         accr = __builtin_amdgcn_mfma_f32_16x16x32_f16(re_lo, bh, accr, 0, 0, 0);
@@ -118,27 +129,28 @@ struct Dft16Split16 {
         accr = __builtin_amdgcn_mfma_f32_16x16x32_f16(re_hi, bh, accr, 0, 0, 0);
         acci = __builtin_amdgcn_mfma_f32_16x16x32_f16(im_hi, bh, acci, 0, 0, 0);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v[i] = make_float2(accr[i] * sc, acci[i] * sc);
+        for (int i = 0; i < 4; ++i) v[i] = make_float2(accr[i], acci[i]);
     }
 };
 
 // Radix-R0 first stage (Ns = 1, no twiddles) on the vector ALU, in place.
-template <int R0, int BPW>
-__device__ void first_stage(float2 *lds, const Stage &st, const float2 *w16s) {
+template <int LOGL, int BATCH, int NT>
+__device__ void first_stage(float2 *lds, const float2 *w16s) {
+    using S = Len<LOGL>;
+    constexpr int R0 = S::R0;
     if constexpr (R0 > 1) {
-        constexpr int IPT = (4 * BPW) / R0 > 0 ? (4 * BPW) / R0 : 1;  // instances per thread
-        const int nt = blockDim.x;
-        const int per = st.L / R0;
-        const int ninst = st.batch * per;
+        constexpr int PER = S::L / R0;
+        constexpr int NINST = BATCH * PER;
+        constexpr int IPT = (NINST + NT - 1) / NT;
         float2 v[IPT][R0];
 #pragma unroll
         for (int a = 0; a < IPT; ++a) {
-            const int inst = threadIdx.x + a * nt;
-            if (inst < ninst) {
-                const int c = inst / per, j = inst - c * per;
+            const int inst = threadIdx.x + a * NT;
+            if (inst < NINST) {
+                const int c = inst / PER, j = inst % PER;
                 float2 x[R0];
 #pragma unroll
-                for (int r = 0; r < R0; ++r) x[r] = lds[c * st.stride + lds_pos(j + r * per, st.pad_shift)];
+                for (int r = 0; r < R0; ++r) x[r] = lds[c * S::STRIDE + lds_pos<S::PS>(j + r * PER)];
 #pragma unroll
                 for (int p = 0; p < R0; ++p) {
                     float2 acc = x[0];
@@ -155,151 +167,212 @@ __device__ void first_stage(float2 *lds, const Stage &st, const float2 *w16s) {
         __syncthreads();
 #pragma unroll
         for (int a = 0; a < IPT; ++a) {
-            const int inst = threadIdx.x + a * nt;
-            if (inst < ninst) {
-                const int c = inst / per, j = inst - c * per;
+            const int inst = threadIdx.x + a * NT;
+            if (inst < NINST) {
+                const int c = inst / PER, j = inst % PER;
 #pragma unroll
-                for (int p = 0; p < R0; ++p) lds[c * st.stride + lds_pos(j * R0 + p, st.pad_shift)] = v[a][p];
+                for (int p = 0; p < R0; ++p) lds[c * S::STRIDE + lds_pos<S::PS>(j * R0 + p)] = v[a][p];
             }
         }
         __syncthreads();
     }
 }
 
-// All radix-16 stages, in place in LDS.
-template <class Engine, int R0, int BPW>
-__device__ void radix16_stages(float2 *lds, const Stage &st, const float2 *__restrict__ tw,
-                               const Engine &eng) {
+// One radix-16 Stockham stage with span NS, in place in LDS.  tw points at this
+// stage's table: entry (k, g, i) = exp(-2 pi i (g + 4 i) k / (16 NS)).
+template <int LOGL, int BATCH, int NT, int NS, class Engine>
+__device__ void radix16_stage(float2 *lds, const float4 *__restrict__ tw, const Engine &eng) {
+    using S = Len<LOGL>;
+    constexpr int BLOCKS = BATCH * S::LQ / 16;     // 16-instance blocks in the stage
+    constexpr int WAVES = NT / 64;
+    constexpr int BPW = BLOCKS / WAVES;
+    static_assert(BLOCKS % WAVES == 0 && BPW >= 1, "blocks must divide among waves");
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, jj = lane & 15;
     const int wave = threadIdx.x >> 6;
-    const int lq = st.lq;
-    int ns = R0;
-    for (int s = 0; s < st.n16; ++s) {
-        float2 v[BPW][4];
-        const int tstep = lq / ns;   // twiddle index step: L / (16 ns)
+    float2 v[BPW][4];
 #pragma unroll
-        for (int b = 0; b < BPW; ++b) {
-            const int q = (wave * BPW + b) * 16 + jj;
-            const int c = q >> st.lq_shift, j = q & (lq - 1);
-            const int k = j & (ns - 1);
-            const float2 *col = lds + c * st.stride;
+    for (int b = 0; b < BPW; ++b) {
+        const int q = (wave * BPW + b) * 16 + jj;
+        const int c = q >> S::LOGLQ, j = q & (S::LQ - 1);
+        const float2 *col = lds + c * S::STRIDE;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = g + 4 * i;
-                float2 x = col[lds_pos(j + r * lq, st.pad_shift)];
-                if (ns > 1) x = cmul(x, tw[r * k * tstep]);
-                v[b][i] = x;
-            }
-            eng.run(v[b]);
+        for (int i = 0; i < 4; ++i) v[b][i] = col[lds_pos<S::PS>(j + (g + 4 * i) * S::LQ)];
+        if constexpr (NS > 1) {
+            const int k = j & (NS - 1);
+            const float4 *t = tw + (k * 16 + g * 4) / 2;
+            const float4 t01 = t[0], t23 = t[1];
+            v[b][0] = cmul(v[b][0], make_float2(t01.x, t01.y));
+            v[b][1] = cmul(v[b][1], make_float2(t01.z, t01.w));
+            v[b][2] = cmul(v[b][2], make_float2(t23.x, t23.y));
+            v[b][3] = cmul(v[b][3], make_float2(t23.z, t23.w));
         }
-        __syncthreads();
+        eng.run(v[b]);
+    }
+    __syncthreads();
 #pragma unroll
-        for (int b = 0; b < BPW; ++b) {
-            const int q = (wave * BPW + b) * 16 + jj;
-            const int c = q >> st.lq_shift, j = q & (lq - 1);
-            const int k = j & (ns - 1);
-            const int base = (j - k) * 16 + k;   // (j / ns) * 16 ns + k
-            float2 *col = lds + c * st.stride;
+    for (int b = 0; b < BPW; ++b) {
+        const int q = (wave * BPW + b) * 16 + jj;
+        const int c = q >> S::LOGLQ, j = q & (S::LQ - 1);
+        const int k = j & (NS - 1);
+        const int base = (j - k) * 16 + k;   // (j / NS) * 16 NS + k
+        float2 *col = lds + c * S::STRIDE;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int p = g + 4 * i;
-                col[lds_pos(base + p * ns, st.pad_shift)] = v[b][i];
-            }
-        }
-        __syncthreads();
-        ns *= 16;
+        for (int i = 0; i < 4; ++i) col[lds_pos<S::PS>(base + (g + 4 * i) * NS)] = v[b][i];
+    }
+    __syncthreads();
+}
+
+// Offset (in complex entries) of stage STAGE's twiddle table: tables are stored
+// only for stages with span NS > 1, in stage order, 16 NS entries each.
+template <int LOGL>
+constexpr int twiddle_offset(int stage) {
+    int off = 0;
+    for (int s = 0; s < stage; ++s) {
+        const int ns = Len<LOGL>::R0 << (4 * s);
+        if (ns > 1) off += 16 * ns;
+    }
+    return off;
+}
+
+template <int LOGL, int BATCH, int NT, int STAGE, class Engine>
+__device__ void stages_from(float2 *lds, const float4 *tw, const Engine &eng) {
+    using S = Len<LOGL>;
+    if constexpr (STAGE < S::N16) {
+        constexpr int NS = S::R0 << (4 * STAGE);
+        constexpr int OFF = twiddle_offset<LOGL>(STAGE);
+        radix16_stage<LOGL, BATCH, NT, NS, Engine>(lds, reinterpret_cast<const float4 *>(
+                                                            reinterpret_cast<const float2 *>(tw) + OFF), eng);
+        stages_from<LOGL, BATCH, NT, STAGE + 1, Engine>(lds, tw, eng);
     }
 }
 
-template <int SPLIT, int R0, int BPW>
-__device__ void transform_all(float2 *lds, const Stage &st, const float2 *tw, const float2 *w16) {
+template <int LOGL, int BATCH, int NT, bool SPLIT>
+__device__ void transform_all(float2 *lds, const float2 *tw, const float2 *w16) {
     __shared__ float2 w16s[16];
     if (threadIdx.x < 16) w16s[threadIdx.x] = w16[threadIdx.x];
     __syncthreads();
-    first_stage<R0, BPW>(lds, st, w16s);
+    first_stage<LOGL, BATCH, NT>(lds, w16s);
     const int lane = threadIdx.x & 63;
     if constexpr (SPLIT) {
         Dft16Split16 eng;
         eng.init(w16s, lane >> 4, lane & 15);
-        radix16_stages<Dft16Split16, R0, BPW>(lds, st, tw, eng);
+        stages_from<LOGL, BATCH, NT, 0, Dft16Split16>(lds, reinterpret_cast<const float4 *>(tw), eng);
     } else {
         Dft16F32 eng;
         eng.init(w16s, lane >> 4, lane & 15);
-        radix16_stages<Dft16F32, R0, BPW>(lds, st, tw, eng);
+        stages_from<LOGL, BATCH, NT, 0, Dft16F32>(lds, reinterpret_cast<const float4 *>(tw), eng);
     }
 }
 
-// Pass 1: workgroup = one panel of `batch` adjacent fine-grid columns.
-template <int SPLIT, int R0, int BPW>
-__global__ void __launch_bounds__(1024) fft_pass1_kernel(Stage st, const float2 *__restrict__ fine,
-                                                         float2 *__restrict__ mid,
-                                                         const float2 *__restrict__ tw,
-                                                         const float2 *__restrict__ w16, int nfx,
-                                                         int my) {
+__device__ inline float block_max(float v, float *scratch) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float s = 0.f;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s = fmaxf(s, scratch[i]);
+    return s;
+}
+
+// power of two 2^e with max_abs * 2^-e <= 1 (1 for zero data)
+__device__ inline int range_exponent(float max_abs) {
+    int e = 0;
+    if (max_abs > 0.f) frexpf(max_abs, &e);
+    return e;
+}
+
+// Pass 1: a workgroup transforms one panel of BATCH adjacent fine-grid columns.
+template <int LOGL, int BATCH, int NT, bool SPLIT>
+__global__ void __launch_bounds__(NT) fft_pass1_kernel(const float2 *__restrict__ fine,
+                                                       float2 *__restrict__ mid,
+                                                       const float2 *__restrict__ tw,
+                                                       const float2 *__restrict__ w16, int nfx,
+                                                       int my, int xcd_group) {
+    using S = Len<LOGL>;
     extern __shared__ float2 lds[];
-    const int C = st.batch, L = st.L;
-    const int pc = blockIdx.x;
-    const float2 *src = fine + (size_t)pc * L * C;
-    for (int t = threadIdx.x; t < L * C; t += blockDim.x) {
-        const int ly = t / C, c = t - ly * C;
-        lds[c * st.stride + lds_pos(ly, st.pad_shift)] = src[t];
+    __shared__ float scratch[NT / 64];
+    // panels whose output rows share 128-byte lines of mid go to one XCD
+    // (workgroups are dealt to the 8 XCDs round-robin), so the partial-line
+    // writes meet in that XCD's L2
+    int pc = blockIdx.x;
+    if (xcd_group > 1) {
+        const int xcd = pc & 7, slot = pc >> 3;
+        pc = ((slot / xcd_group) * 8 + xcd) * xcd_group + slot % xcd_group;
+    }
+    const float2 *src = fine + (size_t)pc * S::L * BATCH;
+    float big = 0.f;
+    for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
+        const float2 v = src[t];
+        const int ly = t / BATCH, c = t % BATCH;
+        lds[c * S::STRIDE + lds_pos<S::PS>(ly)] = v;
+        if constexpr (SPLIT) big = fmaxf(big, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+    float unscale = 1.f;
+    if constexpr (SPLIT) {
+        const int e = range_exponent(block_max(big, scratch));
+        const float inv = ldexpf(1.f, -e);
+        unscale = ldexpf(1.f, e);
+        __syncthreads();
+        for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
+            const int ly = t / BATCH, c = t % BATCH;
+            float2 &x = lds[c * S::STRIDE + lds_pos<S::PS>(ly)];
+            x = make_float2(x.x * inv, x.y * inv);
+        }
     }
     __syncthreads();
-    transform_all<SPLIT, R0, BPW>(lds, st, tw, w16);
+    transform_all<LOGL, BATCH, NT, SPLIT>(lds, tw, w16);
     const int half = my >> 1;
-    for (int t = threadIdx.x; t < my * C; t += blockDim.x) {
-        const int ky = t / C, c = t - ky * C;
-        int l = ky - half;
-        if (l < 0) l += L;
-        mid[(size_t)ky * nfx + pc * C + c] = lds[c * st.stride + lds_pos(l, st.pad_shift)];
+    for (int t = threadIdx.x; t < my * BATCH; t += NT) {
+        const int ky = t / BATCH, c = t % BATCH;
+        const int l = (ky - half) & (S::L - 1);
+        const float2 v = lds[c * S::STRIDE + lds_pos<S::PS>(l)];
+        mid[(size_t)ky * nfx + pc * BATCH + c] = make_float2(v.x * unscale, v.y * unscale);
     }
 }
 
-// Pass 2: workgroup = `batch` rows of mid; fused deconvolution and phase.
-template <int SPLIT, int R0, int BPW>
-__global__ void __launch_bounds__(1024) fft_pass2_kernel(Stage st, const float2 *__restrict__ mid,
-                                                         float2 *__restrict__ u2,
-                                                         const float2 *__restrict__ tw,
-                                                         const float2 *__restrict__ w16,
-                                                         const float2 *__restrict__ dx,
-                                                         const float2 *__restrict__ dy, int mx) {
+// Pass 2: a workgroup transforms BATCH rows of mid; fused deconvolution and phase.
+template <int LOGL, int BATCH, int NT, bool SPLIT>
+__global__ void __launch_bounds__(NT) fft_pass2_kernel(const float2 *__restrict__ mid,
+                                                       float2 *__restrict__ u2,
+                                                       const float2 *__restrict__ tw,
+                                                       const float2 *__restrict__ w16,
+                                                       const float2 *__restrict__ dx,
+                                                       const float2 *__restrict__ dy, int mx) {
+    using S = Len<LOGL>;
     extern __shared__ float2 lds[];
-    const int C = st.batch, L = st.L;
-    const int row0 = blockIdx.x * C;
-    const float2 *src = mid + (size_t)row0 * L;
-    for (int t = threadIdx.x; t < L * C; t += blockDim.x) {
-        const int c = t / L, lx = t - c * L;
-        lds[c * st.stride + lds_pos(lx, st.pad_shift)] = src[t];
+    __shared__ float scratch[NT / 64];
+    const int row0 = blockIdx.x * BATCH;
+    const float2 *src = mid + (size_t)row0 * S::L;
+    float big = 0.f;
+    for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
+        const float2 v = src[t];
+        const int c = t >> LOGL, lx = t & (S::L - 1);
+        lds[c * S::STRIDE + lds_pos<S::PS>(lx)] = v;
+        if constexpr (SPLIT) big = fmaxf(big, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+    float unscale = 1.f;
+    if constexpr (SPLIT) {
+        const int e = range_exponent(block_max(big, scratch));
+        const float inv = ldexpf(1.f, -e);
+        unscale = ldexpf(1.f, e);
+        __syncthreads();
+        for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
+            const int c = t >> LOGL, lx = t & (S::L - 1);
+            float2 &x = lds[c * S::STRIDE + lds_pos<S::PS>(lx)];
+            x = make_float2(x.x * inv, x.y * inv);
+        }
     }
     __syncthreads();
-    transform_all<SPLIT, R0, BPW>(lds, st, tw, w16);
+    transform_all<LOGL, BATCH, NT, SPLIT>(lds, tw, w16);
     const int half = mx >> 1;
-    for (int t = threadIdx.x; t < mx * C; t += blockDim.x) {
+    for (int t = threadIdx.x; t < mx * BATCH; t += NT) {
         const int c = t / mx, ix = t - c * mx;
-        int l = ix - half;
-        if (l < 0) l += L;
-        const float2 val = lds[c * st.stride + lds_pos(l, st.pad_shift)];
+        const int l = (ix - half) & (S::L - 1);
+        float2 val = lds[c * S::STRIDE + lds_pos<S::PS>(l)];
+        val = make_float2(val.x * unscale, val.y * unscale);
         u2[(size_t)(row0 + c) * mx + ix] = cmul(cmul(val, dx[ix]), dy[row0 + c]);
     }
-}
-
-Stage make_stage(const FftShape &sh) {
-    Stage st;
-    st.L = sh.L;
-    st.r0 = sh.r0;
-    st.n16 = sh.n16;
-    st.lq = sh.lq;
-    int s = 0;
-    while ((1 << s) < sh.lq) ++s;
-    st.lq_shift = s;
-    st.batch = sh.batch;
-    st.stride = sh.stride;
-    int ps = 0;
-    const int unit = sh.lq > 16 ? sh.lq : 16;
-    while ((1 << ps) < unit) ++ps;
-    st.pad_shift = ps;
-    return st;
 }
 
 // Kernels needing more than 64 KB of dynamic LDS must say so once per size.
@@ -312,58 +385,118 @@ hipError_t allow_lds(const void *kernel, size_t lds, size_t &enabled) {
     return hipSuccess;
 }
 
-template <int PASS, int SPLIT, int R0, int BPW>
-hipError_t launch_t(const FftShape &sh, const float2 *in, float2 *out, const float2 *tw,
-                    const float2 *w16, const float2 *dx, const float2 *dy, int nx_out, int n_other,
-                    hipStream_t s) {
-    const Stage st = make_stage(sh);
-    const size_t lds = fft_lds_bytes(sh);
-    const dim3 block(64 * sh.waves);
-    static thread_local size_t enabled = 0;   // per instantiation and host thread
-    if (PASS == 1) {
-        auto k = fft_pass1_kernel<SPLIT, R0, BPW>;
-        hipError_t e = allow_lds((const void *)k, lds, enabled);
-        if (e != hipSuccess) return e;
-        const int groups = nx_out / sh.batch;   // nfx / batch panels
-        hipLaunchKernelGGL(k, dim3(groups), block, lds, s, st, in, out, tw, w16, nx_out, n_other);
-    } else {
-        auto k = fft_pass2_kernel<SPLIT, R0, BPW>;
-        hipError_t e = allow_lds((const void *)k, lds, enabled);
-        if (e != hipSuccess) return e;
-        const int groups = n_other / sh.batch;  // my / batch row groups
-        hipLaunchKernelGGL(k, dim3(groups), block, lds, s, st, in, out, tw, w16, dx, dy, nx_out);
-    }
+// Threads per workgroup for BATCH transforms of length 2^LOGL: one wave per
+// 16-instance block up to 8 waves, then several blocks per wave.
+template <int LOGL, int BATCH>
+constexpr int threads_for() {
+    constexpr int blocks = BATCH * (1 << LOGL) / 256;
+    return blocks <= 8 ? 64 * blocks : 512;
+}
+
+template <int LOGL, int BATCH, bool SPLIT>
+hipError_t launch1(const FftShape &sh, const float2 *fine, float2 *mid, const float2 *tw,
+                   const float2 *w16, int nfx, int my, hipStream_t s) {
+    constexpr int NT = threads_for<LOGL, BATCH>();
+    const size_t lds = (size_t)BATCH * Len<LOGL>::STRIDE * sizeof(float2);
+    static thread_local size_t enabled = 0;
+    auto k = fft_pass1_kernel<LOGL, BATCH, NT, SPLIT>;
+    hipError_t e = allow_lds((const void *)k, lds, enabled);
+    if (e != hipSuccess) return e;
+    const int groups = nfx / BATCH;
+    const int g = 16 / BATCH;   // panels per 128-byte line of a mid row
+    const int xcd_group = (g > 1 && groups % (8 * g) == 0) ? g : 1;
+    (void)sh;
+    hipLaunchKernelGGL(k, dim3(groups), dim3(NT), lds, s, fine, mid, tw, w16, nfx, my, xcd_group);
     return hipGetLastError();
 }
 
-template <int PASS, int SPLIT, int R0>
-hipError_t launch_bpw(const FftShape &sh, const float2 *in, float2 *out, const float2 *tw,
-                      const float2 *w16, const float2 *dx, const float2 *dy, int nx_out,
-                      int n_other, hipStream_t s) {
-    switch (sh.bpw) {
-        case 1: return launch_t<PASS, SPLIT, R0, 1>(sh, in, out, tw, w16, dx, dy, nx_out, n_other, s);
-        case 2: return launch_t<PASS, SPLIT, R0, 2>(sh, in, out, tw, w16, dx, dy, nx_out, n_other, s);
-        case 4: return launch_t<PASS, SPLIT, R0, 4>(sh, in, out, tw, w16, dx, dy, nx_out, n_other, s);
+template <int LOGL, int BATCH, bool SPLIT>
+hipError_t launch2(const FftShape &sh, const float2 *mid, float2 *u2, const float2 *tw,
+                   const float2 *w16, const float2 *dx, const float2 *dy, int mx, int my,
+                   hipStream_t s) {
+    constexpr int NT = threads_for<LOGL, BATCH>();
+    const size_t lds = (size_t)BATCH * Len<LOGL>::STRIDE * sizeof(float2);
+    static thread_local size_t enabled = 0;
+    auto k = fft_pass2_kernel<LOGL, BATCH, NT, SPLIT>;
+    hipError_t e = allow_lds((const void *)k, lds, enabled);
+    if (e != hipSuccess) return e;
+    (void)sh;
+    hipLaunchKernelGGL(k, dim3(my / BATCH), dim3(NT), lds, s, mid, u2, tw, w16, dx, dy, mx);
+    return hipGetLastError();
+}
+
+// Batch sizes used per length (see fft_batch_pass1/2): pass 1 fills about 68 KB
+// of LDS, pass 2 uses one row unless the row is shorter than 256.
+template <bool SPLIT>
+hipError_t dispatch1(const FftShape &sh, const float2 *fine, float2 *mid, const float2 *tw,
+                     const float2 *w16, int nfx, int my, hipStream_t s) {
+    const int log = __builtin_ctz(sh.L);
+    switch (log) {
+        case 5: return launch1<5, 16, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
+        case 6: return launch1<6, 16, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
+        case 7: return launch1<7, 16, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
+        case 8: return launch1<8, 16, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
+        case 9: return launch1<9, 16, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
+        case 10: return launch1<10, 8, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
+        case 11: return launch1<11, 4, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
+        case 12: return launch1<12, 2, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
+        case 13: return launch1<13, 1, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
+        case 14: return launch1<14, 1, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <int PASS, int SPLIT>
-hipError_t launch_r0(const FftShape &sh, const float2 *in, float2 *out, const float2 *tw,
-                     const float2 *w16, const float2 *dx, const float2 *dy, int nx_out, int n_other,
+template <bool SPLIT>
+hipError_t dispatch2(const FftShape &sh, const float2 *mid, float2 *u2, const float2 *tw,
+                     const float2 *w16, const float2 *dx, const float2 *dy, int mx, int my,
                      hipStream_t s) {
-    switch (sh.r0) {
-        case 1: return launch_bpw<PASS, SPLIT, 1>(sh, in, out, tw, w16, dx, dy, nx_out, n_other, s);
-        case 2: return launch_bpw<PASS, SPLIT, 2>(sh, in, out, tw, w16, dx, dy, nx_out, n_other, s);
-        case 4: return launch_bpw<PASS, SPLIT, 4>(sh, in, out, tw, w16, dx, dy, nx_out, n_other, s);
-        case 8: return launch_bpw<PASS, SPLIT, 8>(sh, in, out, tw, w16, dx, dy, nx_out, n_other, s);
+    const int log = __builtin_ctz(sh.L);
+    switch (log) {
+        case 5: return launch2<5, 8, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
+        case 6: return launch2<6, 4, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
+        case 7: return launch2<7, 2, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
+        case 8: return launch2<8, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
+        case 9: return launch2<9, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
+        case 10: return launch2<10, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
+        case 11: return launch2<11, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
+        case 12: return launch2<12, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
+        case 13: return launch2<13, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
+        case 14: return launch2<14, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-size_t fft_lds_bytes(const FftShape &sh) { return (size_t)sh.batch * sh.stride * sizeof(float2); }
+int fft_batch_pass1(int len) {
+    const int log = __builtin_ctz(len);
+    return log <= 9 ? 16 : log == 10 ? 8 : log == 11 ? 4 : log == 12 ? 2 : 1;
+}
+
+int fft_batch_pass2(int len) {
+    const int log = __builtin_ctz(len);
+    return log == 5 ? 8 : log == 6 ? 4 : log == 7 ? 2 : 1;
+}
+
+size_t fft_lds_bytes(int len, int batch) {
+    const int log = __builtin_ctz(len);
+    const int lq = len / 16;
+    const int ps = lq > 16 ? log - 4 : 4;
+    return (size_t)batch * (len + (len >> ps) * 16) * sizeof(float2);
+}
+
+size_t fft_twiddle_entries(int len) {
+    // stages with span NS > 1 store 16 NS entries each
+    const int log = __builtin_ctz(len);
+    const int r0 = 1 << (log % 4);
+    const int n16 = log / 4;
+    size_t total = 0;
+    for (int s = 0; s < n16; ++s) {
+        const int ns = r0 << (4 * s);
+        if (ns > 1) total += 16 * (size_t)ns;
+    }
+    return total;
+}
 
 int fft_max_lds_bytes() {
     int dev = 0, v = 0;
@@ -374,15 +507,15 @@ int fft_max_lds_bytes() {
 
 hipError_t launch_fft_pass1(const FftShape &sh, int split16, const float2 *fine, float2 *mid,
                             const float2 *tw, const float2 *w16, int nfx, int my, hipStream_t s) {
-    if (split16) return launch_r0<1, 1>(sh, fine, mid, tw, w16, nullptr, nullptr, nfx, my, s);
-    return launch_r0<1, 0>(sh, fine, mid, tw, w16, nullptr, nullptr, nfx, my, s);
+    if (split16) return dispatch1<true>(sh, fine, mid, tw, w16, nfx, my, s);
+    return dispatch1<false>(sh, fine, mid, tw, w16, nfx, my, s);
 }
 
 hipError_t launch_fft_pass2(const FftShape &sh, int split16, const float2 *mid, float2 *u2,
                             const float2 *tw, const float2 *w16, const float2 *dx,
                             const float2 *dy, int mx, int my, hipStream_t s) {
-    if (split16) return launch_r0<2, 1>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
-    return launch_r0<2, 0>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
+    if (split16) return dispatch2<true>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
+    return dispatch2<false>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
 }
 
 }  // namespace asf
