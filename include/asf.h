@@ -84,7 +84,8 @@ typedef struct {
     int32_t tile_x, tile_y; /* spreading tile edges in fine cells */
     int32_t ntiles;       /* tiles in the fine grid */
     int64_t slot_cap;     /* capacity of the binned point list (4 n_src) */
-    int32_t col_batch;    /* columns per workgroup in the first FFT pass */
+    int32_t col_batch;    /* panel width C of the fine grid and FFT intermediate (adjacent columns
+                             stored together; columns per workgroup in the first FFT pass) */
     uint32_t flags;
     /* byte offsets into the workspace of buffers tests may inspect */
     size_t off_status, off_tile_start, off_cell, off_frac, off_phase, off_perm, off_fine, off_mid;

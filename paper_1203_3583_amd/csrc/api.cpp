@@ -353,6 +353,7 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
     pl->ws = static_cast<char *>(workspace);
     char *w = pl->ws;
     pl->bin.status = reinterpret_cast<uint32_t *>(w + L.off_status);
+    pl->bin.sched = pl->bin.status + 16;   // same 256-byte segment, its own 64-byte line
     pl->bin.tile_start = reinterpret_cast<uint32_t *>(w + L.off_tile_start);
     pl->bin.cursor = reinterpret_cast<uint32_t *>(w + L.off_cursor);
     pl->bin.cell = reinterpret_cast<uint32_t *>(w + L.off_cell);
@@ -376,8 +377,8 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
     pl->geo.nfx = L.nfx;
     pl->geo.nfy = L.nfy;
     pl->geo.w = L.w;
-    pl->geo.tile_x = L.tile_x;
-    pl->geo.tile_y = L.tile_y;
+    pl->geo.log_tile_x = log2i(L.tile_x);
+    pl->geo.log_tile_y = log2i(L.tile_y);
     pl->geo.ntx = L.ntx;
     pl->geo.nty = L.nty;
     pl->geo.plane = (p->flags & ASF_INCIDENT_NONE) ? 0 : 1;
@@ -451,8 +452,8 @@ int asf_forward(asf_plan_t plan, const void *u1, void *u2, void *stream) {
     }
     {
         StageMark m(p, asf::STAGE_FFT2, s);
-        e = asf::launch_fft_pass2(p->sh2, split, p->mid, static_cast<float2 *>(u2), p->twx, p->w16,
-                                  p->dx, p->dy, p->lay.mx, p->lay.my, s);
+        e = asf::launch_fft_pass2(p->sh2, log2i(p->sh1.batch), split, p->mid, static_cast<float2 *>(u2),
+                                  p->twx, p->w16, p->dx, p->dy, p->lay.mx, p->lay.my, s);
         if (e != hipSuccess) return hip_fail(e, "fft pass 2 launch");
     }
     return ASF_OK;

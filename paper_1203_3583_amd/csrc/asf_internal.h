@@ -11,6 +11,7 @@ namespace asf {
 // Binned point list: one slot per (point, fine-grid tile its footprint touches).
 struct Binned {
     uint32_t *status;      // [1] bit 0: domain error, bit 1: bin overflow
+    uint32_t *sched;       // [2] spreading tile queue: next tile, finished workgroups (zero between launches)
     uint32_t *tile_start;  // [ntiles + 1] exclusive scan of slot counts per tile
     uint32_t *cursor;      // [ntiles] counts, then insertion cursors
     uint32_t *cell;        // [slot_cap] first footprint cell, l0x | l0y << 16
@@ -27,7 +28,7 @@ struct GeoParams {
     double p2x, p2y;
     int nfx, nfy;      // fine grid
     int w;             // spreading width (cells)
-    int tile_x, tile_y; // tile edges (cells)
+    int log_tile_x, log_tile_y; // tile edges (cells), as powers of two
     int ntx, nty;      // tiles per axis
     int plane;         // 1: u_I = exp(i k d1) (cancels the -k d1 term exactly)
 };
@@ -59,12 +60,13 @@ hipError_t launch_bin_scatter(const GeoParams &g, const Binned &b, int64_t n, co
                               const double *y, const double *d, hipStream_t s);
 hipError_t launch_spread(const SpreadParams &p, const Binned &b, const float2 *u1, float2 *fine,
                          hipStream_t s);
-// pass 1: columns of the fine grid (panel layout) -> mid[my][nfx]
+// pass 1: columns of the fine grid (panel layout) -> mid (my x nfx, same panel layout)
 hipError_t launch_fft_pass1(const FftShape &sh, int split16, const float2 *fine, float2 *mid,
                             const float2 *tw, const float2 *w16, int nfx, int my, hipStream_t s);
-// pass 2: rows of mid -> u2[my][mx] with the deconvolution and destination phase
-hipError_t launch_fft_pass2(const FftShape &sh, int split16, const float2 *mid, float2 *u2,
-                            const float2 *tw, const float2 *w16, const float2 *dx,
+// pass 2: rows of mid (panels of 2^log_panel columns) -> u2[my][mx] with the
+// deconvolution and destination phase
+hipError_t launch_fft_pass2(const FftShape &sh, int log_panel, int split16, const float2 *mid,
+                            float2 *u2, const float2 *tw, const float2 *w16, const float2 *dx,
                             const float2 *dy, int mx, int my, hipStream_t s);
 int fft_batch_pass1(int len);          // columns per workgroup in pass 1 (fine-grid panel width)
 int fft_batch_pass2(int len);          // rows per workgroup in pass 2

@@ -5,8 +5,13 @@
 // A 2D forward DFT (exp(-i) sign) of the nfx x nfy fine grid is done in two
 // passes, each pruned to the modes the destination grid keeps:
 //   pass 1: every fine-grid column (length nfy), keep the my centred modes,
-//           write mid[ky][lx] (my x nfx, row-major);
-//   pass 2: every mid row (length nfx), keep the mx centred modes, multiply by
+//           write them to mid in the fine grid's panel layout (panels of C
+//           adjacent columns, element (lx, ky) at ((lx / C) my + ky) C + lx % C),
+//           so that each workgroup writes one contiguous block;
+//   pass 2: every mid row (length nfx), gathered from the panels (C elements at
+//           a time; the 16 / C rows that share a 128-byte line run on one XCD,
+//           whose L2 serves the line to all of them), keep the mx centred
+//           modes, multiply by
 //           Dx[ix] Dy[iy] (1/psi-hat, the destination chirp of Eq. (6)/(7) and
 //           the prefactor exp(i k z0)/(i lambda z0)) and write u2[iy][ix].
 // A workgroup holds `batch` whole transforms in LDS.  Each transform of length
@@ -287,19 +292,11 @@ template <int LOGL, int BATCH, int NT, bool SPLIT>
 __global__ void __launch_bounds__(NT) fft_pass1_kernel(const float2 *__restrict__ fine,
                                                        float2 *__restrict__ mid,
                                                        const float2 *__restrict__ tw,
-                                                       const float2 *__restrict__ w16, int nfx,
-                                                       int my, int xcd_group) {
+                                                       const float2 *__restrict__ w16, int my) {
     using S = Len<LOGL>;
     extern __shared__ float2 lds[];
     __shared__ float scratch[NT / 64];
-    // panels whose output rows share 128-byte lines of mid go to one XCD
-    // (workgroups are dealt to the 8 XCDs round-robin), so the partial-line
-    // writes meet in that XCD's L2
-    int pc = blockIdx.x;
-    if (xcd_group > 1) {
-        const int xcd = pc & 7, slot = pc >> 3;
-        pc = ((slot / xcd_group) * 8 + xcd) * xcd_group + slot % xcd_group;
-    }
+    const int pc = blockIdx.x;
     const float2 *src = fine + (size_t)pc * S::L * BATCH;
     float big = 0.f;
     for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
@@ -323,11 +320,12 @@ __global__ void __launch_bounds__(NT) fft_pass1_kernel(const float2 *__restrict_
     __syncthreads();
     transform_all<LOGL, BATCH, NT, SPLIT>(lds, tw, w16);
     const int half = my >> 1;
+    float2 *dst = mid + (size_t)pc * my * BATCH;   // this panel's block of mid
     for (int t = threadIdx.x; t < my * BATCH; t += NT) {
         const int ky = t / BATCH, c = t % BATCH;
         const int l = (ky - half) & (S::L - 1);
         const float2 v = lds[c * S::STRIDE + lds_pos<S::PS>(l)];
-        mid[(size_t)ky * nfx + pc * BATCH + c] = make_float2(v.x * unscale, v.y * unscale);
+        dst[t] = make_float2(v.x * unscale, v.y * unscale);
     }
 }
 
@@ -338,16 +336,24 @@ __global__ void __launch_bounds__(NT) fft_pass2_kernel(const float2 *__restrict_
                                                        const float2 *__restrict__ tw,
                                                        const float2 *__restrict__ w16,
                                                        const float2 *__restrict__ dx,
-                                                       const float2 *__restrict__ dy, int mx) {
+                                                       const float2 *__restrict__ dy, int mx,
+                                                       int my, int log_panel, int xcd_group) {
     using S = Len<LOGL>;
     extern __shared__ float2 lds[];
     __shared__ float scratch[NT / 64];
-    const int row0 = blockIdx.x * BATCH;
-    const float2 *src = mid + (size_t)row0 * S::L;
+    // workgroups are dealt to the 8 XCDs round-robin: give the xcd_group
+    // workgroups whose rows share lines of mid consecutive slots on one XCD
+    int g = blockIdx.x;
+    if (xcd_group > 1) {
+        const int xcd = g & 7, slot = g >> 3;
+        g = ((slot / xcd_group) * 8 + xcd) * xcd_group + slot % xcd_group;
+    }
+    const int row0 = g * BATCH;
+    const int cmask = (1 << log_panel) - 1;
     float big = 0.f;
     for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
-        const float2 v = src[t];
         const int c = t >> LOGL, lx = t & (S::L - 1);
+        const float2 v = mid[((((size_t)(lx >> log_panel)) * my + row0 + c) << log_panel) + (lx & cmask)];
         lds[c * S::STRIDE + lds_pos<S::PS>(lx)] = v;
         if constexpr (SPLIT) big = fmaxf(big, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
@@ -396,24 +402,21 @@ constexpr int threads_for() {
 template <int LOGL, int BATCH, bool SPLIT>
 hipError_t launch1(const FftShape &sh, const float2 *fine, float2 *mid, const float2 *tw,
                    const float2 *w16, int nfx, int my, hipStream_t s) {
+    (void)sh;
     constexpr int NT = threads_for<LOGL, BATCH>();
     const size_t lds = (size_t)BATCH * Len<LOGL>::STRIDE * sizeof(float2);
     static thread_local size_t enabled = 0;
     auto k = fft_pass1_kernel<LOGL, BATCH, NT, SPLIT>;
     hipError_t e = allow_lds((const void *)k, lds, enabled);
     if (e != hipSuccess) return e;
-    const int groups = nfx / BATCH;
-    const int g = 16 / BATCH;   // panels per 128-byte line of a mid row
-    const int xcd_group = (g > 1 && groups % (8 * g) == 0) ? g : 1;
-    (void)sh;
-    hipLaunchKernelGGL(k, dim3(groups), dim3(NT), lds, s, fine, mid, tw, w16, nfx, my, xcd_group);
+    hipLaunchKernelGGL(k, dim3(nfx / BATCH), dim3(NT), lds, s, fine, mid, tw, w16, my);
     return hipGetLastError();
 }
 
 template <int LOGL, int BATCH, bool SPLIT>
 hipError_t launch2(const FftShape &sh, const float2 *mid, float2 *u2, const float2 *tw,
                    const float2 *w16, const float2 *dx, const float2 *dy, int mx, int my,
-                   hipStream_t s) {
+                   int log_panel, hipStream_t s) {
     constexpr int NT = threads_for<LOGL, BATCH>();
     const size_t lds = (size_t)BATCH * Len<LOGL>::STRIDE * sizeof(float2);
     static thread_local size_t enabled = 0;
@@ -421,7 +424,12 @@ hipError_t launch2(const FftShape &sh, const float2 *mid, float2 *u2, const floa
     hipError_t e = allow_lds((const void *)k, lds, enabled);
     if (e != hipSuccess) return e;
     (void)sh;
-    hipLaunchKernelGGL(k, dim3(my / BATCH), dim3(NT), lds, s, mid, u2, tw, w16, dx, dy, mx);
+    const int groups = my / BATCH;
+    const int rows_per_line = 16 >> log_panel;   // rows of mid that share a 128-byte line
+    const int g = rows_per_line > BATCH ? rows_per_line / BATCH : 1;
+    const int xcd_group = (g > 1 && groups % (8 * g) == 0) ? g : 1;
+    hipLaunchKernelGGL(k, dim3(groups), dim3(NT), lds, s, mid, u2, tw, w16, dx, dy, mx, my, log_panel,
+                       xcd_group);
     return hipGetLastError();
 }
 
@@ -447,21 +455,21 @@ hipError_t dispatch1(const FftShape &sh, const float2 *fine, float2 *mid, const 
 }
 
 template <bool SPLIT>
-hipError_t dispatch2(const FftShape &sh, const float2 *mid, float2 *u2, const float2 *tw,
+hipError_t dispatch2(const FftShape &sh, int log_panel, const float2 *mid, float2 *u2, const float2 *tw,
                      const float2 *w16, const float2 *dx, const float2 *dy, int mx, int my,
                      hipStream_t s) {
     const int log = __builtin_ctz(sh.L);
     switch (log) {
-        case 5: return launch2<5, 8, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
-        case 6: return launch2<6, 4, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
-        case 7: return launch2<7, 2, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
-        case 8: return launch2<8, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
-        case 9: return launch2<9, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
-        case 10: return launch2<10, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
-        case 11: return launch2<11, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
-        case 12: return launch2<12, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
-        case 13: return launch2<13, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
-        case 14: return launch2<14, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
+        case 5: return launch2<5, 8, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
+        case 6: return launch2<6, 4, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
+        case 7: return launch2<7, 2, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
+        case 8: return launch2<8, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
+        case 9: return launch2<9, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
+        case 10: return launch2<10, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
+        case 11: return launch2<11, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
+        case 12: return launch2<12, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
+        case 13: return launch2<13, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
+        case 14: return launch2<14, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -511,11 +519,11 @@ hipError_t launch_fft_pass1(const FftShape &sh, int split16, const float2 *fine,
     return dispatch1<false>(sh, fine, mid, tw, w16, nfx, my, s);
 }
 
-hipError_t launch_fft_pass2(const FftShape &sh, int split16, const float2 *mid, float2 *u2,
-                            const float2 *tw, const float2 *w16, const float2 *dx,
+hipError_t launch_fft_pass2(const FftShape &sh, int log_panel, int split16, const float2 *mid,
+                            float2 *u2, const float2 *tw, const float2 *w16, const float2 *dx,
                             const float2 *dy, int mx, int my, hipStream_t s) {
-    if (split16) return dispatch2<true>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
-    return dispatch2<false>(sh, mid, u2, tw, w16, dx, dy, mx, my, s);
+    if (split16) return dispatch2<true>(sh, log_panel, mid, u2, tw, w16, dx, dy, mx, my, s);
+    return dispatch2<false>(sh, log_panel, mid, u2, tw, w16, dx, dy, mx, my, s);
 }
 
 }  // namespace asf

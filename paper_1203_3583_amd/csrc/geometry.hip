@@ -7,9 +7,14 @@
 //   xi_j   = p2 x_j / (lambda r0_j)                           (cycles per destination pixel)
 // With the normal plane wave u_I = exp(i k d1) the -k d1 term and the incident
 // phase cancel exactly, so the kernel forms phi = k |x|^2 / (2 r0) directly and
-// never builds the ~1e4 rad intermediate.  phi is reduced mod 2 pi in FP64
-// before the FP64 sincos; xi is wrapped to [0, 1) (exp(-2 pi i m xi) is
-// 1-periodic in xi for integer m) and scaled to the fine grid, g = xi * nf.
+// never builds the ~1e4 rad intermediate.  The phase is formed in FP64 in
+// revolutions, phi / (2 pi) = |x|^2 s / 2 (- d / lambda without the plane
+// wave), with s = 1 / (lambda r0) the same factor the frequencies use; its
+// integer part is removed exactly in FP64 and only the remainder in
+// [-1/2, 1/2] revolutions is rounded to FP32 for sincos(pi t) (phase error
+// below 2e-7 rad, whatever the size of phi).  xi is wrapped to [0, 1)
+// (exp(-2 pi i m xi) is 1-periodic in xi for integer m) and scaled to the fine
+// grid, g = xi * nf.
 // The footprint of the spreading kernel starts at cell l0 = ceil(g - w/2); the
 // FP32 offset g - l0 - (w-1)/2 lies in (-1/2, 1/2], so its rounding error is at
 // most 2^-26 cell however large the phase was.
@@ -25,15 +30,12 @@
 namespace asf {
 namespace {
 
-constexpr double kTwoPiHi = 6.283185307179586;        // 2 pi rounded to FP64
-constexpr double kTwoPiLo = 2.4492935982947064e-16;   // 2 pi - kTwoPiHi
-
 struct PointTiles {
     int n;        // tiles touched (0 if the point is invalid)
     int key[4];   // tile indices ty * ntx + tx
     int l0x, l0y; // first footprint cell, wrapped into the fine grid
     float fx, fy; // offsets in (-1/2, 1/2]
-    double r0;
+    double s;     // 1 / (lambda r0)
 };
 
 // The counting and the scattering kernel must derive identical cells from the
@@ -49,11 +51,11 @@ __device__ inline void axis_cell(double xi, int nf, int w, int &l0, float &off) 
     l0 = c;
 }
 
-__device__ inline int axis_tiles(int l0, int nf, int w, int tile, int *t) {
+__device__ inline int axis_tiles(int l0, int nf, int w, int log_tile, int *t) {
     int last = l0 + w - 1;
     if (last >= nf) last -= nf;
-    t[0] = l0 / tile;
-    t[1] = last / tile;
+    t[0] = l0 >> log_tile;
+    t[1] = last >> log_tile;
     return t[1] != t[0] ? 2 : 1;
 }
 
@@ -63,14 +65,15 @@ __device__ inline PointTiles point_tiles(const GeoParams &g, double x, double y,
     p.n = 0;
     p.l0x = p.l0y = 0;
     p.fx = p.fy = 0.f;
-    p.r0 = g.z0 - d;
-    if (!(p.r0 > 0.0) || !isfinite(x) || !isfinite(y) || !isfinite(d)) return p;
-    const double s = g.inv_lambda / p.r0;
-    axis_cell(g.p2x * x * s, g.nfx, g.w, p.l0x, p.fx);
-    axis_cell(g.p2y * y * s, g.nfy, g.w, p.l0y, p.fy);
+    p.s = 0.0;
+    const double r0 = g.z0 - d;
+    if (!(r0 > 0.0) || !isfinite(x) || !isfinite(y) || !isfinite(d)) return p;
+    p.s = g.inv_lambda / r0;
+    axis_cell(g.p2x * x * p.s, g.nfx, g.w, p.l0x, p.fx);
+    axis_cell(g.p2y * y * p.s, g.nfy, g.w, p.l0y, p.fy);
     int tx[2], ty[2];
-    const int nx = axis_tiles(p.l0x, g.nfx, g.w, g.tile_x, tx);
-    const int ny = axis_tiles(p.l0y, g.nfy, g.w, g.tile_y, ty);
+    const int nx = axis_tiles(p.l0x, g.nfx, g.w, g.log_tile_x, tx);
+    const int ny = axis_tiles(p.l0y, g.nfy, g.w, g.log_tile_y, ty);
     for (int a = 0; a < ny; ++a)
         for (int b = 0; b < nx; ++b) p.key[p.n++] = ty[a] * g.ntx + tx[b];
     return p;
@@ -110,100 +113,160 @@ __device__ inline WaveGroup wave_group(int key, bool active) {
 __global__ void __launch_bounds__(256) bin_reset_kernel(Binned b, int ntiles) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < ntiles) b.cursor[i] = 0u;
-    if (i == 0) b.status[0] = 0u;
-}
-
-__global__ void __launch_bounds__(256) bin_count_kernel(GeoParams g, Binned b, int64_t n,
-                                                        const double *__restrict__ x,
-                                                        const double *__restrict__ y,
-                                                        const double *__restrict__ d) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    PointTiles p;
-    p.n = 0;
-    if (j < n) {
-        p = point_tiles(g, x[j], y[j], d[j]);
-        if (p.n == 0) atomicOr(b.status, 1u);
-    }
-    // one non-returning atomic per distinct tile per wave and replica
-    for (int r = 0; r < 4; ++r) {
-        const bool act = r < p.n;
-        const WaveGroup grp = wave_group(act ? p.key[r] : 0, act);
-        if (act && grp.leader == __lane_id()) atomicAdd(&b.cursor[p.key[r]], grp.size);
+    if (i == 0) {
+        b.status[0] = 0u;
+        b.sched[0] = 0u;
+        b.sched[1] = 0u;
     }
 }
 
-// Exclusive scan of the per-tile counts by one workgroup of 1024 threads.
-__global__ void __launch_bounds__(1024) bin_scan_kernel(Binned b, int ntiles) {
-    __shared__ uint32_t sums[1024];
-    const int t = threadIdx.x;
-    const int per = (ntiles + 1023) / 1024;
-    const int lo = min(t * per, ntiles), hi = min(lo + per, ntiles);
-    uint32_t s = 0;
-    for (int i = lo; i < hi; ++i) s += b.cursor[i];
-    sums[t] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = t >= off ? sums[t - off] : 0u;
-        __syncthreads();
-        sums[t] += v;
-        __syncthreads();
-    }
-    uint32_t run = t ? sums[t - 1] : 0u;
-    for (int i = lo; i < hi; ++i) {
-        const uint32_t c = b.cursor[i];
-        b.tile_start[i] = run;
-        b.cursor[i] = run;
-        run += c;
-    }
-    if (t == 1023) b.tile_start[ntiles] = sums[1023];
+constexpr int kGeoThreads = 256;
+constexpr int kGeoPoints = 4;   // points per thread, loads in flight together
+
+// point j of this thread's k-th batch: consecutive lanes take consecutive points
+__device__ inline int64_t geo_index(int k) {
+    return ((int64_t)blockIdx.x * kGeoPoints + k) * kGeoThreads + threadIdx.x;
 }
 
-__global__ void __launch_bounds__(256) bin_scatter_kernel(GeoParams g, Binned b, int64_t n,
-                                                          const double *__restrict__ x,
-                                                          const double *__restrict__ y,
-                                                          const double *__restrict__ d) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    PointTiles p;
-    p.n = 0;
-    float2 ph = make_float2(0.f, 0.f);
-    if (j < n) {
-        const double xj = x[j], yj = y[j], dj = d[j];
-        p = point_tiles(g, xj, yj, dj);
-        if (p.n > 0) {
-            double q = (xj * xj + yj * yj) / (2.0 * p.r0);
-            if (!g.plane) q -= dj;
-            const double phi = g.k * q;
-            const double nrev = rint(phi / kTwoPiHi);
-            double red = fma(-nrev, kTwoPiHi, phi);
-            red = fma(-nrev, kTwoPiLo, red);
-            double sn, cs;
-            sincos(red, &sn, &cs);
-            ph = make_float2((float)cs, (float)sn);
+__global__ void __launch_bounds__(kGeoThreads) bin_count_kernel(GeoParams g, Binned b, int64_t n,
+                                                                const double *__restrict__ x,
+                                                                const double *__restrict__ y,
+                                                                const double *__restrict__ d) {
+    double xv[kGeoPoints], yv[kGeoPoints], dv[kGeoPoints];
+#pragma unroll
+    for (int k = 0; k < kGeoPoints; ++k) {
+        const int64_t j = geo_index(k);
+        const bool in = j < n;
+        xv[k] = in ? x[j] : 0.0;
+        yv[k] = in ? y[j] : 0.0;
+        dv[k] = in ? d[j] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kGeoPoints; ++k) {
+        PointTiles p;
+        p.n = 0;
+        if (geo_index(k) < n) {
+            p = point_tiles(g, xv[k], yv[k], dv[k]);
+            if (p.n == 0) atomicOr(b.status, 1u);
+        }
+        // one non-returning atomic per distinct tile per wave and replica
+        for (int r = 0; r < 4; ++r) {
+            const bool act = r < p.n;
+            const WaveGroup grp = wave_group(act ? p.key[r] : 0, act);
+            if (act && grp.leader == __lane_id()) atomicAdd(&b.cursor[p.key[r]], grp.size);
         }
     }
-    const uint32_t cell = (uint32_t)p.l0x | ((uint32_t)p.l0y << 16);
-    // group the four replica keys first, then let the leaders reserve their
-    // groups' slots with atomics that are all in flight at once
-    WaveGroup grp[4];
+}
+
+// Exclusive scan of the per-tile counts by one workgroup of 1024 threads, in
+// chunks of 8192 tiles: each thread loads 8 consecutive counts at once, the
+// thread sums are scanned within waves by shuffles and across the 16 waves
+// through LDS, and a running carry links the chunks.
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 8;
+
+__global__ void __launch_bounds__(kScanThreads) bin_scan_kernel(Binned b, int ntiles) {
+    __shared__ uint32_t wsum[kScanThreads / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    uint32_t carry = 0;
+    for (int base = 0; base < ntiles; base += kScanThreads * kScanPer) {
+        const int lo = base + t * kScanPer;
+        uint32_t v[kScanPer];
+        uint32_t s = 0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) grp[r] = wave_group(r < p.n ? p.key[r] : 0, r < p.n);
-    uint32_t base[4];
+        for (int k = 0; k < kScanPer; ++k) {
+            v[k] = lo + k < ntiles ? b.cursor[lo + k] : 0u;
+            s += v[k];
+        }
+        uint32_t inc = s;   // inclusive scan within the wave
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        base[r] = (r < p.n && grp[r].leader == __lane_id()) ? atomicAdd(&b.cursor[p.key[r]], grp[r].size) : 0u;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t u = __shfl_up(inc, off);
+            if (lane >= off) inc += u;
+        }
+        if (lane == 63) wsum[wave] = inc;
+        __syncthreads();
+        if (wave == 0) {
+            uint32_t u = lane < kScanThreads / 64 ? wsum[lane] : 0u;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const bool act = r < p.n;
-        const int key = act ? p.key[r] : 0;
-        const uint32_t slot = __shfl(base[r], grp[r].leader) + grp[r].rank;
-        if (act) {
-            if (slot < b.tile_start[key + 1]) {
-                b.cell[slot] = cell;
-                b.frac[slot] = make_float2(p.fx, p.fy);
-                b.phase[slot] = ph;
-                b.perm[slot] = (uint32_t)j;
-            } else {
-                atomicOr(b.status, 2u);
+            for (int off = 1; off < kScanThreads / 64; off <<= 1) {
+                const uint32_t q = __shfl_up(u, off);
+                if (lane >= off) u += q;
+            }
+            if (lane < kScanThreads / 64) wsum[lane] = u;   // inclusive totals of waves 0..lane
+        }
+        __syncthreads();
+        uint32_t run = carry + (wave ? wsum[wave - 1] : 0u) + inc - s;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            if (lo + k < ntiles) {
+                b.tile_start[lo + k] = run;
+                b.cursor[lo + k] = run;
+            }
+            run += v[k];
+        }
+        carry += wsum[kScanThreads / 64 - 1];
+        __syncthreads();   // wsum is rewritten by the next chunk
+    }
+    if (t == 0) b.tile_start[ntiles] = carry;
+}
+
+__global__ void __launch_bounds__(kGeoThreads) bin_scatter_kernel(GeoParams g, Binned b, int64_t n,
+                                                                  const double *__restrict__ x,
+                                                                  const double *__restrict__ y,
+                                                                  const double *__restrict__ d) {
+    double xv[kGeoPoints], yv[kGeoPoints], dv[kGeoPoints];
+#pragma unroll
+    for (int k = 0; k < kGeoPoints; ++k) {
+        const int64_t j = geo_index(k);
+        const bool in = j < n;
+        xv[k] = in ? x[j] : 0.0;
+        yv[k] = in ? y[j] : 0.0;
+        dv[k] = in ? d[j] : 0.0;
+    }
+    PointTiles p[kGeoPoints];
+    WaveGroup grp[kGeoPoints][4];
+    uint32_t base[kGeoPoints][4];
+#pragma unroll
+    for (int k = 0; k < kGeoPoints; ++k) {
+        p[k].n = 0;
+        if (geo_index(k) < n) p[k] = point_tiles(g, xv[k], yv[k], dv[k]);
+        // group the replica keys, then let the leaders reserve their groups'
+        // slots; the atomics of all batches and replicas are in flight at once
+#pragma unroll
+        for (int r = 0; r < 4; ++r) grp[k][r] = wave_group(r < p[k].n ? p[k].key[r] : 0, r < p[k].n);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            base[k][r] = (r < p[k].n && grp[k][r].leader == __lane_id())
+                             ? atomicAdd(&b.cursor[p[k].key[r]], grp[k][r].size) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kGeoPoints; ++k) {
+        float2 ph = make_float2(0.f, 0.f);
+        if (p[k].n > 0) {
+            // phi / (2 pi) = k (|x|^2 / (2 r0) [- d]) / (2 pi) = |x|^2 s / 2 [- d / lambda]
+            double rev = 0.5 * p[k].s * (xv[k] * xv[k] + yv[k] * yv[k]);
+            if (!g.plane) rev -= dv[k] * g.inv_lambda;
+            const float t = (float)(rev - rint(rev));   // exact in FP64, then one rounding
+            float sn, cs;
+            sincospif(2.f * t, &sn, &cs);
+            ph = make_float2(cs, sn);
+        }
+        const uint32_t cell = (uint32_t)p[k].l0x | ((uint32_t)p[k].l0y << 16);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const bool act = r < p[k].n;
+            const int key = act ? p[k].key[r] : 0;
+            const uint32_t slot = __shfl(base[k][r], grp[k][r].leader) + grp[k][r].rank;
+            if (act) {
+                if (slot < b.tile_start[key + 1]) {
+                    b.cell[slot] = cell;
+                    b.frac[slot] = make_float2(p[k].fx, p[k].fy);
+                    b.phase[slot] = ph;
+                    b.perm[slot] = (uint32_t)geo_index(k);
+                } else {
+                    atomicOr(b.status, 2u);
+                }
             }
         }
     }
@@ -219,20 +282,22 @@ hipError_t launch_bin_reset(const Binned &b, int ntiles, hipStream_t s) {
 
 hipError_t launch_bin_count(const GeoParams &g, const Binned &b, int64_t n, const double *x,
                             const double *y, const double *d, hipStream_t s) {
-    const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(bin_count_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g, b, n, x, y, d);
+    const int64_t per = (int64_t)kGeoThreads * kGeoPoints;
+    const int64_t blocks = (n + per - 1) / per;
+    hipLaunchKernelGGL(bin_count_kernel, dim3((unsigned)blocks), dim3(kGeoThreads), 0, s, g, b, n, x, y, d);
     return hipGetLastError();
 }
 
 hipError_t launch_bin_scan(const Binned &b, int ntiles, hipStream_t s) {
-    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, s, b, ntiles);
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, b, ntiles);
     return hipGetLastError();
 }
 
 hipError_t launch_bin_scatter(const GeoParams &g, const Binned &b, int64_t n, const double *x,
                               const double *y, const double *d, hipStream_t s) {
-    const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g, b, n, x, y, d);
+    const int64_t per = (int64_t)kGeoThreads * kGeoPoints;
+    const int64_t blocks = (n + per - 1) / per;
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3((unsigned)blocks), dim3(kGeoThreads), 0, s, g, b, n, x, y, d);
     return hipGetLastError();
 }
 

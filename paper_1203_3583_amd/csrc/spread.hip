@@ -10,34 +10,48 @@
 // only its own cells -- every fine cell is written exactly once with plain
 // stores, no global atomics and no separate clear of the fine grid.
 //
+// Kernel values.  psi at the w cells of a footprint is a polynomial in the
+// point's cell offset f (es_poly.h, FP64 Chebyshev interpolants, within 1e-7 of
+// psi at w = 7); psi is even, so the cells i and w-1-i share the even and odd
+// parts of one polynomial: about w + 3 FMAs per pair of cells instead of an
+// exp and a sqrt per cell.
+//
 // Accumulation is in fixed point with LDS integer atomics: on gfx950 an LDS
 // float atomic add runs about one lane at a time, the integer ones at full LDS
 // rate.  A term t is made an integer by y = fma(a, k, 1.5 * 2^23): for
-// |t| <= 2^22 the float y lies in [2^23, 2^24), where floats are the integers,
+// |t| < 2^22 the float y lies in [2^23, 2^24), where floats are the integers,
 // so the FMA rounds the exact product to the nearest integer (ties to even:
 // unbiased, which matters because a bias per term would add up coherently over
 // ~1e9 terms at the lowest modes) and the bit pattern of y is
 // 0x4B400000 + round(t).  One 64-bit integer add of a constant then removes the
-// 0x4B400000 offsets.  The scale 2^e is set per tile as the largest e with
-// 2^e M <= 2^22, M = max over the tile's points of |Re u1| + |Im u1| (a bound on
-// |c_j|), so the rounding step is M 2^-22.  Two ways of holding a cell, chosen
-// per tile from K = w^2 times the largest number of footprints that start in
-// one cell (an upper bound on the terms any cell receives):
-//   packed:  if K <= 511 no cell sum can leave int32 (511 * 2^22 < 2^31), and
-//            one 64-bit word holds Re + 2^32 Im, so a single ds_add_u64 adds
-//            both parts of a term (the carry of the low half into the high
-//            half is undone exactly at unpacking);
-//   split:   otherwise (dense tiles) Re and Im are separate 64-bit sums,
-//            accumulated in two sweeps over the same LDS array.
+// 0x4B400000 offsets.  Per tile, M = max(|Re c_j|, |Im c_j|) over its points
+// bounds every term's parts, and K = w^2 times the most footprints that start
+// in one cell bounds the terms any cell receives.  Terms are scaled to below
+// 2^22 (rounding step 2^-22 M), and
+//   packed (K <= 511): no cell sum leaves int32 (511 (2^22 + 1/2) < 2^31), so one
+//            64-bit word holds Re + 2^32 Im: a single ds_add_u64 adds both parts
+//            of a term (the carry of the low half into the high half is undone
+//            exactly at unpacking);
+//   split:   denser tiles keep separate 64-bit sums of Re and Im, accumulated in
+//            two sweeps over the same LDS array.
 // Integer addition is associative, so the spread is bitwise deterministic.
 //
-// Each thread keeps the global loads of several slots in flight at once; on
-// this path the time goes to memory latency, not to the LDS atomics.
+// Bank conflicts.  A wave's 64 lanes add the same footprint offset to 64
+// different points, so lane l touches base_l + const; LDS serves a quarter wave
+// at a time, conflict-free when the 16 bases are distinct modulo 16 cells.  In
+// tiles with many records (dense regions, where whole quarter waves can hit one
+// cell) the records are counting-sorted by that residue in LDS and dealt out
+// column-wise: lane i of a quarter wave takes sorted entry i * ceil(n/16) + q,
+// so a quarter wave draws one entry from each sixteenth of the sorted list --
+// distinct residues unless a residue class is larger than n/16.  Light tiles
+// skip the sort and add from registers.  Measured on gfx950, ds_add_u64 runs at
+// ~10 lanes/clk/CU conflict-free and ~6 with random addresses.
 //
 // The fine grid is stored in panels of `panel` adjacent columns: element
 // (gx, gy) lives at ((gx / panel) * nfy + gy) * panel + gx % panel, so that the
 // first FFT pass reads a panel of columns as one contiguous block.
 #include "asf_internal.h"
+#include "es_poly.h"
 
 namespace asf {
 namespace {
@@ -45,25 +59,54 @@ namespace {
 constexpr int kTileXMax = 64;
 constexpr int kTileYMax = 32;
 constexpr int kThreads = 512;
-constexpr int kBatch = 4;   // slots per thread with loads in flight together
+constexpr int kBatch = 2;                 // records per thread held in registers
+constexpr int kChunk = 2 * kThreads;      // records sorted and dealt at a time
+constexpr int kWavesPerSimd = 6;          // three 512-thread workgroups per CU (LDS allows three)
 
-__device__ inline float es_kernel(float z, float beta_log2e) {
-    const float a = fmaxf(0.f, 1.f - z * z);
-    return __builtin_amdgcn_exp2f(beta_log2e * (__builtin_amdgcn_sqrtf(a) - 1.f));
+template <int W>
+struct TileGeom {
+    static constexpr int PAD = W - 1;
+    // LDS row pitch (cells), = 2 mod 16: the write-out reads 16 lanes as 8 rows x 2
+    // adjacent columns, which then fall in 16 distinct bank pairs
+    static constexpr int PITCH = (kTileXMax + 2 * PAD - 2 + 15) / 16 * 16 + 2;
+    static constexpr int ROWS = kTileYMax + 2 * PAD;
+    static constexpr int CELLS = PITCH * ROWS;
+};
+
+// psi at the w footprint cells for offset f in [-1/2, 1/2]
+template <int W>
+__device__ inline void es_values(float f, float (&v)[W]) {
+    constexpr int D = es_poly_degree(W);
+    const float u = f * f;
+#pragma unroll
+    for (int i = 0; i < (W + 1) / 2; ++i) {
+        float e = kEsPoly[W - 2][i][D & ~1];
+#pragma unroll
+        for (int k = (D & ~1) - 2; k >= 0; k -= 2) e = __builtin_fmaf(e, u, kEsPoly[W - 2][i][k]);
+        if (2 * i == W - 1) {
+            v[i] = e;
+        } else {
+            constexpr int DO = (D - 1) | 1;   // highest odd power
+            float o = kEsPoly[W - 2][i][DO];
+#pragma unroll
+            for (int k = DO - 2; k >= 1; k -= 2) o = __builtin_fmaf(o, u, kEsPoly[W - 2][i][k]);
+            v[i] = __builtin_fmaf(f, o, e);
+            v[W - 1 - i] = __builtin_fmaf(-f, o, e);
+        }
+    }
 }
 
 constexpr float kMagic = 12582912.f;             // 1.5 * 2^23
 constexpr unsigned kMagicBits = 0x4B400000u;      // bit pattern of kMagic
-
 constexpr unsigned long long kMagic1 = kMagicBits;
 constexpr unsigned long long kMagic2 = ((unsigned long long)kMagicBits << 32) | kMagicBits;
 
-// round(a k) as a 64-bit two's-complement integer, for |a k| <= 2^22
+// round(a k) as a 64-bit two's-complement integer, for |a k| < 2^22
 __device__ inline unsigned long long term1(float a, float k) {
     return (unsigned long long)__float_as_uint(__builtin_fmaf(a, k, kMagic)) - kMagic1;
 }
 
-// round(re) + 2^32 round(im) modulo 2^64, for |re|, |im| <= 2^22
+// round(re) + 2^32 round(im) modulo 2^64, for |re|, |im| < 2^22
 __device__ inline unsigned long long term(float ar, float ai, float k) {
     const float yr = __builtin_fmaf(ar, k, kMagic);
     const float yi = __builtin_fmaf(ai, k, kMagic);
@@ -73,17 +116,6 @@ __device__ inline unsigned long long term(float ar, float ai, float k) {
 __device__ inline void unpack2(unsigned long long v, int &re, int &im) {
     re = (int)(unsigned)(v & 0xffffffffull);
     im = (int)(unsigned)((v - (unsigned long long)(long long)re) >> 32);
-}
-
-__device__ inline float block_max(float v, float *scratch) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
-    __syncthreads();
-    float s = 0.f;
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s = fmaxf(s, scratch[i]);
-    return s;
 }
 
 // padded start position of a point in this tile, or false if it does not touch it
@@ -98,157 +130,293 @@ __device__ inline bool local_start(uint32_t cell, int x0, int y0, int pad, int h
     return px >= 0 && px <= hix && py >= 0 && py <= hiy;
 }
 
+// the records of one batch: slot base + k * nt for k < kBatch.  Until the u1
+// gather pc holds exp(i phi); after it, c = u1 exp(i phi) (unscaled).
+struct Batch {
+    uint32_t j[kBatch], cell[kBatch];
+    float2 fr[kBatch], pc[kBatch];
+};
+
+// binned record fields (the u1 gather is separate so that it can be issued later,
+// once the indices have arrived)
+__device__ inline void load_records(Batch &r, const Binned &b, uint32_t base, uint32_t s1, int nt) {
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+        const uint32_t s = base + k * nt;
+        const bool in = s < s1;
+        r.j[k] = in ? b.perm[s] : 0xffffffffu;
+        r.cell[k] = in ? b.cell[s] : 0u;
+        r.fr[k] = in ? b.frac[s] : make_float2(0.f, 0.f);
+        r.pc[k] = in ? b.phase[s] : make_float2(0.f, 0.f);
+    }
+}
+
+__device__ inline void gather_u(Batch &r, const float2 *__restrict__ u1, int64_t n) {
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+        const float2 u = r.j[k] < n ? u1[r.j[k]] : make_float2(0.f, 0.f);
+        const float2 ph = r.pc[k];
+        r.pc[k] = make_float2(u.x * ph.x - u.y * ph.y, u.x * ph.y + u.y * ph.x);
+    }
+}
+
+template <int W, int PITCH>
+__device__ inline void accumulate(unsigned long long *row, float4 d, bool packed) {
+    float kx[W], ky[W];
+    es_values<W>(d.z, kx);
+    es_values<W>(d.w, ky);
+#pragma unroll
+    for (int jy = 0; jy < W; ++jy) {
+        const float ar = d.x * ky[jy], ai = d.y * ky[jy];
+        if (packed) {
+#pragma unroll
+            for (int i = 0; i < W; ++i) atomicAdd(row + jy * PITCH + i, term(ar, ai, kx[i]));
+        } else {
+#pragma unroll
+            for (int i = 0; i < W; ++i) atomicAdd(row + jy * PITCH + i, term1(ar, kx[i]));
+        }
+    }
+}
+
+// Tiles with more records than this deal them out by start residue (see the
+// file comment); lighter tiles add their footprints straight from registers,
+// where random residues cost less than the sort.
+constexpr uint32_t kDealRecords = 1024;
+
+// Read back the tile's own cells in the order they are written out and convert
+// them to FP32.  Thread tid handles cells tid + k nt of the tile in panel order;
+// with nt a multiple of panel * tile_y each thread keeps its column offset and
+// row, and successive k step 16 columns: +16 cells in LDS, +16 nfy in the grid.
+template <int W, int PITCH>
+__device__ inline void write_tile(const unsigned long long *acc, float2 *__restrict__ fine,
+                                  const SpreadParams &p, int x0, int y0, int ncell, int nt,
+                                  bool packed, int sweep, float unscale) {
+    constexpr int PAD = W - 1;
+    const int tid = threadIdx.x;
+    const int C = 1 << p.log_panel;
+    const int c = tid & (C - 1);
+    const int rest = tid >> p.log_panel;
+    const int ly = rest & ((1 << p.log_tile_y) - 1);
+    const int lx = ((rest >> p.log_tile_y) << p.log_panel) + c;
+    const unsigned long long *src = acc + (ly + PAD) * PITCH + lx + PAD;
+    const int step = nt >> p.log_tile_y;   // columns per k
+    float2 *dst = fine + ((((size_t)((x0 + lx) >> p.log_panel) * p.nfy + y0 + ly) << p.log_panel) + c);
+    const size_t dstep = (size_t)step * p.nfy;
+    for (int k = 0; k < ncell / nt; ++k) {
+        const unsigned long long v = src[k * step];
+        float2 *d = dst + k * dstep;
+        if (packed) {
+            int sr, si;
+            unpack2(v, sr, si);
+            *d = make_float2((float)sr * unscale, (float)si * unscale);
+        } else {
+            // split tiles: sweep 0 writes the real part, sweep 1 the imaginary part
+            reinterpret_cast<float *>(d)[sweep] = (float)(long long)v * unscale;
+        }
+    }
+}
+
 template <int W>
-__global__ void __launch_bounds__(kThreads) spread_kernel(SpreadParams p, Binned b,
+__global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadParams p, Binned b,
                                                           const float2 *__restrict__ u1,
                                                           float2 *__restrict__ fine) {
-    constexpr int PAD = W - 1;
-    constexpr int CELLS = (kTileXMax + 2 * PAD) * (kTileYMax + 2 * PAD);
-    constexpr int STARTS = (kTileXMax + PAD) * (kTileYMax + PAD);
-    constexpr int B = kBatch;
-    __shared__ unsigned long long acc[CELLS];
-    __shared__ int starts[STARTS];                 // footprint starts per padded cell
-    __shared__ float scratch[kThreads / 64];
+    using G = TileGeom<W>;
+    constexpr int PAD = G::PAD;
+    constexpr int PITCH = G::PITCH;
+    constexpr int SWMAX = (kTileXMax + PAD) * (kTileYMax + PAD);
+    constexpr int SDAT = (kChunk + 16) > (SWMAX + 3) / 4 ? (kChunk + 16) : (SWMAX + 3) / 4;
+    __shared__ __align__(16) unsigned long long acc[G::CELLS];
+    __shared__ __align__(16) float4 sdat[SDAT];          // dealt records (Re c, Im c, fx, fy)
+    __shared__ int sbase[kChunk + 16];                   // their padded start cell
+    __shared__ unsigned rcount[16];                      // records per start residue
+    __shared__ float red[2][kThreads / 64];
+    int *starts = reinterpret_cast<int *>(sdat);         // footprint-start histogram (phase A)
 
     const int t = blockIdx.x;
-    const int ty = t >> p.log_ntx, tx = t & ((1 << p.log_ntx) - 1);
     const int tsx = 1 << p.log_tile_x, tsy = 1 << p.log_tile_y;
-    const int x0 = tx << p.log_tile_x, y0 = ty << p.log_tile_y;
-    const int pwx = tsx + 2 * PAD, pwy = tsy + 2 * PAD;   // padded tile; pwx = LDS row stride
-    const int swx = tsx + PAD, swy = tsy + PAD;           // start positions per axis
+    const int ext_x = tsx + 2 * PAD, ext_y = tsy + 2 * PAD;   // padded tile extent
+    const int swx = tsx + PAD, swy = tsy + PAD;               // start positions per axis
     const int hix = swx - 1, hiy = swy - 1;
-    const int nt = blockDim.x;
-    for (int i = threadIdx.x; i < pwx * pwy; i += nt) acc[i] = 0ull;
-    for (int i = threadIdx.x; i < swx * swy; i += nt) starts[i] = 0;
+    const int nt = blockDim.x, tid = threadIdx.x, lane = tid & 63;
+    const bool fold_x = p.nfx < ext_x, fold_y = p.nfy < ext_y;
+    const int ncell = tsx * tsy;
+    const uint32_t per_batch = (uint32_t)(kBatch * nt);
+    const int ty = t >> p.log_ntx, tx = t & ((1 << p.log_ntx) - 1);
+    const int x0 = tx << p.log_tile_x, y0 = ty << p.log_tile_y;
+    {
+        uint4 *a4 = reinterpret_cast<uint4 *>(acc);
+        for (int i = tid; i < G::CELLS / 2; i += nt) a4[i] = make_uint4(0u, 0u, 0u, 0u);
+        for (int i = tid; i < swx * swy; i += nt) starts[i] = 0;
+        if (tid < 16) rcount[tid] = 0u;
+    }
+    const uint32_t s0 = b.tile_start[t], s1 = b.tile_start[t + 1];
+    const bool reload = s1 - s0 > per_batch;
+    const bool deal = s1 - s0 > kDealRecords;
+    Batch r;
+    int rb[kBatch];   // padded start cell of each record, -1 if it does not touch the tile
     __syncthreads();
 
-    // pass 1: largest |Re u1| + |Im u1| and the count of footprint starts per
-    // position; B slots per thread have their loads in flight together
-    const uint32_t s0 = b.tile_start[t], s1 = b.tile_start[t + 1];
+    // phase A: largest |Re c| or |Im c| and the count of footprint starts per
+    // position.  A tile of at most kBatch * nt records keeps them in registers
+    // for phase B; larger tiles reload them there.
     float big = 0.f;
-    for (uint32_t base = s0 + threadIdx.x; base < s1; base += B * nt) {
-        uint32_t j[B], cell[B];
+    for (uint32_t base = s0; base < s1; base += per_batch) {
+        load_records(r, b, base + tid, s1, nt);
+        gather_u(r, u1, p.n);
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-            const uint32_t s = base + k * nt;
-            const bool in = s < s1;
-            j[k] = in ? b.perm[s] : 0xffffffffu;
-            cell[k] = in ? b.cell[s] : 0u;
-        }
-        float2 u[B];
-#pragma unroll
-        for (int k = 0; k < B; ++k) u[k] = j[k] < p.n ? u1[j[k]] : make_float2(0.f, 0.f);
-#pragma unroll
-        for (int k = 0; k < B; ++k) {
+        for (int k = 0; k < kBatch; ++k) {
             int px, py;
-            if (j[k] < p.n && local_start(cell[k], x0, y0, PAD, hix, hiy, p.nfx, p.nfy, px, py)) {
-                big = fmaxf(big, fabsf(u[k].x) + fabsf(u[k].y));
+            rb[k] = -1;
+            if (r.j[k] < p.n && local_start(r.cell[k], x0, y0, PAD, hix, hiy, p.nfx, p.nfy, px, py)) {
+                rb[k] = py * PITCH + px;
+                big = fmaxf(big, fmaxf(fabsf(r.pc[k].x), fabsf(r.pc[k].y)));
                 atomicAdd(&starts[py * swx + px], 1);
             }
         }
     }
-    big = block_max(big, scratch);   // contains a barrier: starts[] is complete
-    int most = 0;                    // most footprint starts in one cell
-    for (int i = threadIdx.x; i < swx * swy; i += nt) most = max(most, starts[i]);
-    const float kbound = (float)(W * W) * block_max((float)most, scratch);
+    __syncthreads();               // starts[] complete
+    int most = 0;                  // most footprint starts in one cell
+    for (int i = tid; i < swx * swy; i += nt) most = max(most, starts[i]);
+    float mostf = (float)most;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        big = fmaxf(big, __shfl_xor(big, off));
+        mostf = fmaxf(mostf, __shfl_xor(mostf, off));
+    }
+    if (lane == 0) {
+        red[0][tid >> 6] = big;
+        red[1][tid >> 6] = mostf;
+    }
+    __syncthreads();
+    big = 0.f;
+    mostf = 0.f;
+    for (int i = 0; i < nt / 64; ++i) {
+        big = fmaxf(big, red[0][i]);
+        mostf = fmaxf(mostf, red[1][i]);
+    }
+    const bool packed = mostf * (float)(W * W) <= 511.f;   // 511 (2^22 + 1/2) < 2^31
     int e = 0;
     if (big > 0.f) {
         int em;
-        frexpf(big, &em);                   // big <= 2^em
-        e = 22 - em;
+        frexpf(big * (1.f + 0x1p-18f), &em);   // margin for rounding in c and psi
+        e = 22 - em;                            // terms bounded by 2^22
     }
-    const bool packed = kbound <= 511.f;
     e = max(-120, min(e, 120));
     const float scale = ldexpf(1.f, e);
-    const double unscale = ldexp(1.0, -e);
+    const float unscale = ldexpf(1.f, -e);
 
-    // pass 2: accumulate every footprint.  Packed tiles need one sweep; split
-    // (dense) tiles sweep twice over one 64-bit array, Re first, then Im.
-    constexpr float kz = 2.f / (float)W;
-    constexpr float half = 0.5f * (float)(W - 1);
-    const bool fold_x = p.nfx < pwx, fold_y = p.nfy < pwy;
-    const int C = 1 << p.log_panel;
-    const int ncell = tsx * tsy;
+    // phase B: accumulate every footprint (split tiles: two sweeps, Re then Im)
     const int sweeps = packed ? 1 : 2;
     for (int sweep = 0; sweep < sweeps; ++sweep) {
-        for (uint32_t base = s0 + threadIdx.x; base < s1; base += B * nt) {
-            uint32_t j[B], cell[B];
-            float2 fr[B], ph[B];
+        for (uint32_t bb = s0; bb < s1; bb += per_batch) {
+            if (reload) {
+                load_records(r, b, bb + tid, s1, nt);
+                gather_u(r, u1, p.n);
 #pragma unroll
-            for (int k = 0; k < B; ++k) {
-                const uint32_t s = base + k * nt;
-                const bool in = s < s1;
-                j[k] = in ? b.perm[s] : 0xffffffffu;
-                cell[k] = in ? b.cell[s] : 0u;
-                fr[k] = in ? b.frac[s] : make_float2(0.f, 0.f);
-                ph[k] = in ? b.phase[s] : make_float2(0.f, 0.f);
-            }
-            float2 u[B];
-#pragma unroll
-            for (int k = 0; k < B; ++k) u[k] = j[k] < p.n ? u1[j[k]] : make_float2(0.f, 0.f);
-#pragma unroll
-            for (int k = 0; k < B; ++k) {
-                int px, py;
-                if (!(j[k] < p.n && local_start(cell[k], x0, y0, PAD, hix, hiy, p.nfx, p.nfy, px, py))) continue;
-                const float cr = (u[k].x * ph[k].x - u[k].y * ph[k].y) * scale;
-                const float ci = (u[k].x * ph[k].y + u[k].y * ph[k].x) * scale;
-                // split sweep 0 adds Re, sweep 1 adds Im, each into the low half
-                const float c0 = packed ? cr : (sweep == 0 ? cr : ci);
-                float kx[W];
-#pragma unroll
-                for (int i = 0; i < W; ++i) kx[i] = es_kernel(((float)i - half - fr[k].x) * kz, p.beta_log2e);
-                unsigned long long *row = acc + py * pwx + px;
-#pragma unroll
-                for (int jy = 0; jy < W; ++jy) {
-                    const float ky = es_kernel(((float)jy - half - fr[k].y) * kz, p.beta_log2e);
-                    const float ar = c0 * ky, ai = ci * ky;
-                    if (packed) {
-#pragma unroll
-                        for (int i = 0; i < W; ++i) atomicAdd(row + jy * pwx + i, term(ar, ai, kx[i]));
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < W; ++i) atomicAdd(row + jy * pwx + i, term1(ar, kx[i]));
-                    }
+                for (int k = 0; k < kBatch; ++k) {
+                    int px, py;
+                    rb[k] = (r.j[k] < p.n && local_start(r.cell[k], x0, y0, PAD, hix, hiy, p.nfx, p.nfy, px, py))
+                                ? py * PITCH + px : -1;
                 }
+            }
+            if (!deal) {
+#pragma unroll
+                for (int k = 0; k < kBatch; ++k) {
+                    if (rb[k] < 0) continue;
+                    const float cr = r.pc[k].x * scale, ci = r.pc[k].y * scale;
+                    // split sweep 0 adds Re, sweep 1 adds Im, each alone
+                    const float c0 = packed ? cr : (sweep == 0 ? cr : ci);
+                    accumulate<W, PITCH>(acc + rb[k], make_float4(c0, ci, r.fr[k].x, r.fr[k].y), packed);
+                }
+                continue;
+            }
+#pragma unroll
+            for (int h = 0; h < kBatch / 2; ++h) {
+                if (bb + (uint32_t)(h * 2 * nt) >= s1) break;   // uniform over the block
+                // sort this chunk's records by start residue: rank within class
+                float4 rec[2];
+                int rres[2];
+                unsigned rrank[2];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int k = 2 * h + q;
+                    const float cr = r.pc[k].x * scale, ci = r.pc[k].y * scale;
+                    const float c0 = packed ? cr : (sweep == 0 ? cr : ci);
+                    rec[q] = make_float4(c0, ci, r.fr[k].x, r.fr[k].y);
+                    rres[q] = rb[k] & 15;
+                    rrank[q] = rb[k] >= 0 ? atomicAdd(&rcount[rres[q]], 1u) : 0u;
+                }
+                __syncthreads();   // residue counts complete
+                // exclusive prefix of the 16 counts, held by lanes 0..15 of every wave
+                const unsigned cnt = lane < 16 ? rcount[lane] : 0u;
+                unsigned inc = cnt;
+#pragma unroll
+                for (int off = 1; off < 16; off <<= 1) {
+                    const unsigned v = __shfl_up(inc, off);
+                    if (lane >= off) inc += v;
+                }
+                const unsigned total = __shfl(inc, 15);
+                const unsigned excl = inc - cnt;
+                const unsigned n16 = (total + 15u) >> 4;
+                const float inv16 = n16 ? 1.f / (float)n16 : 0.f;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    // sorted position, then the column-wise deal: position srt goes
+                    // to slot (srt mod n16) * 16 + srt / n16 (the quotient is exact:
+                    // the float estimate of (srt + 1/2) / n16 is >= 1/128 from an
+                    // integer)
+                    const unsigned srt = rrank[q] + __shfl(excl, rres[q]);
+                    if (rb[2 * h + q] < 0) continue;
+                    const unsigned quo = (unsigned)(((float)srt + 0.5f) * inv16);
+                    const unsigned slot = (srt - quo * n16) * 16u + quo;
+                    sdat[slot] = rec[q];
+                    sbase[slot] = rb[2 * h + q];
+                }
+                __syncthreads();   // records dealt; counts read by everyone
+                if (tid < 16) rcount[tid] = 0u;
+#pragma unroll 1
+                for (int q = 0; q < 2; ++q) {
+                    const unsigned s = (unsigned)(tid + q * nt);
+                    if ((s >> 4) >= n16 || (s & 15u) * n16 + (s >> 4) >= total) continue;
+                    accumulate<W, PITCH>(acc + sbase[s], sdat[s], packed);
+                }
+                __syncthreads();   // staging reused by the next chunk
             }
         }
         __syncthreads();
 
-        // read back the tile's own cells (in the order they are written out);
-        // on axes where the whole grid is narrower than the padded tile, fold
-        // the wrapped halo back in
-        for (int i = threadIdx.x; i < ncell; i += nt) {
-            const int c = i & (C - 1);
-            const int rest = i >> p.log_panel;
-            const int ly = rest & (tsy - 1);
-            const int q = rest >> p.log_tile_y;
-            const int lx = (q << p.log_panel) + c;
-            unsigned long long v = 0ull;
-            if (!fold_x && !fold_y) {
-                v = acc[(ly + PAD) * pwx + lx + PAD];
-            } else {
-                for (int oy = ly + PAD - 2 * p.nfy; oy < pwy; oy += p.nfy) {
+        if (!fold_x && !fold_y) {
+            write_tile<W, PITCH>(acc, fine, p, x0, y0, ncell, nt, packed, sweep, unscale);
+        } else {
+            // grids narrower than the padded tile: fold the wrapped halo back in
+            const int C = 1 << p.log_panel;
+            for (int i = tid; i < ncell; i += nt) {
+                const int c = i & (C - 1);
+                const int rest = i >> p.log_panel;
+                const int ly = rest & (tsy - 1);
+                const int lx = ((rest >> p.log_tile_y) << p.log_panel) + c;
+                unsigned long long v = 0ull;
+                for (int oy = ly + PAD - 2 * p.nfy; oy < ext_y; oy += p.nfy) {
                     if (oy < 0 || (!fold_y && oy != ly + PAD)) continue;
-                    for (int ox = lx + PAD - 2 * p.nfx; ox < pwx; ox += p.nfx) {
+                    for (int ox = lx + PAD - 2 * p.nfx; ox < ext_x; ox += p.nfx) {
                         if (ox < 0 || (!fold_x && ox != lx + PAD)) continue;
-                        v += acc[oy * pwx + ox];
+                        v += acc[oy * PITCH + ox];
                     }
                 }
-            }
-            const int gx = x0 + lx, gy = y0 + ly;
-            float2 *dst = fine + ((((size_t)(gx >> p.log_panel) * p.nfy + gy) << p.log_panel) + c);
-            if (packed) {
-                int sr, si;
-                unpack2(v, sr, si);
-                *dst = make_float2((float)((double)sr * unscale), (float)((double)si * unscale));
-            } else {
-                // split tiles: sweep 0 writes the real part, sweep 1 the imaginary part
-                reinterpret_cast<float *>(dst)[sweep] = (float)((double)(long long)v * unscale);
+                float2 *dst = fine + ((((size_t)((x0 + lx) >> p.log_panel) * p.nfy + y0 + ly) << p.log_panel) + c);
+                if (packed) {
+                    int sr, si;
+                    unpack2(v, sr, si);
+                    *dst = make_float2((float)sr * unscale, (float)si * unscale);
+                } else {
+                    reinterpret_cast<float *>(dst)[sweep] = (float)(long long)v * unscale;
+                }
             }
         }
         if (sweep + 1 < sweeps) {
             __syncthreads();
-            for (int i = threadIdx.x; i < pwx * pwy; i += nt) acc[i] = 0ull;
+            uint4 *a4 = reinterpret_cast<uint4 *>(acc);
+            for (int i = tid; i < G::CELLS / 2; i += nt) a4[i] = make_uint4(0u, 0u, 0u, 0u);
             __syncthreads();
         }
     }
@@ -267,6 +435,7 @@ hipError_t launch_w(const SpreadParams &p, const Binned &b, const float2 *u1, fl
 hipError_t launch_spread(const SpreadParams &p, const Binned &b, const float2 *u1, float2 *fine,
                          hipStream_t s) {
     if ((1 << p.log_tile_x) > kTileXMax || (1 << p.log_tile_y) > kTileYMax) return hipErrorInvalidValue;
+    if ((1 << p.log_tile_x) % 16 != 0) return hipErrorInvalidValue;   // start residues need 16 | tile_x
     switch (p.w) {
         case 2: return launch_w<2>(p, b, u1, fine, s);
         case 3: return launch_w<3>(p, b, u1, fine, s);
