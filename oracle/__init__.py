@@ -10,6 +10,10 @@ and the normal plane-wave incidence u_I = exp(i k d1) -- as the plain FP64 direc
 sum over source points, one sincos per term, at any set of destination pixels.
 It is written in C (``asf_oracle.c``) and parallel over pixels with OpenMP.
 
+``adjoint`` evaluates the adjoint of that linear map, g1 = A^H g2, the same
+way (one sincos per term, parallel over source points): the backward of the
+forward with respect to u1.
+
 ``mp_direct`` is the same definition at 50 significant digits with mpmath, for
 tiny inputs only: it checks the FP64 rounding of ``direct``, not its formula.
 The formula itself is pinned by the tests in ``tests/test_oracle_pins.py``
@@ -58,6 +62,12 @@ def load_library(path: str):
         ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+    lib.asf_oracle_adjoint.restype = ctypes.c_int
+    lib.asf_oracle_adjoint.argtypes = [
+        ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
     lib.asf_oracle_threads.restype = ctypes.c_int
     lib.asf_oracle_threads.argtypes = [ctypes.c_int32]
     return lib
@@ -118,6 +128,34 @@ def direct_grid(x, y, d, u, lam, z0, p2x, p2y, mx, my, ix_range=None, iy_range=N
     vals = direct(x, y, d, u, lam, z0, p2x, p2y, mx, my, gx.reshape(-1), gy.reshape(-1),
                   incident, nthreads, lib)
     return vals.reshape(len(iys), len(ixs))
+
+
+def adjoint(x, y, d, g2, lam, z0, p2x, p2y, jidx=None, incident="plane", nthreads=0, lib=None):
+    """g1 = A^H g2 at source points jidx (default: all), by the direct FP64 sum.
+
+    A is the linear map u1 -> u2 that ``direct`` evaluates; g2: complex [my, mx]
+    (row-major, complex64 promoted exactly).  Returns complex128 [len(jidx)].
+    """
+    lib = _load() if lib is None else lib
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    g2 = np.ascontiguousarray(g2, dtype=np.complex128)
+    if g2.ndim != 2:
+        raise ValueError("g2 must be [my, mx]")
+    my, mx = g2.shape
+    n = x.shape[0]
+    if not (y.shape[0] == n and d.shape[0] == n):
+        raise ValueError("x, y, d must have equal length")
+    jidx = np.arange(n, dtype=np.int64) if jidx is None else np.ascontiguousarray(jidx, dtype=np.int64).reshape(-1)
+    out = np.empty(2 * jidx.shape[0], dtype=np.float64)
+    rc = lib.asf_oracle_adjoint(
+        n, x.ctypes.data, y.ctypes.data, d.ctypes.data, float(lam), float(z0), float(p2x),
+        float(p2y), int(mx), int(my), INCIDENT[incident], g2.ctypes.data, jidx.shape[0],
+        jidx.ctypes.data, out.ctypes.data, int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle: invalid arguments or r0 = z0 - d1 <= 0")
+    return out.view(np.complex128)
 
 
 def mp_direct(x, y, d, u, lam, z0, p2x, p2y, mx, my, ix, iy, incident="plane", dps=50):

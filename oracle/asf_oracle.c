@@ -95,3 +95,62 @@ int asf_oracle_direct(int64_t n, const double *x, const double *y, const double 
     }
     return 0;
 }
+
+/*
+ * The adjoint of the same linear map, u1 -> u2 above: for source point j
+ *
+ *   g1_j = sum over pixels (ix, iy) of conj(A(ix, iy; j)) g2(ix, iy),
+ *
+ * where A(ix, iy; j) is the coefficient that multiplies u_j in u2(X, Y):
+ * the prefactor 1/(i lambda z0), exp(i k (z0 + (X^2 + Y^2)/(2 z0))) and the
+ * term's own phase.  The conjugate is formed as exp(-i (sum of the phases)) times
+ * i/(lambda z0), one sincos per term.
+ *
+ * g2         FP64 [2 mx my]: complex destination field, interleaved, row-major (iy, ix)
+ * n_eval     number of source points to evaluate
+ * jidx       int64 [n_eval]: their indices into x, y, d
+ * out        FP64 [2 n_eval]: complex g1 at those points, interleaved
+ * Other arguments as for asf_oracle_direct.  Parallel over points.
+ */
+int asf_oracle_adjoint(int64_t n, const double *x, const double *y, const double *d,
+                       double lambda, double z0, double p2x, double p2y, int32_t mx, int32_t my,
+                       int32_t incident, const double *g2, int64_t n_eval, const int64_t *jidx,
+                       double *out, int32_t threads)
+{
+    if (n < 0 || n_eval < 0 || !(lambda > 0.0) || !(z0 > 0.0) || mx < 0 || my < 0) return -1;
+    for (int64_t e = 0; e < n_eval; ++e)
+        if (jidx[e] < 0 || jidx[e] >= n || !(z0 - d[jidx[e]] > 0.0)) return -1;
+
+    const double pi = 3.14159265358979323846;
+    const double k = 2.0 * pi / lambda;
+    const double a = 1.0 / (lambda * z0);
+    const int nthr = asf_oracle_threads(threads);
+
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
+    for (int64_t e = 0; e < n_eval; ++e) {
+        const int64_t j = jidx[e];
+        const double r0 = z0 - d[j];
+        double sr = 0.0, si = 0.0;
+        for (int32_t iy = 0; iy < my; ++iy) {
+            const double Y = p2y * (double)(iy - my / 2);
+            for (int32_t ix = 0; ix < mx; ++ix) {
+                const double X = p2x * (double)(ix - mx / 2);
+                double arg = k * (-d[j] + (x[j] * x[j] + y[j] * y[j]) / (2.0 * r0)
+                                  - (x[j] * X + y[j] * Y) / r0);
+                if (incident == ORACLE_INCIDENT_PLANE) arg += k * d[j];
+                arg += k * (z0 + (X * X + Y * Y) / (2.0 * z0));
+                double s, c;
+                sincos(arg, &s, &c);
+                /* conj(exp(i arg)) g2 = (c - i s)(gr + i gi) */
+                const double gr = g2[2 * ((int64_t)iy * mx + ix)];
+                const double gi = g2[2 * ((int64_t)iy * mx + ix) + 1];
+                sr += c * gr + s * gi;
+                si += c * gi - s * gr;
+            }
+        }
+        /* conj(1 / (i lambda z0)) = i / (lambda z0) */
+        out[2 * e] = -a * si;
+        out[2 * e + 1] = a * sr;
+    }
+    return 0;
+}

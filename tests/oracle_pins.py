@@ -18,7 +18,12 @@ re-typing the oracle's formula, and returns (error, bound):
 * ``separable``: column-only x jitter and row-only y jitter make the sum a
   product of two dense matrices;
 * ``plane_identity``: u_I = exp(i k d1) equals folding exp(i k d1) into u1;
-* ``single_point``: |u2| = |u1| / (lambda z0) everywhere.
+* ``single_point``: |u2| = |u1| / (lambda z0) everywhere;
+* ``adjoint_dot_*``: <A u, g> = <u, A^H g> for random u, g, against the
+  (independently pinned) forward -- true for the adjoint and no other map;
+* ``adjoint_centred_dft``: on the centred-DFT geometry A = P F C with diagonal
+  pre- and post-phases, so A^H g = conj(C) F^H (conj(P) g) with F^H the
+  unnormalised inverse DFT (numpy.fft).
 
 Every function takes an optional ``lib`` (an oracle variant) so that
 ``test_planted_mistakes`` can show each planted error fails some pin.
@@ -207,6 +212,47 @@ def single_point(lib=None):
     return float(np.max(np.abs(np.abs(got) - want)) / want), 1e-12
 
 
+def adjoint_dot(incident, lib=None):
+    w = synth.config("sinusoid_128", side=10, out=8)
+    rng = np.random.default_rng(11)
+    errs = []
+    ix, iy = np.meshgrid(np.arange(w.mx), np.arange(w.my))
+    for _ in range(3):
+        u = rng.standard_normal(w.n) + 1j * rng.standard_normal(w.n)
+        g = rng.standard_normal((w.my, w.mx)) + 1j * rng.standard_normal((w.my, w.mx))
+        au = oracle.direct(w.x, w.y, w.d, u, w.lam, w.z0, w.p2x, w.p2y, w.mx, w.my,
+                           ix.reshape(-1), iy.reshape(-1), incident, lib=lib)
+        ahg = oracle.adjoint(w.x, w.y, w.d, g, w.lam, w.z0, w.p2x, w.p2y, incident=incident, lib=lib)
+        lhs = np.vdot(g.reshape(-1), au)
+        rhs = np.vdot(ahg, u)
+        errs.append(abs(lhs - rhs) / (np.linalg.norm(au) * np.linalg.norm(g)))
+    # phases ~ k z0 ~ 1.2e6 rad are formed in two different groupings: ~1e-10 each
+    return max(errs), 1e-9
+
+
+def adjoint_centred_dft(incident, lib=None):
+    lam, z0, c = 532e-9, 0.1, 15e-6
+    nx, ny, p1x, p1y = 16, 12, 8e-6, 6e-6
+    r0 = z0 - c
+    p2x, p2y = lam * r0 / (nx * p1x), lam * r0 / (ny * p1y)
+    X1, Y1 = np.meshgrid(p1x * (np.arange(nx) - nx // 2), p1y * (np.arange(ny) - ny // 2))
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))
+    got = oracle.adjoint(X1.reshape(-1), Y1.reshape(-1), np.full(nx * ny, c), g, lam, z0, p2x, p2y,
+                         incident=incident, lib=lib).reshape(ny, nx)
+    k = 2 * np.pi / lam
+    pre = np.exp(1j * k * (-c + (X1 ** 2 + Y1 ** 2) / (2 * r0)))
+    if incident == "plane":
+        pre = pre * np.exp(1j * k * c)
+    X, Y = dest_xy(nx, ny, p2x, p2y)
+    post = (np.exp(1j * k * (z0 + (X ** 2 + Y ** 2) / (2 * z0))) / (1j * lam * z0)).reshape(ny, nx)
+    h = np.conj(post) * g
+    t = np.fft.fftshift(np.fft.ifft2(np.fft.ifftshift(h))) * (nx * ny)
+    # the oracle adds k z0 ~ 1.2e6 rad into each term's argument before sincos (FP64
+    # ulp there ~ 2e-10 rad); the reference rounds it separately
+    return rel_l2(got, np.conj(pre) * t), 5e-10
+
+
 PINS = {
     "centred_dft_flat_none": lambda lib=None: centred_dft(0.0, "none", lib),
     "centred_dft_raised_none": lambda lib=None: centred_dft(20e-6, "none", lib),
@@ -218,4 +264,8 @@ PINS = {
     "separable": separable,
     "plane_identity": plane_identity,
     "single_point": single_point,
+    "adjoint_dot_plane": lambda lib=None: adjoint_dot("plane", lib),
+    "adjoint_dot_none": lambda lib=None: adjoint_dot("none", lib),
+    "adjoint_centred_dft_plane": lambda lib=None: adjoint_centred_dft("plane", lib),
+    "adjoint_centred_dft_none": lambda lib=None: adjoint_centred_dft("none", lib),
 }

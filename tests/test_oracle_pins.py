@@ -82,6 +82,12 @@ MUTANTS = {
     "centre_off_by_one": ("(double)(ix[e] - mx / 2)", "(double)(ix[e] - (mx - 1) / 2)"),
     "incident_sign": ("arg += k * d[j];", "arg -= k * d[j];"),
     "prefactor_lambda": ("1.0 / (lambda * z0)", "1.0 / (lambda * 0.1)"),
+    # mistakes in the adjoint alone
+    "adjoint_not_conjugated": ("sr += c * gr + s * gi;", "sr += c * gr - s * gi;"),
+    "adjoint_prefactor_sign": ("out[2 * e] = -a * si;", "out[2 * e] = a * si;"),
+    "adjoint_dropped_output_chirp": ("arg += k * (z0 + (X * X + Y * Y) / (2.0 * z0));", "arg += k * z0;"),
+    "adjoint_centre_off_by_one": ("(double)(ix - mx / 2)", "(double)(ix - (mx - 1) / 2)"),
+    "adjoint_swapped_axes": ("double)(iy - my / 2)", "double)(iy - mx / 2)"),
 }
 
 
