@@ -146,10 +146,23 @@ int asf_status(asf_plan_t plan, void *stream);
  */
 int asf_forward(asf_plan_t plan, const void *u1, void *u2, void *stream);
 
+
 /*
- * Adjoint transform g1 = A^H g2 (type-2 interpolation), for gradients.
- *   g2  complex64 [my][mx] device array; g1 complex64 [n_src] device array.
- * Not implemented yet: returns ASF_ENOSYS.
+ * Adjoint transform g1 = A^H g2 of the forward's linear map u1 -> u2: for each
+ * source point j, g1_j = sum over pixels of conj(A(pixel; j)) g2(pixel), the
+ * conjugate of Eq. (7)'s coefficient of u1_j (Sec. 2).  This is the backward of
+ * the forward with respect to u1 (PyTorch's convention for complex gradients:
+ * the gradient of u1 is A^H times the gradient of u2).  Computed as the type-2
+ * (uniform to non-uniform) NUFFT: g2 times conj(Dx Dy) (the conjugate post-phase
+ * over the kernel's Fourier transform), zero-padded to the fine grid, the
+ * unnormalised exp(+i) DFT (rows, then columns; FP32 or split-FP16 as the plan's
+ * flags say), interpolation with the same kernel at every point (no atomics),
+ * times the conjugate pre-phase exp(-i phi_j).
+ *   g2  complex64 [my][mx] device array, row-major (the forward's u2 layout)
+ *   g1  complex64 [n_src] device array, aligned with the plan's x1, y1, d1
+ * Uses the plan's workspace (do not run a forward and an adjoint of one plan
+ * concurrently).  Asynchronous on `stream`; never synchronises.
+ * Returns ASF_OK, ASF_EINVAL or ASF_EHIP.
  */
 int asf_adjoint(asf_plan_t plan, const void *g2, void *g1, void *stream);
 
@@ -158,11 +171,13 @@ int asf_plan_info(asf_plan_t plan, asf_info *info);
 
 /*
  * Per-stage timing with HIP events recorded on the forward's stream.
- * asf_set_timing(plan, 1) makes later asf_setpts/asf_forward calls record an
- * event pair around each stage; asf_stage_times synchronises on the last pair
- * and writes up to n durations (ms, host array) in the order
- * [count, scan, scatter, spread, fft_pass1, fft_pass2], returning how many it
- * wrote (negative on error).  Timing adds a few microseconds per stage.
+ * asf_set_timing(plan, 1) makes later asf_setpts/asf_forward/asf_adjoint calls
+ * record an event pair around each stage; asf_stage_times synchronises on the
+ * last pair and writes up to n durations (ms, host array) in the order
+ * [count, scan, scatter, spread, fft_pass1, fft_pass2, adj_fft_pass2,
+ * adj_fft_pass1, interp], returning how many it wrote (negative on error); a
+ * stage not run since timing was enabled reads -1.  Timing adds a few
+ * microseconds per stage.
  */
 int asf_set_timing(asf_plan_t plan, int enable);
 int asf_stage_times(asf_plan_t plan, double *ms, int n);

@@ -24,7 +24,8 @@ ASF_FFT_FP32 = 0
 ASF_FFT_SPLIT_FP16 = 1
 ASF_INCIDENT_NONE = 2
 
-STAGES = ("count", "scan", "scatter", "spread", "fft_pass1", "fft_pass2")
+STAGES = ("count", "scan", "scatter", "spread", "fft_pass1", "fft_pass2",
+          "adj_fft_pass2", "adj_fft_pass1", "interp")
 
 _CODES = {ASF_EINVAL: "EINVAL", ASF_EDOMAIN: "EDOMAIN", ASF_ENOMEM: "ENOMEM", ASF_EHIP: "EHIP",
           ASF_ESIZE: "ESIZE", ASF_ENOSYS: "ENOSYS"}
@@ -195,9 +196,17 @@ class Plan:
         return out
 
     def adjoint(self, g2, out=None, stream=None):
+        """g1 = A^H g2 (complex64 [n]) from g2 (complex64 [my, mx]) on the GPU, asynchronously."""
         torch = self._torch
+        if not isinstance(g2, torch.Tensor) or g2.dtype != torch.complex64 or g2.device != self.device:
+            raise TypeError(f"g2 must be a complex64 tensor on {self.device}")
+        if g2.numel() != self.mx * self.my or not g2.is_contiguous():
+            raise ValueError(f"g2 must be contiguous with {self.my} x {self.mx} elements")
         if out is None:
             out = torch.empty(self.n, dtype=torch.complex64, device=self.device)
+        elif (out.dtype != torch.complex64 or out.device != self.device or out.numel() != self.n
+              or not out.is_contiguous()):
+            raise ValueError("out must be a contiguous complex64 [n] tensor on the plan's device")
         _check(lib().asf_adjoint(self._h, g2.data_ptr(), out.data_ptr(),
                                  _stream_ptr(torch, self.device, stream)))
         return out

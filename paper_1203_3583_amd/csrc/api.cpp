@@ -460,8 +460,29 @@ int asf_forward(asf_plan_t plan, const void *u1, void *u2, void *stream) {
 }
 
 int asf_adjoint(asf_plan_t plan, const void *g2, void *g1, void *stream) {
-    (void)plan; (void)g2; (void)g1; (void)stream;
-    return fail(ASF_ENOSYS, "asf_adjoint is not implemented");
+    if (!plan || !g2 || !g1) return fail(ASF_EINVAL, "plan, g2, g1 must be non-NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    asf_plan_s *p = plan;
+    const int split = (p->prm.flags & ASF_FFT_MASK) == ASF_FFT_SPLIT_FP16;
+    hipError_t e;
+    {
+        StageMark m(p, asf::STAGE_ADJ_FFT2, s);
+        e = asf::launch_fft_adj_rows(p->lay.nfx, split, static_cast<const float2 *>(g2), p->mid, p->twx,
+                                     p->w16, p->dx, p->dy, p->lay.mx, p->lay.my, s);
+        if (e != hipSuccess) return hip_fail(e, "adjoint row pass launch");
+    }
+    {
+        StageMark m(p, asf::STAGE_ADJ_FFT1, s);
+        e = asf::launch_fft_adj_cols(p->lay.nfy, split, p->mid, p->fine, p->twy, p->w16, p->lay.nfx,
+                                     p->lay.my, s);
+        if (e != hipSuccess) return hip_fail(e, "adjoint column pass launch");
+    }
+    {
+        StageMark m(p, asf::STAGE_INTERP, s);
+        e = asf::launch_interp(p->sp, p->bin, p->fine, static_cast<float2 *>(g1), s);
+        if (e != hipSuccess) return hip_fail(e, "interpolation launch");
+    }
+    return ASF_OK;
 }
 
 int asf_plan_info(asf_plan_t plan, asf_info *info) {

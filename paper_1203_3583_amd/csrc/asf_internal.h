@@ -49,7 +49,11 @@ struct FftShape {
     int batch;      // transforms per workgroup
 };
 
-enum { STAGE_COUNT = 0, STAGE_SCAN, STAGE_SCATTER, STAGE_SPREAD, STAGE_FFT1, STAGE_FFT2, NSTAGES };
+enum {
+    STAGE_COUNT = 0, STAGE_SCAN, STAGE_SCATTER, STAGE_SPREAD, STAGE_FFT1, STAGE_FFT2,   // forward
+    STAGE_ADJ_FFT2, STAGE_ADJ_FFT1, STAGE_INTERP,                                      // adjoint
+    NSTAGES
+};
 
 // ---- launchers (one per kernel family) ---------------------------------------
 hipError_t launch_bin_reset(const Binned &b, int ntiles, hipStream_t s);
@@ -68,6 +72,16 @@ hipError_t launch_fft_pass1(const FftShape &sh, int split16, const float2 *fine,
 hipError_t launch_fft_pass2(const FftShape &sh, int log_panel, int split16, const float2 *mid,
                             float2 *u2, const float2 *tw, const float2 *w16, const float2 *dx,
                             const float2 *dy, int mx, int my, hipStream_t s);
+// adjoint: rows of g2 (pre-corrected, zero-padded) -> mid (my x nfx, row-major)
+hipError_t launch_fft_adj_rows(int len, int split16, const float2 *g2, float2 *mid, const float2 *tw,
+                               const float2 *w16, const float2 *dx, const float2 *dy, int mx, int my,
+                               hipStream_t s);
+// adjoint: columns of mid (zero-padded) -> fine grid (panel layout)
+hipError_t launch_fft_adj_cols(int len, int split16, const float2 *mid, float2 *fine,
+                               const float2 *tw, const float2 *w16, int nfx, int my, hipStream_t s);
+// adjoint of spreading: fine grid -> g1[n] (caller's order)
+hipError_t launch_interp(const SpreadParams &p, const Binned &b, const float2 *fine, float2 *g1,
+                         hipStream_t s);
 int fft_batch_pass1(int len);          // columns per workgroup in pass 1 (fine-grid panel width)
 int fft_batch_pass2(int len);          // rows per workgroup in pass 2
 size_t fft_lds_bytes(int len, int batch);

@@ -381,6 +381,119 @@ __global__ void __launch_bounds__(NT) fft_pass2_kernel(const float2 *__restrict_
     }
 }
 
+// ---- adjoint (type-2 direction) -------------------------------------------------
+// The adjoint of the forward's two pruned passes: the kept modes, zero-padded
+// to the fine grid, go through the unnormalised inverse-direction (exp(+i)) DFT,
+// rows first, then columns.  exp(+i) transforms reuse the exp(-i) stages as
+// conj(DFT(conj(x))): values are conjugated on the way into LDS and out of it.
+// Mode m of a length-L transform sits at index m mod L; destination pixel ix
+// is mode ix - mx/2.
+
+// Adjoint pass 2: a workgroup takes BATCH rows of g2, multiplies by
+// conj(Dx[ix] Dy[iy]) (the adjoint of the fused deconvolution and phase),
+// zero-pads to nfx and writes the transformed rows to mid (my x nfx, row-major).
+template <int LOGL, int BATCH, int NT, bool SPLIT>
+__global__ void __launch_bounds__(NT) fft_adj_rows_kernel(const float2 *__restrict__ g2,
+                                                          float2 *__restrict__ mid,
+                                                          const float2 *__restrict__ tw,
+                                                          const float2 *__restrict__ w16,
+                                                          const float2 *__restrict__ dx,
+                                                          const float2 *__restrict__ dy, int mx) {
+    using S = Len<LOGL>;
+    extern __shared__ float2 lds[];
+    __shared__ float scratch[NT / 64];
+    const int row0 = blockIdx.x * BATCH;
+    const int half = mx >> 1;
+    float big = 0.f;
+    for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
+        const int c = t >> LOGL, l = t & (S::L - 1);
+        const int m = l < S::L / 2 ? l : l - S::L;
+        const int ix = m + half;
+        float2 v = make_float2(0.f, 0.f);
+        if (ix >= 0 && ix < mx) {
+            // conj(g conj(Dx Dy)) = conj(g) Dx Dy
+            const float2 g = g2[(size_t)(row0 + c) * mx + ix];
+            v = cmul(cmul(make_float2(g.x, -g.y), dx[ix]), dy[row0 + c]);
+        }
+        lds[c * S::STRIDE + lds_pos<S::PS>(l)] = v;
+        if constexpr (SPLIT) big = fmaxf(big, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+    float unscale = 1.f;
+    if constexpr (SPLIT) {
+        const int e = range_exponent(block_max(big, scratch));
+        const float inv = ldexpf(1.f, -e);
+        unscale = ldexpf(1.f, e);
+        __syncthreads();
+        for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
+            const int c = t >> LOGL, l = t & (S::L - 1);
+            float2 &x = lds[c * S::STRIDE + lds_pos<S::PS>(l)];
+            x = make_float2(x.x * inv, x.y * inv);
+        }
+    }
+    __syncthreads();
+    transform_all<LOGL, BATCH, NT, SPLIT>(lds, tw, w16);
+    float2 *dst = mid + (size_t)row0 * S::L;
+    for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
+        const int c = t >> LOGL, l = t & (S::L - 1);
+        const float2 v = lds[c * S::STRIDE + lds_pos<S::PS>(l)];
+        dst[t] = make_float2(v.x * unscale, -v.y * unscale);
+    }
+}
+
+// Adjoint pass 1: a workgroup takes BATCH adjacent columns of mid (the my kept
+// rows), zero-pads to nfy and writes the transformed columns to the fine grid
+// in its panel layout (one contiguous block per workgroup).  The 16 / BATCH
+// panels that share 128-byte lines of mid rows run on one XCD.
+template <int LOGL, int BATCH, int NT, bool SPLIT>
+__global__ void __launch_bounds__(NT) fft_adj_cols_kernel(const float2 *__restrict__ mid,
+                                                          float2 *__restrict__ fine,
+                                                          const float2 *__restrict__ tw,
+                                                          const float2 *__restrict__ w16,
+                                                          int nfx, int my, int xcd_group) {
+    using S = Len<LOGL>;
+    extern __shared__ float2 lds[];
+    __shared__ float scratch[NT / 64];
+    int pc = blockIdx.x;
+    if (xcd_group > 1) {
+        const int xcd = pc & 7, slot = pc >> 3;
+        pc = ((slot / xcd_group) * 8 + xcd) * xcd_group + slot % xcd_group;
+    }
+    const int half = my >> 1;
+    float big = 0.f;
+    for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
+        const int l = t / BATCH, c = t % BATCH;
+        const int m = l < S::L / 2 ? l : l - S::L;
+        const int ky = m + half;
+        float2 v = make_float2(0.f, 0.f);
+        if (ky >= 0 && ky < my) {
+            const float2 g = mid[(size_t)ky * nfx + pc * BATCH + c];
+            v = make_float2(g.x, -g.y);
+        }
+        lds[c * S::STRIDE + lds_pos<S::PS>(l)] = v;
+        if constexpr (SPLIT) big = fmaxf(big, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+    float unscale = 1.f;
+    if constexpr (SPLIT) {
+        const int e = range_exponent(block_max(big, scratch));
+        const float inv = ldexpf(1.f, -e);
+        unscale = ldexpf(1.f, e);
+        __syncthreads();
+        for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
+            const int l = t / BATCH, c = t % BATCH;
+            float2 &x = lds[c * S::STRIDE + lds_pos<S::PS>(l)];
+            x = make_float2(x.x * inv, x.y * inv);
+        }
+    }
+    __syncthreads();
+    transform_all<LOGL, BATCH, NT, SPLIT>(lds, tw, w16);
+    float2 *dst = fine + (size_t)pc * S::L * BATCH;
+    for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
+        const int l = t / BATCH, c = t % BATCH;
+        const float2 v = lds[c * S::STRIDE + lds_pos<S::PS>(l)];
+        dst[t] = make_float2(v.x * unscale, -v.y * unscale);
+    }
+}
+
 // Kernels needing more than 64 KB of dynamic LDS must say so once per size.
 hipError_t allow_lds(const void *kernel, size_t lds, size_t &enabled) {
     if (lds > 65536 && lds > enabled) {
@@ -431,6 +544,71 @@ hipError_t launch2(const FftShape &sh, const float2 *mid, float2 *u2, const floa
     hipLaunchKernelGGL(k, dim3(groups), dim3(NT), lds, s, mid, u2, tw, w16, dx, dy, mx, my, log_panel,
                        xcd_group);
     return hipGetLastError();
+}
+
+template <int LOGL, int BATCH, bool SPLIT>
+hipError_t launch_adj2(const float2 *g2, float2 *mid, const float2 *tw, const float2 *w16,
+                       const float2 *dx, const float2 *dy, int mx, int my, hipStream_t s) {
+    constexpr int NT = threads_for<LOGL, BATCH>();
+    const size_t lds = (size_t)BATCH * Len<LOGL>::STRIDE * sizeof(float2);
+    static thread_local size_t enabled = 0;
+    auto k = fft_adj_rows_kernel<LOGL, BATCH, NT, SPLIT>;
+    hipError_t e = allow_lds((const void *)k, lds, enabled);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(my / BATCH), dim3(NT), lds, s, g2, mid, tw, w16, dx, dy, mx);
+    return hipGetLastError();
+}
+
+template <int LOGL, int BATCH, bool SPLIT>
+hipError_t launch_adj1(const float2 *mid, float2 *fine, const float2 *tw, const float2 *w16,
+                       int nfx, int my, hipStream_t s) {
+    constexpr int NT = threads_for<LOGL, BATCH>();
+    const size_t lds = (size_t)BATCH * Len<LOGL>::STRIDE * sizeof(float2);
+    static thread_local size_t enabled = 0;
+    auto k = fft_adj_cols_kernel<LOGL, BATCH, NT, SPLIT>;
+    hipError_t e = allow_lds((const void *)k, lds, enabled);
+    if (e != hipSuccess) return e;
+    const int groups = nfx / BATCH;
+    const int g = BATCH < 16 ? 16 / BATCH : 1;   // panels per 128-byte line of a mid row
+    const int xcd_group = (g > 1 && groups % (8 * g) == 0) ? g : 1;
+    hipLaunchKernelGGL(k, dim3(groups), dim3(NT), lds, s, mid, fine, tw, w16, nfx, my, xcd_group);
+    return hipGetLastError();
+}
+
+template <bool SPLIT>
+hipError_t dispatch_adj2(int len, const float2 *g2, float2 *mid, const float2 *tw, const float2 *w16,
+                         const float2 *dx, const float2 *dy, int mx, int my, hipStream_t s) {
+    switch (__builtin_ctz(len)) {
+        case 5: return launch_adj2<5, 8, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
+        case 6: return launch_adj2<6, 4, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
+        case 7: return launch_adj2<7, 2, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
+        case 8: return launch_adj2<8, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
+        case 9: return launch_adj2<9, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
+        case 10: return launch_adj2<10, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
+        case 11: return launch_adj2<11, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
+        case 12: return launch_adj2<12, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
+        case 13: return launch_adj2<13, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
+        case 14: return launch_adj2<14, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <bool SPLIT>
+hipError_t dispatch_adj1(int len, const float2 *mid, float2 *fine, const float2 *tw,
+                         const float2 *w16, int nfx, int my, hipStream_t s) {
+    switch (__builtin_ctz(len)) {
+        case 5: return launch_adj1<5, 16, SPLIT>(mid, fine, tw, w16, nfx, my, s);
+        case 6: return launch_adj1<6, 16, SPLIT>(mid, fine, tw, w16, nfx, my, s);
+        case 7: return launch_adj1<7, 16, SPLIT>(mid, fine, tw, w16, nfx, my, s);
+        case 8: return launch_adj1<8, 16, SPLIT>(mid, fine, tw, w16, nfx, my, s);
+        case 9: return launch_adj1<9, 16, SPLIT>(mid, fine, tw, w16, nfx, my, s);
+        case 10: return launch_adj1<10, 8, SPLIT>(mid, fine, tw, w16, nfx, my, s);
+        case 11: return launch_adj1<11, 4, SPLIT>(mid, fine, tw, w16, nfx, my, s);
+        case 12: return launch_adj1<12, 2, SPLIT>(mid, fine, tw, w16, nfx, my, s);
+        case 13: return launch_adj1<13, 1, SPLIT>(mid, fine, tw, w16, nfx, my, s);
+        case 14: return launch_adj1<14, 1, SPLIT>(mid, fine, tw, w16, nfx, my, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // Batch sizes used per length (see fft_batch_pass1/2): pass 1 fills about 68 KB
@@ -524,6 +702,19 @@ hipError_t launch_fft_pass2(const FftShape &sh, int log_panel, int split16, cons
                             const float2 *dy, int mx, int my, hipStream_t s) {
     if (split16) return dispatch2<true>(sh, log_panel, mid, u2, tw, w16, dx, dy, mx, my, s);
     return dispatch2<false>(sh, log_panel, mid, u2, tw, w16, dx, dy, mx, my, s);
+}
+
+hipError_t launch_fft_adj_rows(int len, int split16, const float2 *g2, float2 *mid, const float2 *tw,
+                               const float2 *w16, const float2 *dx, const float2 *dy, int mx, int my,
+                               hipStream_t s) {
+    if (split16) return dispatch_adj2<true>(len, g2, mid, tw, w16, dx, dy, mx, my, s);
+    return dispatch_adj2<false>(len, g2, mid, tw, w16, dx, dy, mx, my, s);
+}
+
+hipError_t launch_fft_adj_cols(int len, int split16, const float2 *mid, float2 *fine,
+                               const float2 *tw, const float2 *w16, int nfx, int my, hipStream_t s) {
+    if (split16) return dispatch_adj1<true>(len, mid, fine, tw, w16, nfx, my, s);
+    return dispatch_adj1<false>(len, mid, fine, tw, w16, nfx, my, s);
 }
 
 }  // namespace asf

@@ -430,6 +430,83 @@ hipError_t launch_w(const SpreadParams &p, const Binned &b, const float2 *u1, fl
     return hipGetLastError();
 }
 
+// Interpolation, the adjoint of spreading (the type-2 direction): every point
+// gathers its w x w footprint of the fine grid with the same kernel weights,
+//   g_j = conj(exp(i phi_j)) sum_l psi(l_x - g_x) psi(l_y - g_y) F[l],
+// the conjugate pre-phase being the adjoint of the pre-phase multiply.  One
+// workgroup per tile copies into LDS the cells the footprints of the tile's own
+// points reach (the tile plus w-1 cells right and below, periodic).  A point is
+// handled in the tile that holds its first footprint cell and skipped in the
+// other bins that list it, so each point is written once, with a plain store:
+// no atomics, and FP32 sums in registers.
+constexpr int kInterpThreads = 256;
+
+template <int W>
+__global__ void __launch_bounds__(kInterpThreads) interp_kernel(SpreadParams p, Binned b,
+                                                                const float2 *__restrict__ fine,
+                                                                float2 *__restrict__ g1) {
+    constexpr int RP = kTileXMax + W - 1;   // LDS row pitch (cells)
+    __shared__ float2 reg[(kTileYMax + W - 1) * RP];
+    const int t = blockIdx.x;
+    const int tsx = 1 << p.log_tile_x, tsy = 1 << p.log_tile_y;
+    const int rx = tsx + W - 1, ry = tsy + W - 1;
+    const int ty = t >> p.log_ntx, tx = t & ((1 << p.log_ntx) - 1);
+    const int x0 = tx << p.log_tile_x, y0 = ty << p.log_tile_y;
+    const int nt = blockDim.x, tid = threadIdx.x;
+    // copy the region in the fine grid's panel order (C adjacent columns per row,
+    // rows of a panel contiguous), so consecutive lanes read consecutive elements
+    const int C = 1 << p.log_panel;
+    const int rxp = (rx + C - 1) & ~(C - 1);
+    const float inv_ry = 1.f / (float)ry;
+    for (int i = tid; i < rxp * ry; i += nt) {
+        const int c = i & (C - 1);
+        const int rest = i >> p.log_panel;
+        const int qx = (int)(((float)rest + 0.5f) * inv_ry);   // rest / ry, exact for rest < 2^20
+        const int yy = rest - qx * ry;
+        const int xx = qx * C + c;
+        if (xx >= rx) continue;
+        int gx = x0 + xx, gy = y0 + yy;
+        if (gx >= p.nfx) gx -= p.nfx;
+        if (gy >= p.nfy) gy -= p.nfy;
+        reg[yy * RP + xx] = fine[(((size_t)(gx >> p.log_panel) * p.nfy + gy) << p.log_panel) + (gx & (C - 1))];
+    }
+    __syncthreads();
+    const uint32_t s0 = b.tile_start[t], s1 = b.tile_start[t + 1];
+    for (uint32_t s = s0 + tid; s < s1; s += nt) {
+        const uint32_t cell = b.cell[s];
+        const int px = (int)(cell & 0xffffu) - x0, py = (int)(cell >> 16) - y0;
+        if (px < 0 || px >= tsx || py < 0 || py >= tsy) continue;   // not this point's home tile
+        const uint32_t j = b.perm[s];
+        const float2 fr = b.frac[s], ph = b.phase[s];
+        float kx[W], ky[W];
+        es_values<W>(fr.x, kx);
+        es_values<W>(fr.y, ky);
+        const float2 *row = reg + py * RP + px;
+        float ar = 0.f, ai = 0.f;
+#pragma unroll
+        for (int jy = 0; jy < W; ++jy) {
+            float sr = 0.f, si = 0.f;
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                const float2 v = row[jy * RP + i];
+                sr = __builtin_fmaf(kx[i], v.x, sr);
+                si = __builtin_fmaf(kx[i], v.y, si);
+            }
+            ar = __builtin_fmaf(ky[jy], sr, ar);
+            ai = __builtin_fmaf(ky[jy], si, ai);
+        }
+        // times conj(exp(i phi))
+        g1[j] = make_float2(ar * ph.x + ai * ph.y, ai * ph.x - ar * ph.y);
+    }
+}
+
+template <int W>
+hipError_t launch_interp_w(const SpreadParams &p, const Binned &b, const float2 *fine, float2 *g1,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(interp_kernel<W>, dim3(p.ntx * p.nty), dim3(kInterpThreads), 0, s, p, b, fine, g1);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_spread(const SpreadParams &p, const Binned &b, const float2 *u1, float2 *fine,
@@ -445,6 +522,22 @@ hipError_t launch_spread(const SpreadParams &p, const Binned &b, const float2 *u
         case 7: return launch_w<7>(p, b, u1, fine, s);
         case 8: return launch_w<8>(p, b, u1, fine, s);
         case 9: return launch_w<9>(p, b, u1, fine, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_interp(const SpreadParams &p, const Binned &b, const float2 *fine, float2 *g1,
+                         hipStream_t s) {
+    if ((1 << p.log_tile_x) > kTileXMax || (1 << p.log_tile_y) > kTileYMax) return hipErrorInvalidValue;
+    switch (p.w) {
+        case 2: return launch_interp_w<2>(p, b, fine, g1, s);
+        case 3: return launch_interp_w<3>(p, b, fine, g1, s);
+        case 4: return launch_interp_w<4>(p, b, fine, g1, s);
+        case 5: return launch_interp_w<5>(p, b, fine, g1, s);
+        case 6: return launch_interp_w<6>(p, b, fine, g1, s);
+        case 7: return launch_interp_w<7>(p, b, fine, g1, s);
+        case 8: return launch_interp_w<8>(p, b, fine, g1, s);
+        case 9: return launch_interp_w<9>(p, b, fine, g1, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -182,16 +182,3 @@ def test_domain_errors_raise():
     assert e.value.code == asf.asf.ASF_EDOMAIN
     plan.close()
 
-
-def test_adjoint_not_implemented():
-    torch = torch_gpu()
-    import paper_1203_3583_amd as asf
-
-    w = synth.config("sinusoid_128", side=16, out=16)
-    x, y, d, _ = to_dev(torch, w)
-    plan = asf.Plan(x, y, d, w.lam, w.z0, w.p2x, w.p2y, w.mx, w.my)
-    g2 = torch.zeros((16, 16), dtype=torch.complex64, device="cuda")
-    with pytest.raises(asf.AsfError) as e:
-        plan.adjoint(g2)
-    assert e.value.code == asf.asf.ASF_ENOSYS
-    plan.close()
