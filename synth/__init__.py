@@ -148,10 +148,39 @@ def _sinusoid_4096(seed: int = 0, side: int = 4096, out: int | None = None) -> W
                     {"side": side, "seed": seed})
 
 
+def smooth_target(rng: np.random.Generator, nx: int, ny: int, sigma_px: float = 4.0) -> np.ndarray:
+    """Target intensity (ny, nx) float64 in [0, 1]: uniform noise U[0, 1) filtered by a
+    periodic Gaussian of standard deviation sigma_px pixels, rescaled to [0, 1]."""
+    noise = rng.uniform(0.0, 1.0, size=(ny, nx))
+    fy = np.fft.fftfreq(ny)[:, None]
+    fx = np.fft.fftfreq(nx)[None, :]
+    gain = np.exp(-2.0 * (np.pi * sigma_px) ** 2 * (fx * fx + fy * fy))
+    t = np.real(np.fft.ifft2(np.fft.fft2(noise) * gain))
+    t -= t.min()
+    return t / t.max()
+
+
+def _holo_1024(seed: int = 0, side: int = 1024, out: int | None = None) -> Workload:
+    """Phase-hologram problem: 1024^2 phase-only source on a spherical cap R = 80 mm,
+    8 um pitch with +-0.3 pitch jitter, unit amplitude, zero initial phase,
+    lambda = 532 nm, z0 = 0.15 m, 1024^2 destination at 8 um; the target intensity
+    (Gaussian-filtered uniform noise, sigma 4 px) is in meta["target"]."""
+    rng = np.random.default_rng(seed)
+    p = 8e-6
+    x, y = jittered_grid(rng, side, side, p, 0.3 * p)
+    d = spherical_cap(x, y, 80e-3)
+    u = np.ones(side * side, dtype=np.complex64)
+    m = side if out is None else out
+    target = smooth_target(rng, m, m, 4.0)
+    return Workload("holo_1024", x, y, d, u, 532e-9, 0.15, p, p, m, m, 1e-5, "plane",
+                    {"side": side, "seed": seed, "target": target})
+
+
 _CONFIGS = {
     "sinusoid_128": _sinusoid_128,
     "cap_2048": _cap_2048,
     "sinusoid_4096": _sinusoid_4096,
+    "holo_1024": _holo_1024,
 }
 CONFIG_NAMES = tuple(_CONFIGS)
 
