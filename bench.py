@@ -7,6 +7,8 @@ z0 = 0.2 m, 2048 x 2048 destination at 8 um, sigma = 2, w = 7, tol 1e-5).
 One step is the whole hot path over one batch of synthetic input already
 resident in HBM: the FP64 pre-phase and tile binning (asf_setpts) and the
 spreading plus both FFT passes with the fused deconvolution (asf_forward).
+The line also reports the geometry-cached forward alone (``fwd``) and the
+adjoint of the same plan (``adjoint``, the type-2 direction used for gradients).
 
 Prints one JSON line.  ``value`` is NU points/s (source points per second of
 whole-step time).  Both FFT precisions are timed; the headline is the faster
@@ -71,6 +73,26 @@ def stored_traffic():
         return None
 
 
+def time_calls(torch, plan, fn, steps, warmup):
+    """Average seconds per call of fn() (plan geometry cached), and its stage times."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    plan.set_timing(True)
+    acc = {}
+    for _ in range(steps):
+        fn()
+        for k, v in plan.stage_times().items():
+            acc[k] = acc.get(k, 0.0) + v / steps
+    plan.set_timing(False)
+    return sec, acc
+
+
 def time_steps(torch, plan, x, y, d, u, out, steps, warmup, stage_events):
     for _ in range(warmup):
         plan.setpts(x, y, d)
@@ -122,8 +144,14 @@ def main():
         _, stages = time_steps(torch, plan, x, y, d, u, out, args.steps, 0, True)
         plan.forward(u, out=out)
         torch.cuda.synchronize()
-        results[fft] = {"sec": sec, "stages": stages, "info": info,
-                        "u2": out.cpu().numpy().astype(np.complex128)}
+        u2 = out.cpu().numpy().astype(np.complex128)
+        # the geometry-cached forward, and the adjoint (type-2 direction) of the same plan
+        fwd_sec, fwd_stages = time_calls(torch, plan, lambda: plan.forward(u, out=out), args.steps, 2)
+        g1 = torch.empty(w.n, dtype=torch.complex64, device=dev)
+        adj_sec, adj_stages = time_calls(torch, plan, lambda: plan.adjoint(out, out=g1), args.steps, 2)
+        results[fft] = {"sec": sec, "stages": stages, "info": info, "u2": u2,
+                        "fwd_sec": fwd_sec, "fwd_stages": fwd_stages,
+                        "adj_sec": adj_sec, "adj_stages": adj_stages}
         plan.close()
 
     if args.copy_calibration:
@@ -159,8 +187,14 @@ def main():
                    "sigma": 2, "fft": head, "step": "setpts(prephase+bin) + forward(spread+fft+deconv)"},
         "stages_ms": {k: round(v, 4) for k, v in r["stages"].items()},
         "variants": {k: {"ms_per_step": v["sec"] * 1e3, "value": n / v["sec"],
-                         "stages_ms": {s: round(t, 4) for s, t in v["stages"].items()}}
+                         "stages_ms": {s: round(t, 4) for s, t in v["stages"].items()},
+                         "fwd_ms": v["fwd_sec"] * 1e3, "adjoint_ms": v["adj_sec"] * 1e3}
                      for k, v in results.items()},
+        # geometry cached (plan reused): the forward alone, and the adjoint g1 = A^H g2
+        "fwd": {"ms_per_call": r["fwd_sec"] * 1e3, "value": n / r["fwd_sec"], "unit": "NU points/s",
+                "stages_ms": {s: round(t, 4) for s, t in r["fwd_stages"].items()}},
+        "adjoint": {"ms_per_call": r["adj_sec"] * 1e3, "value": n / r["adj_sec"], "unit": "NU points/s",
+                    "stages_ms": {s: round(t, 4) for s, t in r["adj_stages"].items()}},
         "roofline": {
             "kernel": "spread",
             "bound": "hbm",
