@@ -47,7 +47,7 @@ typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef _Float16 v2h __attribute__((ext_vector_type(2)));
 typedef float v2f __attribute__((ext_vector_type(2)));
 
-__device__ inline float2 cmul(float2 a, float2 b) {
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
@@ -66,13 +66,13 @@ struct Len {
 // LDS position of element e: low 4 bits XOR-swizzled by bits 4..7, plus 16 slots
 // of padding every 2^PS elements (keeps a half-wave's accesses on distinct banks).
 template <int PS>
-__device__ inline int lds_pos(int e) {
+__device__ __forceinline__ int lds_pos(int e) {
     return (e ^ ((e >> 4) & 15)) + ((e >> PS) << 4);
 }
 
 struct Dft16F32 {
     float are[8], aim[8];
-    __device__ void init(const float2 *w16, int g, int jj) {
+    __device__ __forceinline__ void init(const float2 *w16, int g, int jj) {
         const int p = (jj >> 2) + 4 * (jj & 3);
 #pragma unroll
         for (int kb = 0; kb < 8; ++kb) {
@@ -82,7 +82,7 @@ struct Dft16F32 {
             aim[kb] = (kb & 1) ? w.x : w.y;
         }
     }
-    __device__ void run(float2 (&v)[4]) const {
+    __device__ __forceinline__ void run(float2 (&v)[4]) const {
         v4f accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kb = 0; kb < 8; ++kb) {
@@ -97,7 +97,7 @@ struct Dft16F32 {
 
 struct Dft16Split16 {
     v8h re_hi, re_lo, im_hi, im_lo;
-    __device__ void init(const float2 *w16, int g, int jj) {
+    __device__ __forceinline__ void init(const float2 *w16, int g, int jj) {
         const int p = (jj >> 2) + 4 * (jj & 3);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -113,7 +113,7 @@ struct Dft16Split16 {
         }
     }
     // inputs already scaled into FP16 range by the workgroup's scale
-    __device__ void run(float2 (&v)[4]) const {
+    __device__ __forceinline__ void run(float2 (&v)[4]) const {
         v8h bh, bl;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -140,7 +140,7 @@ struct Dft16Split16 {
 
 // Radix-R0 first stage (Ns = 1, no twiddles) on the vector ALU, in place.
 template <int LOGL, int BATCH, int NT>
-__device__ void first_stage(float2 *lds, const float2 *w16s) {
+__device__ __forceinline__ void first_stage(float2 *lds, const float2 *w16s) {
     using S = Len<LOGL>;
     constexpr int R0 = S::R0;
     if constexpr (R0 > 1) {
@@ -186,7 +186,7 @@ __device__ void first_stage(float2 *lds, const float2 *w16s) {
 // One radix-16 Stockham stage with span NS, in place in LDS.  tw points at this
 // stage's table: entry (k, g, i) = exp(-2 pi i (g + 4 i) k / (16 NS)).
 template <int LOGL, int BATCH, int NT, int NS, class Engine>
-__device__ void radix16_stage(float2 *lds, const float4 *__restrict__ tw, const Engine &eng) {
+__device__ __forceinline__ void radix16_stage(float2 *lds, const float4 *__restrict__ tw, const Engine &eng) {
     using S = Len<LOGL>;
     constexpr int BLOCKS = BATCH * S::LQ / 16;     // 16-instance blocks in the stage
     constexpr int WAVES = NT / 64;
@@ -241,7 +241,7 @@ constexpr int twiddle_offset(int stage) {
 }
 
 template <int LOGL, int BATCH, int NT, int STAGE, class Engine>
-__device__ void stages_from(float2 *lds, const float4 *tw, const Engine &eng) {
+__device__ __forceinline__ void stages_from(float2 *lds, const float4 *tw, const Engine &eng) {
     using S = Len<LOGL>;
     if constexpr (STAGE < S::N16) {
         constexpr int NS = S::R0 << (4 * STAGE);
@@ -253,7 +253,7 @@ __device__ void stages_from(float2 *lds, const float4 *tw, const Engine &eng) {
 }
 
 template <int LOGL, int BATCH, int NT, bool SPLIT>
-__device__ void transform_all(float2 *lds, const float2 *tw, const float2 *w16) {
+__device__ __forceinline__ void transform_all(float2 *lds, const float2 *tw, const float2 *w16) {
     __shared__ float2 w16s[16];
     if (threadIdx.x < 16) w16s[threadIdx.x] = w16[threadIdx.x];
     __syncthreads();
@@ -270,7 +270,7 @@ __device__ void transform_all(float2 *lds, const float2 *tw, const float2 *w16) 
     }
 }
 
-__device__ inline float block_max(float v, float *scratch) {
+__device__ __forceinline__ float block_max(float v, float *scratch) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
     if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
@@ -281,7 +281,7 @@ __device__ inline float block_max(float v, float *scratch) {
 }
 
 // power of two 2^e with max_abs * 2^-e <= 1 (1 for zero data)
-__device__ inline int range_exponent(float max_abs) {
+__device__ __forceinline__ int range_exponent(float max_abs) {
     int e = 0;
     if (max_abs > 0.f) frexpf(max_abs, &e);
     return e;
