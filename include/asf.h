@@ -66,12 +66,18 @@ typedef struct asf_plan_s *asf_plan_t;
  *   tol       requested relative L2 accuracy in [1e-7, 1e-1]; sets the spreading
  *             width w = ceil(log10(1/tol)) + 2 (7 at 1e-5, so 3..9)
  *   flags     ASF_FFT_* | ASF_INCIDENT_NONE
+ *   x0, y0    centre of the destination window (m), finite: pixel (ix, iy) sits at
+ *             X = x0 + p2x (ix - mx/2), Y = y0 + p2y (iy - my/2); 0, 0 centres it
+ *             on the axis.  An off-axis window enters the sum of Eq. (7) as an
+ *             extra per-point phase -k (x1 x0 + y1 y0) / r0 and in the destination
+ *             chirp; it lets several windows tile one large destination plane.
  */
 typedef struct {
     double lambda, z0, p2x, p2y;
     int32_t mx, my;
     double tol;
     uint32_t flags;
+    double x0, y0;
 } asf_params;
 
 /* Read-only description of a plan (sizes the kernels run at). */
@@ -139,12 +145,22 @@ int asf_status(asf_plan_t plan, void *stream);
  * Forward transform, Eq. (8): u2 = A u1.
  *   u1  complex64 [n_src] device array (interleaved re, im), aligned with x1, y1, d1
  *   u2  complex64 [my][mx] device array, row-major; pixel (ix, iy) at
- *       X = p2x (ix - mx/2), Y = p2y (iy - my/2)
+ *       X = x0 + p2x (ix - mx/2), Y = y0 + p2y (iy - my/2)
  * Asynchronous on `stream`; never synchronises.  u1 must be finite (the spreading
  * accumulates in fixed point; non-finite input gives an unspecified result).
  * Returns ASF_OK, ASF_EINVAL or ASF_EHIP.
  */
 int asf_forward(asf_plan_t plan, const void *u1, void *u2, void *stream);
+
+/*
+ * Accumulating forward: u2 += A u1, same arguments and behaviour as asf_forward
+ * except that u2 is read and added to instead of overwritten.  The fields of
+ * several surfaces (one plan each, sharing the destination grid and window)
+ * then sum into one destination, the superposition the paper's computer-
+ * generated-hologram application needs (Sec. 4).  Calls on one u2 must be
+ * ordered (the same stream, or synchronised).
+ */
+int asf_forward_add(asf_plan_t plan, const void *u1, void *u2, void *stream);
 
 
 /*

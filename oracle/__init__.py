@@ -60,13 +60,14 @@ def load_library(path: str):
     lib.asf_oracle_direct.argtypes = [
         ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
         ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+        ctypes.c_double, ctypes.c_double,
         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
     lib.asf_oracle_adjoint.restype = ctypes.c_int
     lib.asf_oracle_adjoint.argtypes = [
         ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
         ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+        ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
     lib.asf_oracle_threads.restype = ctypes.c_int
     lib.asf_oracle_threads.argtypes = [ctypes.c_int32]
@@ -88,11 +89,12 @@ def threads(requested: int = 0) -> int:
 
 
 def direct(x, y, d, u, lam, z0, p2x, p2y, mx, my, ix, iy, incident="plane", nthreads=0,
-           lib=None):
+           lib=None, x0=0.0, y0=0.0):
     """u2 at destination pixels (ix[e], iy[e]) by the direct FP64 sum of Eq. (7).
 
     x, y, d: float64 [n] source coordinates and displacement (m); u: complex [n]
-    source field (complex64 input is promoted exactly to complex128); ix, iy: int [n_eval].
+    source field (complex64 input is promoted exactly to complex128); ix, iy: int [n_eval];
+    (x0, y0): the destination window's centre, pixel (ix, iy) at x0 + p2x (ix - mx // 2), ...
     Returns complex128 [n_eval].  Raises ValueError if some z0 - d <= 0.
     ``lib`` selects another compiled variant (tests only); default: the built oracle.
     """
@@ -111,7 +113,7 @@ def direct(x, y, d, u, lam, z0, p2x, p2y, mx, my, ix, iy, incident="plane", nthr
     out = np.empty(2 * ix.shape[0], dtype=np.float64)
     rc = lib.asf_oracle_direct(
         n, x.ctypes.data, y.ctypes.data, d.ctypes.data, u.ctypes.data,
-        float(lam), float(z0), float(p2x), float(p2y), int(mx), int(my),
+        float(lam), float(z0), float(p2x), float(p2y), float(x0), float(y0), int(mx), int(my),
         INCIDENT[incident], ix.shape[0], ix.ctypes.data, iy.ctypes.data,
         out.ctypes.data, int(nthreads))
     if rc != 0:
@@ -120,17 +122,18 @@ def direct(x, y, d, u, lam, z0, p2x, p2y, mx, my, ix, iy, incident="plane", nthr
 
 
 def direct_grid(x, y, d, u, lam, z0, p2x, p2y, mx, my, ix_range=None, iy_range=None,
-                incident="plane", nthreads=0, lib=None):
+                incident="plane", nthreads=0, lib=None, x0=0.0, y0=0.0):
     """u2 on the rectangle ix_range x iy_range (default: the whole grid), shape (rows, cols)."""
     ixs = np.arange(mx) if ix_range is None else np.asarray(list(ix_range))
     iys = np.arange(my) if iy_range is None else np.asarray(list(iy_range))
     gx, gy = np.meshgrid(ixs, iys)
     vals = direct(x, y, d, u, lam, z0, p2x, p2y, mx, my, gx.reshape(-1), gy.reshape(-1),
-                  incident, nthreads, lib)
+                  incident, nthreads, lib, x0, y0)
     return vals.reshape(len(iys), len(ixs))
 
 
-def adjoint(x, y, d, g2, lam, z0, p2x, p2y, jidx=None, incident="plane", nthreads=0, lib=None):
+def adjoint(x, y, d, g2, lam, z0, p2x, p2y, jidx=None, incident="plane", nthreads=0, lib=None,
+            x0=0.0, y0=0.0):
     """g1 = A^H g2 at source points jidx (default: all), by the direct FP64 sum.
 
     A is the linear map u1 -> u2 that ``direct`` evaluates; g2: complex [my, mx]
@@ -151,7 +154,7 @@ def adjoint(x, y, d, g2, lam, z0, p2x, p2y, jidx=None, incident="plane", nthread
     out = np.empty(2 * jidx.shape[0], dtype=np.float64)
     rc = lib.asf_oracle_adjoint(
         n, x.ctypes.data, y.ctypes.data, d.ctypes.data, float(lam), float(z0), float(p2x),
-        float(p2y), int(mx), int(my), INCIDENT[incident], g2.ctypes.data, jidx.shape[0],
+        float(p2y), float(x0), float(y0), int(mx), int(my), INCIDENT[incident], g2.ctypes.data, jidx.shape[0],
         jidx.ctypes.data, out.ctypes.data, int(nthreads))
     if rc != 0:
         raise ValueError("oracle: invalid arguments or r0 = z0 - d1 <= 0")

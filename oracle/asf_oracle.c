@@ -17,7 +17,8 @@
  * as minus, as in Eq. (4), Eq. (5) and the transform kernel of Eq. (9) (Eq. (7)
  * prints a plus; with it, d1 = 0 would not reduce to the ordinary Fresnel
  * transform).  The destination pixel (ix, iy) sits at
- * X = p2x (ix - mx/2), Y = p2y (iy - my/2) (integer division).
+ * X = x0 + p2x (ix - mx/2), Y = y0 + p2y (iy - my/2) (integer division); the
+ * window centre (x0, y0) is 0 for a window on the axis.
  *
  *   u2(X, Y) = exp(i k (z0 + (X^2 + Y^2) / (2 z0))) / (i lambda z0)
  *            * sum_j u_j u_I,j exp(i k [ -d_j + (x_j^2 + y_j^2) / (2 r0_j)
@@ -47,6 +48,7 @@ int asf_oracle_threads(int32_t requested)
  * u          FP64 [2n]: complex source field, interleaved (re, im)
  * lambda, z0 wavelength and source-to-destination distance (m)
  * p2x, p2y   destination pitch (m); mx, my destination grid size
+ * x0, y0     destination window centre (m)
  * incident   0: plane wave exp(i k d1); 1: u_I = 1
  * n_eval     number of destination pixels to evaluate
  * ix, iy     int32 [n_eval]: pixel column and row
@@ -56,7 +58,7 @@ int asf_oracle_threads(int32_t requested)
  */
 int asf_oracle_direct(int64_t n, const double *x, const double *y, const double *d,
                       const double *u, double lambda, double z0, double p2x, double p2y,
-                      int32_t mx, int32_t my, int32_t incident, int64_t n_eval,
+                      double x0, double y0, int32_t mx, int32_t my, int32_t incident, int64_t n_eval,
                       const int32_t *ix, const int32_t *iy, double *out, int32_t threads)
 {
     if (n < 0 || n_eval < 0 || !(lambda > 0.0) || !(z0 > 0.0)) return -1;
@@ -69,8 +71,8 @@ int asf_oracle_direct(int64_t n, const double *x, const double *y, const double 
 
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
     for (int64_t e = 0; e < n_eval; ++e) {
-        const double X = p2x * (double)(ix[e] - mx / 2);
-        const double Y = p2y * (double)(iy[e] - my / 2);
+        const double X = x0 + p2x * (double)(ix[e] - mx / 2);
+        const double Y = y0 + p2y * (double)(iy[e] - my / 2);
         double sr = 0.0, si = 0.0;
         for (int64_t j = 0; j < n; ++j) {
             const double r0 = z0 - d[j];
@@ -113,7 +115,8 @@ int asf_oracle_direct(int64_t n, const double *x, const double *y, const double 
  * Other arguments as for asf_oracle_direct.  Parallel over points.
  */
 int asf_oracle_adjoint(int64_t n, const double *x, const double *y, const double *d,
-                       double lambda, double z0, double p2x, double p2y, int32_t mx, int32_t my,
+                       double lambda, double z0, double p2x, double p2y, double x0, double y0,
+                       int32_t mx, int32_t my,
                        int32_t incident, const double *g2, int64_t n_eval, const int64_t *jidx,
                        double *out, int32_t threads)
 {
@@ -132,9 +135,9 @@ int asf_oracle_adjoint(int64_t n, const double *x, const double *y, const double
         const double r0 = z0 - d[j];
         double sr = 0.0, si = 0.0;
         for (int32_t iy = 0; iy < my; ++iy) {
-            const double Y = p2y * (double)(iy - my / 2);
+            const double Y = y0 + p2y * (double)(iy - my / 2);
             for (int32_t ix = 0; ix < mx; ++ix) {
-                const double X = p2x * (double)(ix - mx / 2);
+                const double X = x0 + p2x * (double)(ix - mx / 2);
                 double arg = k * (-d[j] + (x[j] * x[j] + y[j] * y[j]) / (2.0 * r0)
                                   - (x[j] * X + y[j] * Y) / r0);
                 if (incident == ORACLE_INCIDENT_PLANE) arg += k * d[j];

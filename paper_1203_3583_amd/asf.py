@@ -40,7 +40,8 @@ class AsfError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("lam", ctypes.c_double), ("z0", ctypes.c_double), ("p2x", ctypes.c_double),
                 ("p2y", ctypes.c_double), ("mx", ctypes.c_int32), ("my", ctypes.c_int32),
-                ("tol", ctypes.c_double), ("flags", ctypes.c_uint32)]
+                ("tol", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -79,6 +80,8 @@ def lib():
         L.asf_status.argtypes = [vp, vp]
         L.asf_forward.restype = i32
         L.asf_forward.argtypes = [vp, vp, vp, vp]
+        L.asf_forward_add.restype = i32
+        L.asf_forward_add.argtypes = [vp, vp, vp, vp]
         L.asf_adjoint.restype = i32
         L.asf_adjoint.argtypes = [vp, vp, vp, vp]
         L.asf_plan_info.restype = i32
@@ -105,13 +108,15 @@ def _check(rc):
     return rc
 
 
-def make_params(lam, z0, p2x, p2y, mx, my, tol=1e-5, fft="fp32", incident="plane") -> Params:
+def make_params(lam, z0, p2x, p2y, mx, my, tol=1e-5, fft="fp32", incident="plane", x0=0.0,
+                y0=0.0) -> Params:
     flags = {"fp32": ASF_FFT_FP32, "split_fp16": ASF_FFT_SPLIT_FP16}[fft]
     if incident == "none":
         flags |= ASF_INCIDENT_NONE
     elif incident != "plane":
         raise ValueError(f"incident must be 'plane' or 'none', got {incident!r}")
-    return Params(float(lam), float(z0), float(p2x), float(p2y), int(mx), int(my), float(tol), flags)
+    return Params(float(lam), float(z0), float(p2x), float(p2y), int(mx), int(my), float(tol), flags,
+                  float(x0), float(y0))
 
 
 def workspace_bytes(n_src, params: Params) -> int:
@@ -139,11 +144,12 @@ class Plan:
 
     x1, y1, d1: float64 device tensors [n] (m); optics lam, z0 (m); destination
     pitch p2x, p2y (m) and size mx x my; tol sets the spreading width; fft is
-    "fp32" or "split_fp16"; incident is "plane" (u_I = exp(i k d1)) or "none".
+    "fp32" or "split_fp16"; incident is "plane" (u_I = exp(i k d1)) or "none";
+    (x0, y0) centres the destination window off the axis (m).
     """
 
     def __init__(self, x1, y1, d1, lam, z0, p2x, p2y, mx, my, tol=1e-5, fft="fp32",
-                 incident="plane", stream=None):
+                 incident="plane", stream=None, x0=0.0, y0=0.0):
         import torch
 
         self._torch = torch
@@ -155,7 +161,7 @@ class Plan:
             _dev_f64(torch, t, name, n, self.device)
         self.n = n
         self.mx, self.my = int(mx), int(my)
-        self.params = make_params(lam, z0, p2x, p2y, mx, my, tol, fft, incident)
+        self.params = make_params(lam, z0, p2x, p2y, mx, my, tol, fft, incident, x0, y0)
         nbytes = workspace_bytes(n, self.params)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         h = ctypes.c_void_p()
@@ -179,8 +185,11 @@ class Plan:
         _check(lib().asf_status(self._h, _stream_ptr(self._torch, self.device, stream)))
 
     # -- transforms -----------------------------------------------------------------
-    def forward(self, u1, out=None, stream=None):
-        """u2 (complex64 [my, mx]) from u1 (complex64 [n]) on the GPU, asynchronously."""
+    def forward(self, u1, out=None, stream=None, accumulate=False):
+        """u2 (complex64 [my, mx]) from u1 (complex64 [n]) on the GPU, asynchronously.
+
+        accumulate=True adds A u1 into ``out`` (asf_forward_add) instead of overwriting it.
+        """
         torch = self._torch
         if not isinstance(u1, torch.Tensor) or u1.dtype != torch.complex64 or u1.device != self.device:
             raise TypeError(f"u1 must be a complex64 tensor on {self.device}")
@@ -191,8 +200,10 @@ class Plan:
         elif (out.dtype != torch.complex64 or out.device != self.device or out.numel() != self.mx * self.my
               or not out.is_contiguous()):
             raise ValueError("out must be a contiguous complex64 [my, mx] tensor on the plan's device")
-        _check(lib().asf_forward(self._h, u1.data_ptr(), out.data_ptr(),
-                                 _stream_ptr(torch, self.device, stream)))
+        if accumulate and out is None:
+            raise ValueError("accumulate=True needs the out tensor to add into")
+        fn = lib().asf_forward_add if accumulate else lib().asf_forward
+        _check(fn(self._h, u1.data_ptr(), out.data_ptr(), _stream_ptr(torch, self.device, stream)))
         return out
 
     def adjoint(self, g2, out=None, stream=None):

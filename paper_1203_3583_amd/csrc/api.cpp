@@ -75,6 +75,7 @@ int check_params(int64_t n, const asf_params *p) {
     for (int i = 0; i < 4; ++i)
         if (!std::isfinite(v[i]) || !(v[i] > 0.0)) return fail(ASF_EINVAL, "%s must be finite and > 0", names[i]);
     if (!std::isfinite(p->tol) || p->tol < 1e-7 || p->tol > 1e-1) return fail(ASF_EINVAL, "tol must be in [1e-7, 1e-1]");
+    if (!std::isfinite(p->x0) || !std::isfinite(p->y0)) return fail(ASF_EINVAL, "x0, y0 must be finite");
     if (p->flags & ~(ASF_FFT_MASK | ASF_INCIDENT_NONE)) return fail(ASF_EINVAL, "unknown flag bits 0x%x", p->flags);
     if (!is_pow2(p->mx) || !is_pow2(p->my) || p->mx < 16 || p->my < 16 || p->mx > 8192 || p->my > 8192)
         return fail(ASF_ESIZE, "mx, my must be powers of two in [16, 8192], got %d x %d", p->mx, p->my);
@@ -276,7 +277,7 @@ int upload_tables(asf_plan_s *p, hipStream_t s) {
     const double c0r = std::sin(a0) / (q.lambda * q.z0), c0i = -std::cos(a0) / (q.lambda * q.z0);
     for (int ix = 0; ix < L.mx; ++ix) {
         const int m = ix - L.mx / 2;
-        const double X = q.p2x * m;
+        const double X = q.x0 + q.p2x * m;
         const double ch = reduce(k * X * X / (2.0 * q.z0));
         const double inv = 1.0 / phx[m < 0 ? -m : m];
         const double er = std::cos(ch) * inv, ei = std::sin(ch) * inv;
@@ -284,7 +285,7 @@ int upload_tables(asf_plan_s *p, hipStream_t s) {
     }
     for (int iy = 0; iy < L.my; ++iy) {
         const int n = iy - L.my / 2;
-        const double Y = q.p2y * n;
+        const double Y = q.y0 + q.p2y * n;
         const double ch = reduce(k * Y * Y / (2.0 * q.z0));
         const double inv = 1.0 / phy[n < 0 ? -n : n];
         dy[iy] = make_float2((float)(std::cos(ch) * inv), (float)(std::sin(ch) * inv));
@@ -374,6 +375,8 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
     pl->geo.z0 = p->z0;
     pl->geo.p2x = p->p2x;
     pl->geo.p2y = p->p2y;
+    pl->geo.x0 = p->x0;
+    pl->geo.y0 = p->y0;
     pl->geo.nfx = L.nfx;
     pl->geo.nfy = L.nfy;
     pl->geo.w = L.w;
@@ -434,7 +437,9 @@ int asf_status(asf_plan_t plan, void *stream) {
     return read_status(plan, static_cast<hipStream_t>(stream));
 }
 
-int asf_forward(asf_plan_t plan, const void *u1, void *u2, void *stream) {
+namespace {
+
+int forward(asf_plan_t plan, const void *u1, void *u2, void *stream, int accumulate) {
     if (!plan || !u1 || !u2) return fail(ASF_EINVAL, "plan, u1, u2 must be non-NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
     asf_plan_s *p = plan;
@@ -453,10 +458,20 @@ int asf_forward(asf_plan_t plan, const void *u1, void *u2, void *stream) {
     {
         StageMark m(p, asf::STAGE_FFT2, s);
         e = asf::launch_fft_pass2(p->sh2, log2i(p->sh1.batch), split, p->mid, static_cast<float2 *>(u2),
-                                  p->twx, p->w16, p->dx, p->dy, p->lay.mx, p->lay.my, s);
+                                  p->twx, p->w16, p->dx, p->dy, p->lay.mx, p->lay.my, accumulate, s);
         if (e != hipSuccess) return hip_fail(e, "fft pass 2 launch");
     }
     return ASF_OK;
+}
+
+}  // namespace
+
+int asf_forward(asf_plan_t plan, const void *u1, void *u2, void *stream) {
+    return forward(plan, u1, u2, stream, 0);
+}
+
+int asf_forward_add(asf_plan_t plan, const void *u1, void *u2, void *stream) {
+    return forward(plan, u1, u2, stream, 1);
 }
 
 int asf_adjoint(asf_plan_t plan, const void *g2, void *g1, void *stream) {

@@ -26,6 +26,7 @@ struct GeoParams {
     double inv_lambda; // 1 / lambda
     double z0;
     double p2x, p2y;
+    double x0, y0;     // destination window centre (extra pre-phase -k (x x0 + y y0) / r0)
     int nfx, nfy;      // fine grid
     int w;             // spreading width (cells)
     int log_tile_x, log_tile_y; // tile edges (cells), as powers of two
@@ -71,7 +72,7 @@ hipError_t launch_fft_pass1(const FftShape &sh, int split16, const float2 *fine,
 // deconvolution and destination phase
 hipError_t launch_fft_pass2(const FftShape &sh, int log_panel, int split16, const float2 *mid,
                             float2 *u2, const float2 *tw, const float2 *w16, const float2 *dx,
-                            const float2 *dy, int mx, int my, hipStream_t s);
+                            const float2 *dy, int mx, int my, int accumulate, hipStream_t s);
 // adjoint: rows of g2 (pre-corrected, zero-padded) -> mid (my x nfx, row-major)
 hipError_t launch_fft_adj_rows(int len, int split16, const float2 *g2, float2 *mid, const float2 *tw,
                                const float2 *w16, const float2 *dx, const float2 *dy, int mx, int my,

@@ -337,7 +337,8 @@ __global__ void __launch_bounds__(NT) fft_pass2_kernel(const float2 *__restrict_
                                                        const float2 *__restrict__ w16,
                                                        const float2 *__restrict__ dx,
                                                        const float2 *__restrict__ dy, int mx,
-                                                       int my, int log_panel, int xcd_group) {
+                                                       int my, int log_panel, int xcd_group,
+                                                       int accumulate) {
     using S = Len<LOGL>;
     extern __shared__ float2 lds[];
     __shared__ float scratch[NT / 64];
@@ -377,7 +378,13 @@ __global__ void __launch_bounds__(NT) fft_pass2_kernel(const float2 *__restrict_
         const int l = (ix - half) & (S::L - 1);
         float2 val = lds[c * S::STRIDE + lds_pos<S::PS>(l)];
         val = make_float2(val.x * unscale, val.y * unscale);
-        u2[(size_t)(row0 + c) * mx + ix] = cmul(cmul(val, dx[ix]), dy[row0 + c]);
+        float2 r = cmul(cmul(val, dx[ix]), dy[row0 + c]);
+        float2 *dst = u2 + (size_t)(row0 + c) * mx + ix;
+        if (accumulate) {
+            const float2 old = *dst;
+            r = make_float2(old.x + r.x, old.y + r.y);
+        }
+        *dst = r;
     }
 }
 
@@ -529,7 +536,7 @@ hipError_t launch1(const FftShape &sh, const float2 *fine, float2 *mid, const fl
 template <int LOGL, int BATCH, bool SPLIT>
 hipError_t launch2(const FftShape &sh, const float2 *mid, float2 *u2, const float2 *tw,
                    const float2 *w16, const float2 *dx, const float2 *dy, int mx, int my,
-                   int log_panel, hipStream_t s) {
+                   int log_panel, int accumulate, hipStream_t s) {
     constexpr int NT = threads_for<LOGL, BATCH>();
     const size_t lds = (size_t)BATCH * Len<LOGL>::STRIDE * sizeof(float2);
     static thread_local size_t enabled = 0;
@@ -542,7 +549,7 @@ hipError_t launch2(const FftShape &sh, const float2 *mid, float2 *u2, const floa
     const int g = rows_per_line > BATCH ? rows_per_line / BATCH : 1;
     const int xcd_group = (g > 1 && groups % (8 * g) == 0) ? g : 1;
     hipLaunchKernelGGL(k, dim3(groups), dim3(NT), lds, s, mid, u2, tw, w16, dx, dy, mx, my, log_panel,
-                       xcd_group);
+                       xcd_group, accumulate);
     return hipGetLastError();
 }
 
@@ -638,19 +645,19 @@ hipError_t dispatch1(const FftShape &sh, const float2 *fine, float2 *mid, const 
 template <bool SPLIT>
 hipError_t dispatch2(const FftShape &sh, int log_panel, const float2 *mid, float2 *u2, const float2 *tw,
                      const float2 *w16, const float2 *dx, const float2 *dy, int mx, int my,
-                     hipStream_t s) {
+                     int accumulate, hipStream_t s) {
     const int log = __builtin_ctz(sh.L);
     switch (log) {
-        case 5: return launch2<5, 8, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
-        case 6: return launch2<6, 4, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
-        case 7: return launch2<7, 2, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
-        case 8: return launch2<8, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
-        case 9: return launch2<9, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
-        case 10: return launch2<10, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
-        case 11: return launch2<11, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
-        case 12: return launch2<12, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
-        case 13: return launch2<13, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
-        case 14: return launch2<14, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, s);
+        case 5: return launch2<5, 8, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
+        case 6: return launch2<6, 4, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
+        case 7: return launch2<7, 2, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
+        case 8: return launch2<8, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
+        case 9: return launch2<9, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
+        case 10: return launch2<10, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
+        case 11: return launch2<11, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
+        case 12: return launch2<12, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
+        case 13: return launch2<13, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
+        case 14: return launch2<14, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -702,9 +709,9 @@ hipError_t launch_fft_pass1(const FftShape &sh, int split16, const float2 *fine,
 
 hipError_t launch_fft_pass2(const FftShape &sh, int log_panel, int split16, const float2 *mid,
                             float2 *u2, const float2 *tw, const float2 *w16, const float2 *dx,
-                            const float2 *dy, int mx, int my, hipStream_t s) {
-    if (split16) return dispatch2<true>(sh, log_panel, mid, u2, tw, w16, dx, dy, mx, my, s);
-    return dispatch2<false>(sh, log_panel, mid, u2, tw, w16, dx, dy, mx, my, s);
+                            const float2 *dy, int mx, int my, int accumulate, hipStream_t s) {
+    if (split16) return dispatch2<true>(sh, log_panel, mid, u2, tw, w16, dx, dy, mx, my, accumulate, s);
+    return dispatch2<false>(sh, log_panel, mid, u2, tw, w16, dx, dy, mx, my, accumulate, s);
 }
 
 hipError_t launch_fft_adj_rows(int len, int split16, const float2 *g2, float2 *mid, const float2 *tw,

@@ -4,6 +4,7 @@
 //
 // For point j with r0 = z0 - d1 (Eq. (4)):
 //   phi_j  = k (-d_j + |x_j|^2 / (2 r0_j)) + arg u_I,j        (pre-phase, Eq. (7)/(8))
+//            - k (x_j x0 + y_j y0) / r0_j                  (destination window centred at x0, y0)
 //   xi_j   = p2 x_j / (lambda r0_j)                           (cycles per destination pixel)
 // With the normal plane wave u_I = exp(i k d1) the -k d1 term and the incident
 // phase cancel exactly, so the kernel forms phi = k |x|^2 / (2 r0) directly and
@@ -252,6 +253,8 @@ __global__ void __launch_bounds__(kGeoThreads) bin_scatter_kernel(GeoParams g, B
             // phi / (2 pi) = k (|x|^2 / (2 r0) [- d]) / (2 pi) = |x|^2 s / 2 [- d / lambda]
             double rev = 0.5 * p[k].s * (xv[k] * xv[k] + yv[k] * yv[k]);
             if (!g.plane) rev -= dv[k] * g.inv_lambda;
+            // off-axis window: -k (x x0 + y y0) / r0 = -2 pi (x x0 + y y0) s
+            rev -= (xv[k] * g.x0 + yv[k] * g.y0) * p[k].s;
             const float t = (float)(rev - rint(rev));   // exact in FP64, then one rounding
             float sn, cs;
             sincospif(2.f * t, &sn, &cs);

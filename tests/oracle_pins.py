@@ -21,6 +21,10 @@ re-typing the oracle's formula, and returns (error, bound):
 * ``single_point``: |u2| = |u1| / (lambda z0) everywhere;
 * ``adjoint_dot_*``: <A u, g> = <u, A^H g> for random u, g, against the
   (independently pinned) forward -- true for the adjoint and no other map;
+* ``window_*``: an off-axis destination window (centre x0, y0) -- a whole-pixel
+  offset is the same sum at shifted pixel indices; a tilted Gaussian beam
+  seen through a window centred near its landing point matches the closed form
+  at the window's coordinates; the adjoint with a window passes the dot test;
 * ``adjoint_centred_dft``: on the centred-DFT geometry A = P F C with diagonal
   pre- and post-phases, so A^H g = conj(C) F^H (conj(P) g) with F^H the
   unnormalised inverse DFT (numpy.fft).
@@ -253,6 +257,48 @@ def adjoint_centred_dft(incident, lib=None):
     return rel_l2(got, np.conj(pre) * t), 5e-10
 
 
+def window_integer_shift(lib=None):
+    w = synth.config("sinusoid_128", side=20, out=16)
+    a, b = 3, -2
+    ix, iy = np.meshgrid(np.arange(w.mx), np.arange(w.my))
+    ix, iy = ix.reshape(-1), iy.reshape(-1)
+    got = oracle.direct(w.x, w.y, w.d, w.u, w.lam, w.z0, w.p2x, w.p2y, w.mx, w.my, ix, iy,
+                        lib=lib, x0=a * w.p2x, y0=b * w.p2y)
+    want = oracle.direct(w.x, w.y, w.d, w.u, w.lam, w.z0, w.p2x, w.p2y, w.mx, w.my, ix + a, iy + b,
+                         lib=lib)
+    # X formed as x0 + p2x (ix - m/2) or as p2x (ix + a - m/2): ulp-level phase differences
+    return rel_l2(got, want), 1e-11
+
+
+def window_offset_gaussian(lib=None):
+    lam, z0, c = 532e-9, 0.1, 10e-6
+    r0 = z0 - c
+    tilt = (3e-3, -2e-3)                       # lands near (0.27 mm, -0.18 mm)
+    x, y, u = gaussian_source(128, 160, 8e-6, 6.4e-6, 80e-6, 100e-6, tilt=tilt, lam=lam)
+    mx, my, p2x, p2y = 100, 80, 10e-6, 12e-6
+    x0, y0 = 0.2637e-3, -0.1743e-3            # not a whole number of pixels
+    got = oracle.direct_grid(x, y, np.full_like(x, c), u, lam, z0, p2x, p2y, mx, my,
+                             incident="none", lib=lib, x0=x0, y0=y0) * 8e-6 * 6.4e-6
+    X, Y = dest_xy(mx, my, p2x, p2y)
+    X, Y = X + x0, Y + y0
+    want = flat_surface_factor(X, Y, z0, r0, lam) * beam_2d(X, Y, 80e-6, 100e-6, lam, r0, tilt)
+    return rel_l2(got, want.reshape(my, mx)), 1e-9
+
+
+def window_adjoint_dot(lib=None):
+    w = synth.config("sinusoid_128", side=10, out=8)
+    rng = np.random.default_rng(13)
+    x0, y0 = 0.41e-3, -0.23e-3
+    ix, iy = np.meshgrid(np.arange(w.mx), np.arange(w.my))
+    u = rng.standard_normal(w.n) + 1j * rng.standard_normal(w.n)
+    g = rng.standard_normal((w.my, w.mx)) + 1j * rng.standard_normal((w.my, w.mx))
+    au = oracle.direct(w.x, w.y, w.d, u, w.lam, w.z0, w.p2x, w.p2y, w.mx, w.my,
+                       ix.reshape(-1), iy.reshape(-1), lib=lib, x0=x0, y0=y0)
+    ahg = oracle.adjoint(w.x, w.y, w.d, g, w.lam, w.z0, w.p2x, w.p2y, lib=lib, x0=x0, y0=y0)
+    lhs, rhs = np.vdot(g.reshape(-1), au), np.vdot(ahg, u)
+    return abs(lhs - rhs) / (np.linalg.norm(au) * np.linalg.norm(g)), 1e-9
+
+
 PINS = {
     "centred_dft_flat_none": lambda lib=None: centred_dft(0.0, "none", lib),
     "centred_dft_raised_none": lambda lib=None: centred_dft(20e-6, "none", lib),
@@ -264,6 +310,9 @@ PINS = {
     "separable": separable,
     "plane_identity": plane_identity,
     "single_point": single_point,
+    "window_integer_shift": window_integer_shift,
+    "window_offset_gaussian": window_offset_gaussian,
+    "window_adjoint_dot": window_adjoint_dot,
     "adjoint_dot_plane": lambda lib=None: adjoint_dot("plane", lib),
     "adjoint_dot_none": lambda lib=None: adjoint_dot("none", lib),
     "adjoint_centred_dft_plane": lambda lib=None: adjoint_centred_dft("plane", lib),

@@ -61,12 +61,14 @@ def test_workspace_bytes_layout(asf):
     (dict(mx=100), "ESIZE"),
     (dict(my=8), "ESIZE"),
     (dict(mx=16384), "ESIZE"),
+    (dict(x0=float("inf")), "EINVAL"),
+    (dict(y0=float("nan")), "EINVAL"),
 ])
 def test_bad_parameters_rejected(asf, kw, code):
-    args = dict(lam=532e-9, z0=0.2, p2x=8e-6, p2y=8e-6, mx=64, my=64, tol=1e-5)
+    args = dict(lam=532e-9, z0=0.2, p2x=8e-6, p2y=8e-6, mx=64, my=64, tol=1e-5, x0=0.0, y0=0.0)
     args.update(kw)
     p = asf.asf.Params(args["lam"], args["z0"], args["p2x"], args["p2y"], args["mx"], args["my"],
-                       args["tol"], 0)
+                       args["tol"], 0, args["x0"], args["y0"])
     assert asf.lib().asf_workspace_bytes(100, ctypes.byref(p)) == 0
     msg = asf.last_error()
     assert msg

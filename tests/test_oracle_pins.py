@@ -82,6 +82,10 @@ MUTANTS = {
     "centre_off_by_one": ("(double)(ix[e] - mx / 2)", "(double)(ix[e] - (mx - 1) / 2)"),
     "incident_sign": ("arg += k * d[j];", "arg -= k * d[j];"),
     "prefactor_lambda": ("1.0 / (lambda * z0)", "1.0 / (lambda * 0.1)"),
+    "window_offset_sign": ("const double X = x0 + p2x * (double)(ix[e] - mx / 2);",
+                           "const double X = -x0 + p2x * (double)(ix[e] - mx / 2);"),
+    "window_offset_dropped": ("const double Y = y0 + p2y * (double)(iy[e] - my / 2);",
+                              "const double Y = p2y * (double)(iy[e] - my / 2);"),
     # mistakes in the adjoint alone
     "adjoint_not_conjugated": ("sr += c * gr + s * gi;", "sr += c * gr - s * gi;"),
     "adjoint_prefactor_sign": ("out[2 * e] = -a * si;", "out[2 * e] = a * si;"),
