@@ -14,6 +14,13 @@ It is written in C (``asf_oracle.c``) and parallel over pixels with OpenMP.
 way (one sincos per term, parallel over source points): the backward of the
 forward with respect to u1.
 
+``surface`` evaluates the two direct sums that precede Eq. (7): Eq. (5)
+(Fresnel on the surface, before the output-chirp approximation) and Eq. (2)-(3)
+(the Huygens sum on the surface, no expansion of r).  ``line`` evaluates the
+one-dimensional forms of Eq. (7), (5) and (2) used by the paper's profiles
+(Sec. 3), read as a surface that does not vary along y (the y integral done
+analytically; see ``asf_oracle.c``).  These serve the approximation study.
+
 ``mp_direct`` is the same definition at 50 significant digits with mpmath, for
 tiny inputs only: it checks the FP64 rounding of ``direct``, not its formula.
 The formula itself is pinned by the tests in ``tests/test_oracle_pins.py``
@@ -22,7 +29,8 @@ matrix form, invariants).
 
 Readings of the paper taken here: the x1.x2 term carries a minus sign (Eq. (4),
 (5), (9); Eq. (7) prints a plus); unit quadrature weights; destination pixel
-(ix, iy) at X = p2x (ix - mx // 2), Y = p2y (iy - my // 2).
+(ix, iy) at X = x0 + p2x (ix - mx // 2), Y = y0 + p2y (iy - my // 2), with the
+window centre (x0, y0) = 0 unless given.
 """
 from __future__ import annotations
 
@@ -69,6 +77,13 @@ def load_library(path: str):
         ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
         ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+    lib.asf_oracle_surface.restype = ctypes.c_int
+    lib.asf_oracle_surface.argtypes = [ctypes.c_int32] + lib.asf_oracle_direct.argtypes
+    lib.asf_oracle_line.restype = ctypes.c_int
+    lib.asf_oracle_line.argtypes = [
+        ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+        ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
     lib.asf_oracle_threads.restype = ctypes.c_int
     lib.asf_oracle_threads.argtypes = [ctypes.c_int32]
     return lib
@@ -115,6 +130,67 @@ def direct(x, y, d, u, lam, z0, p2x, p2y, mx, my, ix, iy, incident="plane", nthr
         n, x.ctypes.data, y.ctypes.data, d.ctypes.data, u.ctypes.data,
         float(lam), float(z0), float(p2x), float(p2y), float(x0), float(y0), int(mx), int(my),
         INCIDENT[incident], ix.shape[0], ix.ctypes.data, iy.ctypes.data,
+        out.ctypes.data, int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle: invalid arguments or r0 = z0 - d1 <= 0")
+    return out.view(np.complex128)
+
+
+SURFACE_MODELS = {"eq5": 5, "eq2": 2}
+LINE_MODELS = {"eq7": 7, "eq5": 5, "eq2": 2}
+
+
+def surface(model, x, y, d, u, lam, z0, p2x, p2y, mx, my, ix=None, iy=None, incident="plane",
+            nthreads=0, lib=None, x0=0.0, y0=0.0):
+    """u2 by Eq. (5) (``model="eq5"``) or the Huygens sum Eq. (2)-(3) (``"eq2"``).
+
+    Arguments as for ``direct``; ix, iy default to the whole grid, in which case
+    the result has shape (my, mx), else (n_eval,).
+    """
+    lib = _load() if lib is None else lib
+    whole = ix is None
+    if whole:
+        gx, gy = np.meshgrid(np.arange(mx), np.arange(my))
+        ix, iy = gx.reshape(-1), gy.reshape(-1)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.complex128)
+    ix = np.ascontiguousarray(ix, dtype=np.int32).reshape(-1)
+    iy = np.ascontiguousarray(iy, dtype=np.int32).reshape(-1)
+    n = x.shape[0]
+    if not (y.shape[0] == n and d.shape[0] == n and u.shape[0] == n) or ix.shape != iy.shape:
+        raise ValueError("x, y, d, u (and ix, iy) must have equal length")
+    out = np.empty(2 * ix.shape[0], dtype=np.float64)
+    rc = lib.asf_oracle_surface(
+        SURFACE_MODELS[model], n, x.ctypes.data, y.ctypes.data, d.ctypes.data, u.ctypes.data,
+        float(lam), float(z0), float(p2x), float(p2y), float(x0), float(y0), int(mx), int(my),
+        INCIDENT[incident], ix.shape[0], ix.ctypes.data, iy.ctypes.data, out.ctypes.data,
+        int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle: invalid arguments or r0 = z0 - d1 <= 0")
+    vals = out.view(np.complex128)
+    return vals.reshape(my, mx) if whole else vals
+
+
+def line(model, x, d, u, lam, z0, p2, m, ix=None, incident="plane", nthreads=0, lib=None, x0=0.0):
+    """One-dimensional u2 at pixels ix (default: all m) by Eq. (7), (5) or (2) read in 1D.
+
+    x, d: float64 [n] (m); u: complex [n]; pixel ix at X = x0 + p2 (ix - m // 2).
+    Returns complex128 [len(ix)].
+    """
+    lib = _load() if lib is None else lib
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.complex128)
+    ix = np.arange(m, dtype=np.int32) if ix is None else np.ascontiguousarray(ix, dtype=np.int32).reshape(-1)
+    n = x.shape[0]
+    if not (d.shape[0] == n and u.shape[0] == n):
+        raise ValueError("x, d, u must have equal length")
+    out = np.empty(2 * ix.shape[0], dtype=np.float64)
+    rc = lib.asf_oracle_line(
+        LINE_MODELS[model], n, x.ctypes.data, d.ctypes.data, u.ctypes.data, float(lam), float(z0),
+        float(p2), float(x0), int(m), INCIDENT[incident], ix.shape[0], ix.ctypes.data,
         out.ctypes.data, int(nthreads))
     if rc != 0:
         raise ValueError("oracle: invalid arguments or r0 = z0 - d1 <= 0")

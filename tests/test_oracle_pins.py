@@ -4,8 +4,9 @@ The pins themselves (and why each is independent of the oracle's formula) are
 in ``oracle_pins.py``.  ``test_planted_mistakes`` compiles variants of the
 oracle's C source with one plausible error each -- the plus sign printed in
 Eq. (7), z0 in place of r0, a dropped term, x and y swapped, a conjugated
-product, an off-by-one pixel centre -- and requires every variant to fail at
-least one pin.
+product, an off-by-one pixel centre, and in the Huygens sum, Eq. (5) and the 1D
+forms a wrong distance, power, prefactor or sign -- and requires every variant
+to fail at least one pin.
 """
 import os
 import subprocess
@@ -86,6 +87,24 @@ MUTANTS = {
                            "const double X = -x0 + p2x * (double)(ix[e] - mx / 2);"),
     "window_offset_dropped": ("const double Y = y0 + p2y * (double)(iy[e] - my / 2);",
                               "const double Y = p2y * (double)(iy[e] - my / 2);"),
+    # mistakes in Eq. (5) and the Huygens sum, Eq. (2)-(3)
+    "eq5_output_chirp_z0": ("- (x[j] * X + y[j] * Y) / r0 + (X * X + Y * Y) / (2.0 * r0));",
+                            "- (x[j] * X + y[j] * Y) / r0 + (X * X + Y * Y) / (2.0 * z0));"),
+    "eq2_r_with_z0": ("sqrt(dx * dx + dy * dy + r0 * r0);", "sqrt(dx * dx + dy * dy + z0 * z0);"),
+    "eq2_amplitude_1_over_r": ("amp = 1.0 / (r * r);", "amp = 1.0 / r;"),
+    "eq2_prefactor_without_z0": ("a = z0 / lambda;", "a = 1.0 / lambda;"),
+    "eq2_phase_sign": ("arg = k * r;", "arg = -k * r;"),
+    "eq2_dx_sign": ("const double dx = X - x[j], dy = Y - y[j];", "const double dx = X + x[j], dy = Y - y[j];"),
+    # mistakes in the one-dimensional forms
+    "line_prefactor_2d_form": ("a = 1.0 / sqrt(lambda * z0);", "a = 1.0 / (lambda * z0);"),
+    "line_no_quarter_turn": ("phase = k * (z0 + X * X / (2.0 * z0)) - pi / 4.0;",
+                             "phase = k * (z0 + X * X / (2.0 * z0));"),
+    "line_eq5_chirp_z0": ("+ X * X / (2.0 * r0));", "+ X * X / (2.0 * z0));"),
+    "line_cross_term_plus": ("- x[j] * X / r0", "+ x[j] * X / r0"),
+    "line_centre_off_by_one": ("(double)(ix[e] - m / 2)", "(double)(ix[e] - (m - 1) / 2)"),
+    "line_eq2_power": ("amp = 1.0 / (rho * sqrt(rho));", "amp = 1.0 / (rho * rho);"),
+    "line_eq2_rho_with_z0": ("sqrt(dx * dx + r0 * r0);", "sqrt(dx * dx + z0 * z0);"),
+    "line_eq2_no_quarter_turn": ("phase = -pi / 4.0;", "phase = 0.0;"),
     # mistakes in the adjoint alone
     "adjoint_not_conjugated": ("sr += c * gr + s * gi;", "sr += c * gr - s * gi;"),
     "adjoint_prefactor_sign": ("out[2 * e] = -a * si;", "out[2 * e] = a * si;"),
@@ -108,11 +127,11 @@ def _build_mutant(tmp_path, name, old, new):
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_planted_mistakes(tmp_path, name):
+    """Each variant must fail some pin (the pins run until the first that fails)."""
     old, new = MUTANTS[name]
     lib = _build_mutant(tmp_path, name, old, new)
-    failed = []
     for pin, fn in PINS.items():
         err, bound = fn(lib=lib)
         if not err < bound:
-            failed.append(pin)
-    assert failed, f"planted mistake {name} passed every pin"
+            return
+    raise AssertionError(f"planted mistake {name} passed every pin")
