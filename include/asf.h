@@ -10,7 +10,7 @@
  *
  * with k = 2 pi / lambda, r0_j = z0 - d_j, u_I,j = exp(i k d_j) (normal plane
  * wave, the default) or 1, and the destination pixel (ix, iy) at
- * X = p2x (ix - mx/2), Y = p2y (iy - my/2).  The sum is a 2D type-1
+ * X = x0 + p2x (ix - mx/2), Y = y0 + p2y (iy - my/2).  The sum is a 2D type-1
  * (non-uniform to uniform) Fourier transform of Eq. (9) with per-point
  * frequencies x_j / (lambda r0_j) (Eq. (8)); the library computes it as a
  * non-uniform FFT: an exponential-of-semicircle spreading onto a 2x oversampled
@@ -200,6 +200,79 @@ int asf_stage_times(asf_plan_t plan, double *ms, int n);
 
 /* Release the plan (host memory and events; the workspace stays the caller's). */
 int asf_destroy(asf_plan_t plan);
+
+/* ---- one-dimensional profiles ---------------------------------------------- */
+
+/*
+ * The same method for a line source: sample positions x1 along one axis with
+ * displacement d1(x1), onto a line of m destination pixels -- the setting of
+ * the paper's profiles (Sec. 3: tilted facets, a quadratic curve).  The paper
+ * gives the 1D form only by example; it is taken as Eq. (7) for a surface and
+ * field that do not vary along y, with the y integral done analytically and
+ * its amplitude r0 -> z0 as in the 2D amplitude approximation:
+ *
+ *   u2(X) = exp(i k (z0 + X^2 / (2 z0))) / sqrt(i lambda z0)
+ *         * sum_j u1_j u_I,j exp(i k [ -d_j + x_j^2 / (2 r0_j) - x_j X / r0_j ])
+ *
+ * with X = x0 + p2 (ix - m/2).  Computed as a 1D type-1 NUFFT (same kernel,
+ * width and 2x oversampling as the 2D path), one workgroup per field.
+ */
+typedef struct asf_line_s *asf_line_t;
+
+/*
+ * Parameters of a line plan.
+ *   lambda, z0, p2  wavelength, distance, destination pitch (m), finite and > 0
+ *   x0              destination window centre (m), finite
+ *   m               destination pixels, a power of two in [16, 8192]
+ *   tol             requested relative L2 accuracy in [1e-7, 1e-1] (w as for asf_params)
+ *   flags           0 or ASF_INCIDENT_NONE
+ */
+typedef struct {
+    double lambda, z0, p2, x0;
+    int32_t m;
+    double tol;
+    uint32_t flags;
+} asf_line_params;
+
+/* Largest number of source points of a line plan. */
+#define ASF_LINE_MAX_POINTS 16384
+
+/*
+ * Bytes of device workspace a line plan for n_src points needs (host only).
+ * Returns 0 if the arguments are invalid (n_src outside [1, ASF_LINE_MAX_POINTS],
+ * bad parameters; see asf_last_error()).
+ */
+size_t asf_line_workspace_bytes(int64_t n_src, const asf_line_params *p);
+
+/*
+ * Create a line plan: FP64 host tables (deconvolution with the 1D destination
+ * phase, FFT twiddles) and one workgroup that forms each point's pre-phase and
+ * frequency in FP64 (as the 2D geometry kernels do) and sorts the points by
+ * their first fine cell.  Synchronises `stream` once to read the status word.
+ *   out        receives the handle (host pointer)
+ *   n_src      points, in [1, ASF_LINE_MAX_POINTS]
+ *   x1, d1     FP64 [n_src] device arrays (m); read during the call only
+ *   p          host pointer to parameters (copied)
+ *   workspace  device buffer of >= asf_line_workspace_bytes(n_src, p) bytes,
+ *              256-byte aligned, caller-owned, alive until asf_line_destroy
+ * Returns ASF_OK, ASF_EINVAL, ASF_ESIZE, ASF_ENOMEM, ASF_EHIP, or ASF_EDOMAIN if
+ * some r0 <= 0 or a coordinate is non-finite (then *out is NULL).
+ */
+int asf_line_plan(asf_line_t *out, int64_t n_src, const double *x1, const double *d1,
+                  const asf_line_params *p, void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * Forward transform of `batch` fields through the same line geometry.
+ *   u1  complex64 [batch][n_src] device array (interleaved re, im)
+ *   u2  complex64 [batch][m] device array; pixel ix of field b at u2[b m + ix]
+ * batch >= 1.  Asynchronous on `stream`.  The result does not depend on the
+ * batch or on other fields (each field is summed in a fixed order: bitwise
+ * repeatable).  Returns ASF_OK, ASF_EINVAL or ASF_EHIP.
+ */
+int asf_line_forward(asf_line_t plan, int32_t batch, const void *u1, void *u2, void *stream);
+
+/* Release a line plan (host memory only). */
+int asf_line_destroy(asf_line_t plan);
 
 /* Message of the calling thread's last failure ("" if none). */
 const char *asf_last_error(void);

@@ -57,6 +57,14 @@ class Info(ctypes.Structure):
                 ("ws_bytes", ctypes.c_size_t)]
 
 
+class LineParams(ctypes.Structure):
+    _fields_ = [("lam", ctypes.c_double), ("z0", ctypes.c_double), ("p2", ctypes.c_double),
+                ("x0", ctypes.c_double), ("m", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("flags", ctypes.c_uint32)]
+
+
+LINE_MAX_POINTS = 16384
+
 _lib = None
 
 
@@ -92,6 +100,15 @@ def lib():
         L.asf_stage_times.argtypes = [vp, ctypes.POINTER(dbl), i32]
         L.asf_destroy.restype = i32
         L.asf_destroy.argtypes = [vp]
+        L.asf_line_workspace_bytes.restype = ctypes.c_size_t
+        L.asf_line_workspace_bytes.argtypes = [i64, ctypes.POINTER(LineParams)]
+        L.asf_line_plan.restype = i32
+        L.asf_line_plan.argtypes = [ctypes.POINTER(vp), i64, vp, vp, ctypes.POINTER(LineParams), vp,
+                                    ctypes.c_size_t, vp]
+        L.asf_line_forward.restype = i32
+        L.asf_line_forward.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
+        L.asf_line_destroy.restype = i32
+        L.asf_line_destroy.argtypes = [vp]
         L.asf_last_error.restype = ctypes.c_char_p
         L.asf_last_error.argtypes = []
         _lib = L
@@ -195,13 +212,13 @@ class Plan:
             raise TypeError(f"u1 must be a complex64 tensor on {self.device}")
         if u1.numel() != self.n or not u1.is_contiguous():
             raise ValueError(f"u1 must be contiguous with {self.n} elements")
+        if accumulate and out is None:
+            raise ValueError("accumulate=True needs the out tensor to add into")
         if out is None:
             out = torch.empty((self.my, self.mx), dtype=torch.complex64, device=self.device)
         elif (out.dtype != torch.complex64 or out.device != self.device or out.numel() != self.mx * self.my
               or not out.is_contiguous()):
             raise ValueError("out must be a contiguous complex64 [my, mx] tensor on the plan's device")
-        if accumulate and out is None:
-            raise ValueError("accumulate=True needs the out tensor to add into")
         fn = lib().asf_forward_add if accumulate else lib().asf_forward
         _check(fn(self._h, u1.data_ptr(), out.data_ptr(), _stream_ptr(torch, self.device, stream)))
         return out
@@ -247,6 +264,80 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None):
             lib().asf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_line_params(lam, z0, p2, m, tol=1e-5, incident="plane", x0=0.0) -> LineParams:
+    if incident not in ("plane", "none"):
+        raise ValueError(f"incident must be 'plane' or 'none', got {incident!r}")
+    flags = ASF_INCIDENT_NONE if incident == "none" else 0
+    return LineParams(float(lam), float(z0), float(p2), float(x0), int(m), float(tol), flags)
+
+
+def line_workspace_bytes(n_src, params: LineParams) -> int:
+    b = lib().asf_line_workspace_bytes(int(n_src), ctypes.byref(params))
+    if b == 0:
+        raise AsfError(ASF_EINVAL, last_error())
+    return int(b)
+
+
+class LinePlan:
+    """A one-dimensional plan (the paper's profiles): a line source x1 with
+    displacement d1 onto m destination pixels at X = x0 + p2 (ix - m/2).
+
+    x1, d1: float64 device tensors [n] (m), n <= LINE_MAX_POINTS; optics lam, z0;
+    tol sets the spreading width; incident is "plane" or "none".
+    """
+
+    def __init__(self, x1, d1, lam, z0, p2, m, tol=1e-5, incident="plane", x0=0.0, stream=None):
+        import torch
+
+        self._torch = torch
+        self.device = x1.device
+        if self.device.type != "cuda":
+            raise TypeError("x1 must be a GPU tensor")
+        n = x1.numel()
+        for t, name in ((x1, "x1"), (d1, "d1")):
+            _dev_f64(torch, t, name, n, self.device)
+        self.n, self.m = n, int(m)
+        self.params = make_line_params(lam, z0, p2, m, tol, incident, x0)
+        nbytes = line_workspace_bytes(n, self.params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        _check(lib().asf_line_plan(ctypes.byref(h), n, x1.data_ptr(), d1.data_ptr(),
+                                   ctypes.byref(self.params), self.workspace.data_ptr(), nbytes,
+                                   _stream_ptr(torch, self.device, stream)))
+        self._h = h
+
+    def forward(self, u1, out=None, stream=None):
+        """u2 (complex64 [m], or [batch, m]) from u1 (complex64 [n] or [batch, n])."""
+        torch = self._torch
+        if not isinstance(u1, torch.Tensor) or u1.dtype != torch.complex64 or u1.device != self.device:
+            raise TypeError(f"u1 must be a complex64 tensor on {self.device}")
+        if u1.shape[-1] != self.n or u1.dim() not in (1, 2) or not u1.is_contiguous():
+            raise ValueError(f"u1 must be contiguous [n] or [batch, n] with n = {self.n}")
+        batch = 1 if u1.dim() == 1 else u1.shape[0]
+        shape = (self.m,) if u1.dim() == 1 else (batch, self.m)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.complex64, device=self.device)
+        elif (out.dtype != torch.complex64 or out.device != self.device or tuple(out.shape) != shape
+              or not out.is_contiguous()):
+            raise ValueError(f"out must be a contiguous complex64 {shape} tensor on the plan's device")
+        if batch == 0:
+            return out
+        _check(lib().asf_line_forward(self._h, batch, u1.data_ptr(), out.data_ptr(),
+                                      _stream_ptr(torch, self.device, stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().asf_line_destroy(self._h)
             self._h = None
 
     def __del__(self):

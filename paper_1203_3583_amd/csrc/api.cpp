@@ -566,3 +566,174 @@ int asf_destroy(asf_plan_t plan) {
 }
 
 }  // extern "C"
+
+// ---- one-dimensional (line) plans ----------------------------------------------------
+//
+// Tables built in FP64 and rounded once to complex64:
+//   D[ix] = exp(i k (z0 + X^2 / (2 z0))) / sqrt(i lambda z0) / psi_hat(k),  X = x0 + p2 k,
+//   k = ix - m/2 (the 1D post-phase: the 2D prefactor 1/(i lambda z0) with one
+//   axis integrated out, sqrt(i lambda z0) of the Fresnel chirp integral);
+//   tw[e] = exp(-2 pi i e / nf), e < nf/2 (radix-2 stages).
+
+struct asf_line_s {
+    asf_line_params prm;
+    asf::LineGeo geo;
+    asf::LineBins bin;
+    float2 *tw, *dd;
+};
+
+namespace {
+
+struct LineLayout {
+    int n, m, nf, w;
+    double beta;
+    size_t off_status, off_first, off_perm, off_off, off_phase, off_tw, off_dd, total;
+};
+
+int make_line_layout(int64_t n, const asf_line_params *p, LineLayout &L) {
+    if (!p) return fail(ASF_EINVAL, "params is NULL");
+    if (n < 1 || n > asf::kLineMaxPoints)
+        return fail(ASF_EINVAL, "n_src must be in [1, %d], got %lld", asf::kLineMaxPoints, (long long)n);
+    const double v[3] = {p->lambda, p->z0, p->p2};
+    const char *names[3] = {"lambda", "z0", "p2"};
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(v[i]) || !(v[i] > 0.0)) return fail(ASF_EINVAL, "%s must be finite and > 0", names[i]);
+    if (!std::isfinite(p->x0)) return fail(ASF_EINVAL, "x0 must be finite");
+    if (!std::isfinite(p->tol) || p->tol < 1e-7 || p->tol > 1e-1) return fail(ASF_EINVAL, "tol must be in [1e-7, 1e-1]");
+    if (p->flags & ~ASF_INCIDENT_NONE) return fail(ASF_EINVAL, "unknown flag bits 0x%x", p->flags);
+    if (!is_pow2(p->m) || p->m < 16 || p->m > 8192)
+        return fail(ASF_ESIZE, "m must be a power of two in [16, 8192], got %d", p->m);
+    L.n = (int)n;
+    L.m = p->m;
+    L.nf = 2 * p->m;
+    L.w = spread_width(p->tol);
+    L.beta = 2.30 * L.w;
+    size_t o = 0;
+    auto take = [&o](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.off_status = take(kAlign);
+    L.off_first = take(sizeof(uint32_t) * (L.nf + 1));
+    L.off_perm = take(sizeof(uint32_t) * L.n);
+    L.off_off = take(sizeof(float) * L.n);
+    L.off_phase = take(sizeof(float2) * L.n);
+    L.off_tw = take(sizeof(float2) * (L.nf / 2));
+    L.off_dd = take(sizeof(float2) * L.m);
+    L.total = o;
+    return ASF_OK;
+}
+
+int upload_line_tables(asf_line_s *p, const LineLayout &L, hipStream_t s) {
+    const asf_line_params &q = p->prm;
+    const double k = 2.0 * kPi / q.lambda;
+    const std::vector<double> ph = psi_hat(L.m / 2, L.nf, L.w, L.beta);
+    std::vector<float2> dd(L.m), tw(L.nf / 2);
+    // 1 / sqrt(i lambda z0) = exp(-i pi/4) / sqrt(lambda z0)
+    const double amp = 1.0 / std::sqrt(q.lambda * q.z0);
+    for (int ix = 0; ix < L.m; ++ix) {
+        const int m = ix - L.m / 2;
+        const double X = q.x0 + q.p2 * m;
+        const double a = reduce(reduce(k * q.z0) + reduce(k * X * X / (2.0 * q.z0)) - 0.25 * kPi);
+        const double r = amp / ph[m < 0 ? -m : m];
+        dd[ix] = make_float2((float)(r * std::cos(a)), (float)(r * std::sin(a)));
+    }
+    for (int e = 0; e < L.nf / 2; ++e) {
+        const double a = 2.0 * kPi * e / L.nf;
+        tw[e] = make_float2((float)std::cos(a), (float)-std::sin(a));
+    }
+    hipError_t e = hipMemcpyAsync(p->dd, dd.data(), dd.size() * sizeof(float2), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "line table upload");
+    e = hipStreamSynchronize(s);   // the host vectors die here
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return ASF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t asf_line_workspace_bytes(int64_t n_src, const asf_line_params *p) {
+    LineLayout L;
+    if (make_line_layout(n_src, p, L) != ASF_OK) return 0;
+    return L.total;
+}
+
+int asf_line_plan(asf_line_t *out, int64_t n_src, const double *x1, const double *d1,
+                  const asf_line_params *p, void *workspace, size_t ws_bytes, void *stream) {
+    if (!out) return fail(ASF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!x1 || !d1 || !workspace) return fail(ASF_EINVAL, "x1, d1 and workspace must be non-NULL");
+    LineLayout L;
+    int rc = make_line_layout(n_src, p, L);
+    if (rc) return rc;
+    if (ws_bytes < L.total) return fail(ASF_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(ASF_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+    asf_line_s *pl = new (std::nothrow) asf_line_s();
+    if (!pl) return fail(ASF_EINVAL, "out of host memory");
+    pl->prm = *p;
+    char *w = static_cast<char *>(workspace);
+    pl->bin.status = reinterpret_cast<uint32_t *>(w + L.off_status);
+    pl->bin.first = reinterpret_cast<uint32_t *>(w + L.off_first);
+    pl->bin.perm = reinterpret_cast<uint32_t *>(w + L.off_perm);
+    pl->bin.off = reinterpret_cast<float *>(w + L.off_off);
+    pl->bin.phase = reinterpret_cast<float2 *>(w + L.off_phase);
+    pl->tw = reinterpret_cast<float2 *>(w + L.off_tw);
+    pl->dd = reinterpret_cast<float2 *>(w + L.off_dd);
+    pl->geo.inv_lambda = 1.0 / p->lambda;
+    pl->geo.z0 = p->z0;
+    pl->geo.p2 = p->p2;
+    pl->geo.x0 = p->x0;
+    pl->geo.n = L.n;
+    pl->geo.m = L.m;
+    pl->geo.nf = L.nf;
+    pl->geo.log_nf = log2i(L.nf);
+    pl->geo.w = L.w;
+    pl->geo.plane = (p->flags & ASF_INCIDENT_NONE) ? 0 : 1;
+    pl->geo.beta_log2e = (float)(L.beta * 1.4426950408889634);
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = upload_line_tables(pl, L, s);
+    if (!rc) {
+        // the status word starts at zero: a one-word copy from host memory, then the setup kernel
+        static const uint32_t zero = 0;
+        hipError_t e = hipMemcpyAsync(pl->bin.status, &zero, sizeof zero, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = asf::launch_line_setup(pl->geo, pl->bin, x1, d1, s);
+        if (e != hipSuccess) rc = hip_fail(e, "line setup");
+    }
+    if (!rc) {
+        uint32_t st = 0;
+        hipError_t e = hipMemcpyAsync(&st, pl->bin.status, sizeof st, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = hip_fail(e, "line status read");
+        else if (st & 1u) rc = fail(ASF_EDOMAIN, "some point has r0 = z0 - d1 <= 0 or a non-finite coordinate");
+    }
+    if (rc) {
+        delete pl;
+        return rc;
+    }
+    *out = pl;
+    return ASF_OK;
+}
+
+int asf_line_forward(asf_line_t plan, int32_t batch, const void *u1, void *u2, void *stream) {
+    if (!plan || !u1 || !u2) return fail(ASF_EINVAL, "plan, u1, u2 must be non-NULL");
+    if (batch < 1) return fail(ASF_EINVAL, "batch must be >= 1, got %d", batch);
+    hipError_t e = asf::launch_line_forward(plan->geo, plan->bin, plan->tw, plan->dd, batch,
+                                            static_cast<const float2 *>(u1), static_cast<float2 *>(u2),
+                                            static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "line forward launch");
+    return ASF_OK;
+}
+
+int asf_line_destroy(asf_line_t plan) {
+    if (!plan) return fail(ASF_EINVAL, "plan is NULL");
+    delete plan;
+    return ASF_OK;
+}
+
+}  // extern "C"

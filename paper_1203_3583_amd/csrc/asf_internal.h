@@ -50,6 +50,34 @@ struct FftShape {
     int batch;      // transforms per workgroup
 };
 
+// ---- one-dimensional (line) path -------------------------------------------------
+
+// Scalars of a line plan.
+struct LineGeo {
+    double inv_lambda; // 1 / lambda
+    double z0, p2, x0;
+    int n, m, nf, log_nf, w;
+    int plane;         // 1: u_I = exp(i k d1)
+    float beta_log2e;  // ES shape beta times log2(e)
+};
+
+// Points of a line plan sorted by first footprint cell (ties by index).
+struct LineBins {
+    uint32_t *status;  // [1] bit 0: domain error
+    uint32_t *first;   // [nf + 1] first sorted point whose footprint starts at cell c (or later)
+    uint32_t *perm;    // [n] caller index of sorted point j
+    float *off;        // [n] g - c - (w-1)/2, in [-1/2, 1/2]
+    float2 *phase;     // [n] exp(i phi_j)
+};
+
+constexpr int kLineMaxPoints = 16384;   // point index and first cell each fit 14 bits
+constexpr int kLineKeyBits = 14;
+
+hipError_t launch_line_setup(const LineGeo &g, const LineBins &b, const double *x, const double *d,
+                             hipStream_t s);
+hipError_t launch_line_forward(const LineGeo &g, const LineBins &b, const float2 *tw, const float2 *dd,
+                               int batch, const float2 *u1, float2 *u2, hipStream_t s);
+
 enum {
     STAGE_COUNT = 0, STAGE_SCAN, STAGE_SCATTER, STAGE_SPREAD, STAGE_FFT1, STAGE_FFT2,   // forward
     STAGE_ADJ_FFT2, STAGE_ADJ_FFT1, STAGE_INTERP,                                      // adjoint

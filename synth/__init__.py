@@ -33,6 +33,11 @@ __all__ = [
     "config",
     "CONFIG_NAMES",
     "sample_pixels",
+    "LineWorkload",
+    "facet_profile",
+    "quadratic_profile",
+    "line_config",
+    "LINE_CONFIG_NAMES",
 ]
 
 
@@ -200,3 +205,92 @@ def sample_pixels(mx: int, my: int, count: int, seed: int = 1):
     flat = rng.choice(mx * my, size=min(count, mx * my), replace=False)
     flat.sort()
     return (flat % mx).astype(np.int32), (flat // mx).astype(np.int32)
+
+
+# ---------------------------------------------------------------------------
+# One-dimensional profiles (a line source x1 with displacement d1(x1)), sampled
+# uniformly along the surface: equal arc length p between neighbours, so the
+# spacing in x1 shrinks to p |cos theta| where the surface is tilted by theta.
+# ---------------------------------------------------------------------------
+
+@dataclass
+class LineWorkload:
+    """One 1D problem: source samples along a profile, optics and destination line."""
+
+    name: str
+    x: np.ndarray          # float64 [n] source x1 (m)
+    d: np.ndarray          # float64 [n] displacement d1(x1) (m)
+    u: np.ndarray          # complex64 [n] source field u1
+    lam: float
+    z0: float
+    p2: float              # destination pitch (m)
+    m: int                 # destination pixels
+    tol: float = 1e-5
+    incident: str = "plane"
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+
+def facet_profile(angles_deg, points_per_facet: int, pitch: float):
+    """Consecutive planar facets tilted by ``angles_deg`` to the x1 axis, each with
+    ``points_per_facet`` samples at arc-length pitch ``pitch`` (samples at the
+    middle of each arc step, so joints fall between samples).  The profile is
+    continuous; it is shifted so that x1 and d1 both have mean zero.
+    Returns (x, d) float64 arrays in order along the profile."""
+    xs, ds = [], []
+    x_start = d_start = 0.0
+    for a in np.deg2rad(np.asarray(angles_deg, dtype=np.float64)):
+        t = pitch * (np.arange(points_per_facet) + 0.5)
+        xs.append(x_start + t * np.cos(a))
+        ds.append(d_start + t * np.sin(a))
+        x_start += points_per_facet * pitch * np.cos(a)
+        d_start += points_per_facet * pitch * np.sin(a)
+    x, d = np.concatenate(xs), np.concatenate(ds)
+    return x - x.mean(), d - d.mean()
+
+
+def _parabola_arc(x, a):
+    """Arc length of d = a x^2 from the vertex to x (signed)."""
+    t = 2.0 * a * x
+    return (x * np.sqrt(1.0 + t * t)) / 2.0 + np.arcsinh(t) / (4.0 * a)
+
+
+def quadratic_profile(n: int, pitch: float, a: float, newton_steps: int = 60):
+    """d1 = a x1^2 sampled at arc lengths pitch (i - (n-1)/2) from the vertex,
+    the x1 found by Newton's method on the closed-form arc length (ds/dx =
+    sqrt(1 + (2 a x)^2)).  Returns (x, d) float64."""
+    s_target = pitch * (np.arange(n) - (n - 1) / 2.0)
+    x = s_target.copy()
+    for _ in range(newton_steps):
+        x = x - (_parabola_arc(x, a) - s_target) / np.sqrt(1.0 + (2.0 * a * x) ** 2)
+    return x, a * x * x
+
+
+def _facets_1d(seed: int = 0, points: int = 128) -> LineWorkload:
+    """Four planar facets of 128 points tilted -30, -50, 0 and +50 degrees, 10 um
+    arc pitch, unit field, lambda = 633 nm, z0 = 1 m, 1024 destination pixels at 10 um."""
+    x, d = facet_profile((-30.0, -50.0, 0.0, 50.0), points, 10e-6)
+    u = np.ones(x.shape[0], dtype=np.complex64)
+    return LineWorkload("facets_1d", x, d, u, 633e-9, 1.0, 10e-6, 1024, 1e-5, "plane",
+                        {"points_per_facet": points})
+
+
+def _quadratic_1d(seed: int = 0, n: int = 1024, a: float = 100.0) -> LineWorkload:
+    """d1 = a x1^2 (a = 100 / m, slope about +-0.9 at the ends), 1024 points at
+    10 um arc pitch, unit field, lambda = 633 nm, z0 = 1 m, 1024 pixels at 10 um."""
+    x, d = quadratic_profile(n, 10e-6, a)
+    u = np.ones(n, dtype=np.complex64)
+    return LineWorkload("quadratic_1d", x, d, u, 633e-9, 1.0, 10e-6, 1024, 1e-5, "plane",
+                        {"a": a})
+
+
+_LINE_CONFIGS = {"facets_1d": _facets_1d, "quadratic_1d": _quadratic_1d}
+LINE_CONFIG_NAMES = tuple(_LINE_CONFIGS)
+
+
+def line_config(name: str, **kw) -> LineWorkload:
+    """Build a named 1D profile (keyword overrides go to its generator)."""
+    return _LINE_CONFIGS[name](**kw)

@@ -30,7 +30,8 @@ def asf():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("asf_plan", "asf_forward", "asf_adjoint", "asf_destroy", "asf_workspace_bytes",
-                     "asf_last_error", "asf_setpts", "asf_status"):
+                     "asf_last_error", "asf_setpts", "asf_status", "asf_forward_add",
+                     "asf_line_plan", "asf_line_forward", "asf_line_destroy", "asf_line_workspace_bytes"):
         assert required in names
 
 
@@ -98,6 +99,51 @@ def test_null_pointers_and_small_workspace(asf):
         assert getattr(lib, fn)(None, None, None, None) in (asf.asf.ASF_EINVAL, asf.asf.ASF_ENOSYS)
     assert lib.asf_destroy(None) == asf.asf.ASF_EINVAL
     assert lib.asf_setpts(None, None, None, None, None) == asf.asf.ASF_EINVAL
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(lam=0.0), "EINVAL"),
+    (dict(z0=-1.0), "EINVAL"),
+    (dict(p2=float("inf")), "EINVAL"),
+    (dict(x0=float("nan")), "EINVAL"),
+    (dict(tol=1.0), "EINVAL"),
+    (dict(m=100), "ESIZE"),
+    (dict(m=8), "ESIZE"),
+    (dict(m=16384), "ESIZE"),
+    (dict(n=0), "EINVAL"),
+    (dict(n=16385), "EINVAL"),
+])
+def test_line_parameters_rejected(asf, kw, code):
+    args = dict(lam=633e-9, z0=1.0, p2=10e-6, x0=0.0, m=1024, tol=1e-5, n=1024)
+    args.update(kw)
+    p = asf.make_line_params(args["lam"], args["z0"], args["p2"], args["m"], args["tol"], x0=args["x0"])
+    assert asf.lib().asf_line_workspace_bytes(args["n"], ctypes.byref(p)) == 0
+    assert asf.last_error()
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(256)
+    rc = asf.lib().asf_line_plan(ctypes.byref(h), args["n"], dummy, dummy, ctypes.byref(p), dummy,
+                                 1 << 30, None)
+    assert rc == getattr(asf.asf, "ASF_" + code)
+    assert not h.value
+
+
+def test_line_workspace_and_null_pointers(asf):
+    lib = asf.lib()
+    p = asf.make_line_params(633e-9, 1.0, 10e-6, 1024)
+    b = asf.lib().asf_line_workspace_bytes(1024, ctypes.byref(p))
+    # records (index 4, offset 4, phase 8 B per point), first point per fine cell (4 B per cell + 1),
+    # twiddles (nf / 2) and the output table (m), complex64; each segment 256-byte aligned
+    lower = 16 * 1024 + 4 * (2048 + 1) + 8 * 1024 + 8 * 1024
+    assert lower <= b <= lower + 7 * 256
+    assert b % 256 == 0
+    h = ctypes.c_void_p()
+    assert lib.asf_line_plan(None, 10, 256, 256, ctypes.byref(p), 256, b, None) == asf.asf.ASF_EINVAL
+    assert lib.asf_line_plan(ctypes.byref(h), 10, None, 256, ctypes.byref(p), 256, b, None) == asf.asf.ASF_EINVAL
+    need = asf.lib().asf_line_workspace_bytes(10, ctypes.byref(p))
+    assert lib.asf_line_plan(ctypes.byref(h), 10, 256, 256, ctypes.byref(p), 256, need - 1, None) == asf.asf.ASF_ENOMEM
+    assert lib.asf_line_plan(ctypes.byref(h), 10, 256, 256, ctypes.byref(p), 257, need, None) == asf.asf.ASF_EINVAL
+    assert lib.asf_line_forward(None, 1, None, None, None) == asf.asf.ASF_EINVAL
+    assert lib.asf_line_destroy(None) == asf.asf.ASF_EINVAL
 
 
 def test_width_from_tolerance(asf):
