@@ -7,8 +7,9 @@ z0 = 0.2 m, 2048 x 2048 destination at 8 um, sigma = 2, w = 7, tol 1e-5).
 One step is the whole hot path over one batch of synthetic input already
 resident in HBM: the FP64 pre-phase and tile binning (asf_setpts) and the
 spreading plus both FFT passes with the fused deconvolution (asf_forward).
-The line also reports the geometry-cached forward alone (``fwd``) and the
-adjoint of the same plan (``adjoint``, the type-2 direction used for gradients).
+The line also reports the geometry-cached forward alone (``fwd``), the
+adjoint of the same plan (``adjoint``, the type-2 direction used for gradients)
+and the one-dimensional path on a batch of the quadratic profile (``line_1d``).
 
 Prints one JSON line.  ``value`` is NU points/s (source points per second of
 whole-step time).  Both FFT precisions are timed; the headline is the faster
@@ -93,6 +94,35 @@ def time_calls(torch, plan, fn, steps, warmup):
     return sec, acc
 
 
+def line_bench(torch, asf, synth, steps, warmup, batch=4096):
+    """The one-dimensional path: `batch` fields through the quadratic profile
+    (1024 points, 1024 pixels), one launch per call, timed with HIP events on the
+    stream the kernel runs on (torch's current stream)."""
+    w = synth.line_config("quadratic_1d")
+    rng = np.random.default_rng(2)
+    u = rng.standard_normal((batch, w.n)) + 1j * rng.standard_normal((batch, w.n))
+    u = torch.from_numpy(u.astype(np.complex64)).cuda()
+    plan = asf.LinePlan(torch.from_numpy(w.x).cuda(), torch.from_numpy(w.d).cuda(), w.lam, w.z0, w.p2,
+                        w.m, tol=w.tol, incident=w.incident)
+    out = torch.empty((batch, w.m), dtype=torch.complex64, device=u.device)
+    for _ in range(warmup):
+        plan.forward(u, out=out)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        plan.forward(u, out=out)
+    stop.record()
+    torch.cuda.synchronize()
+    sec = start.elapsed_time(stop) * 1e-3 / steps
+    plan.close()
+    alg = batch * 8 * (w.n + w.m)          # u1 read and u2 written once per field
+    return {"workload": "quadratic profile (Sec. 3): 1024 points at 10 um arc pitch, 1024 pixels, "
+                        "lambda=633nm, z0=1m", "batch": batch, "ms_per_call": sec * 1e3,
+            "value": batch * w.n / sec, "unit": "NU points/s",
+            "algorithmic_bytes": alg, "hbm_frac": alg / sec / (HBM_PEAK_GBS * 1e9)}
+
+
 def time_steps(torch, plan, x, y, d, u, out, steps, warmup, stage_events):
     for _ in range(warmup):
         plan.setpts(x, y, d)
@@ -154,6 +184,8 @@ def main():
                         "adj_sec": adj_sec, "adj_stages": adj_stages}
         plan.close()
 
+    line = line_bench(torch, asf, synth, args.steps, args.warmup)
+
     if args.copy_calibration:
         a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
@@ -195,6 +227,7 @@ def main():
                 "stages_ms": {s: round(t, 4) for s, t in r["fwd_stages"].items()}},
         "adjoint": {"ms_per_call": r["adj_sec"] * 1e3, "value": n / r["adj_sec"], "unit": "NU points/s",
                     "stages_ms": {s: round(t, 4) for s, t in r["adj_stages"].items()}},
+        "line_1d": line,
         "roofline": {
             "kernel": "spread",
             "bound": "hbm",
