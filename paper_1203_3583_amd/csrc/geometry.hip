@@ -99,7 +99,8 @@ __device__ inline WaveGroup wave_group(int key, bool active) {
     g.size = 0u;
     while (todo) {
         const int leader = __ffsll((unsigned long long)todo) - 1;
-        const int lkey = __shfl(key, leader);
+        // leader is wave-uniform: read its key with v_readlane, not an LDS permute
+        const int lkey = __builtin_amdgcn_readlane(key, leader);
         const uint64_t mask = __ballot(active && key == lkey) & todo;
         if ((mask >> lane) & 1ull) {
             g.leader = leader;
