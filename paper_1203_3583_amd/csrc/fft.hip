@@ -201,8 +201,16 @@ __device__ __forceinline__ void radix16_stage(float2 *lds, const float4 *__restr
         const int q = (wave * BPW + b) * 16 + jj;
         const int c = q >> S::LOGLQ, j = q & (S::LQ - 1);
         const float2 *col = lds + c * S::STRIDE;
+        if constexpr (S::LQ >= 64) {
+            // e + 4 i LQ changes neither bits 4..7 of e nor e mod 2^PS: the swizzled
+            // positions of the four inputs are one base plus constant offsets
+            const float2 *src = col + lds_pos<S::PS>(j + g * S::LQ);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v[b][i] = col[lds_pos<S::PS>(j + (g + 4 * i) * S::LQ)];
+            for (int i = 0; i < 4; ++i) v[b][i] = src[i * (4 * S::LQ + 64)];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[b][i] = col[lds_pos<S::PS>(j + (g + 4 * i) * S::LQ)];
+        }
         if constexpr (NS > 1) {
             const int k = j & (NS - 1);
             const float4 *t = tw + (k * 16 + g * 4) / 2;
@@ -222,8 +230,15 @@ __device__ __forceinline__ void radix16_stage(float2 *lds, const float4 *__restr
         const int k = j & (NS - 1);
         const int base = (j - k) * 16 + k;   // (j / NS) * 16 NS + k
         float2 *col = lds + c * S::STRIDE;
+        if constexpr (NS >= 64 && (4 * NS) % S::LQ == 0) {
+            // as for the reads: 4 i NS is a multiple of 256 and of 2^PS
+            float2 *dst = col + lds_pos<S::PS>(base + g * NS);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) col[lds_pos<S::PS>(base + (g + 4 * i) * NS)] = v[b][i];
+            for (int i = 0; i < 4; ++i) dst[i * (4 * NS + ((4 * NS) >> S::PS) * 16)] = v[b][i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) col[lds_pos<S::PS>(base + (g + 4 * i) * NS)] = v[b][i];
+        }
     }
     __syncthreads();
 }
