@@ -587,7 +587,7 @@ namespace {
 struct LineLayout {
     int n, m, nf, w;
     double beta;
-    size_t off_status, off_first, off_perm, off_off, off_phase, off_tw, off_dd, total;
+    size_t off_status, off_first, off_perm, off_cell, off_coef, off_tw, off_dd, total;
 };
 
 int make_line_layout(int64_t n, const asf_line_params *p, LineLayout &L) {
@@ -617,8 +617,8 @@ int make_line_layout(int64_t n, const asf_line_params *p, LineLayout &L) {
     L.off_status = take(kAlign);
     L.off_first = take(sizeof(uint32_t) * (L.nf + 1));
     L.off_perm = take(sizeof(uint32_t) * L.n);
-    L.off_off = take(sizeof(float) * L.n);
-    L.off_phase = take(sizeof(float2) * L.n);
+    L.off_cell = take(sizeof(uint32_t) * L.n);
+    L.off_coef = take(sizeof(float2) * (size_t)L.n * L.w);
     L.off_tw = take(sizeof(float2) * (L.nf / 2));
     L.off_dd = take(sizeof(float2) * L.m);
     L.total = o;
@@ -680,8 +680,8 @@ int asf_line_plan(asf_line_t *out, int64_t n_src, const double *x1, const double
     pl->bin.status = reinterpret_cast<uint32_t *>(w + L.off_status);
     pl->bin.first = reinterpret_cast<uint32_t *>(w + L.off_first);
     pl->bin.perm = reinterpret_cast<uint32_t *>(w + L.off_perm);
-    pl->bin.off = reinterpret_cast<float *>(w + L.off_off);
-    pl->bin.phase = reinterpret_cast<float2 *>(w + L.off_phase);
+    pl->bin.cell = reinterpret_cast<uint32_t *>(w + L.off_cell);
+    pl->bin.coef = reinterpret_cast<float2 *>(w + L.off_coef);
     pl->tw = reinterpret_cast<float2 *>(w + L.off_tw);
     pl->dd = reinterpret_cast<float2 *>(w + L.off_dd);
     pl->geo.inv_lambda = 1.0 / p->lambda;
@@ -694,7 +694,7 @@ int asf_line_plan(asf_line_t *out, int64_t n_src, const double *x1, const double
     pl->geo.log_nf = log2i(L.nf);
     pl->geo.w = L.w;
     pl->geo.plane = (p->flags & ASF_INCIDENT_NONE) ? 0 : 1;
-    pl->geo.beta_log2e = (float)(L.beta * 1.4426950408889634);
+    pl->geo.beta = L.beta;
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = upload_line_tables(pl, L, s);

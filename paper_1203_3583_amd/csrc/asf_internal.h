@@ -58,7 +58,7 @@ struct LineGeo {
     double z0, p2, x0;
     int n, m, nf, log_nf, w;
     int plane;         // 1: u_I = exp(i k d1)
-    float beta_log2e;  // ES shape beta times log2(e)
+    double beta;       // ES shape
 };
 
 // Points of a line plan sorted by first footprint cell (ties by index).
@@ -66,8 +66,8 @@ struct LineBins {
     uint32_t *status;  // [1] bit 0: domain error
     uint32_t *first;   // [nf + 1] first sorted point whose footprint starts at cell c (or later)
     uint32_t *perm;    // [n] caller index of sorted point j
-    float *off;        // [n] g - c - (w-1)/2, in [-1/2, 1/2]
-    float2 *phase;     // [n] exp(i phi_j)
+    uint32_t *cell;    // [n] its first footprint cell
+    float2 *coef;      // [n][w] psi_a(offset_j) exp(i phi_j) for footprint cells a < w
 };
 
 constexpr int kLineMaxPoints = 16384;   // point index and first cell each fit 14 bits

@@ -11,16 +11,21 @@
 //    revolutions s x^2 / 2 - s x x0 (- d / lambda without the plane wave),
 //    s = 1 / (lambda r0), integer part removed in FP64, FP32 sincospi of the
 //    remainder; frequency p2 x s wrapped to [0, 1), first footprint cell
-//    c = ceil(g - w/2)), then a bitonic sort of the keys (c, index) in LDS and
-//    the sorted records plus, per cell, the first point starting there.
+//    c = ceil(g - w/2)), then a bitonic sort of the keys (c, index) in LDS, and
+//    per sorted point its caller index and its w spreading coefficients
+//    psi_i(offset) exp(i phi) (kernel values in FP64, rounded once), plus, per
+//    cell, the first point starting there.
 //
-//  * line_forward_kernel (one workgroup per field): each thread owns fine cells
-//    and gathers the points whose footprint covers them from the w cells to
-//    its left (a fixed order: no atomics, bitwise repeatable), writes the sum
-//    to LDS in bit-reversed order, runs an in-place radix-2 FFT over the whole
-//    line in LDS (FP32, twiddles from the FP64-built table) and multiplies the
-//    kept modes by the deconvolution and destination phase.  The work is a few
-//    microseconds of latency per field; batches of fields fill the chip.
+//  * line_forward_kernel (one 256-thread workgroup per field): each thread owns
+//    fine cells and gathers the points whose footprint covers them -- those
+//    starting in the w cells up to its own, one contiguous run of the sorted
+//    list -- one complex multiply-add per (cell, point) pair, in a fixed order
+//    (no atomics, bitwise repeatable); the sums go to LDS in
+//    bit-reversed order; an in-place FFT over the whole line follows in LDS
+//    (FP32, FP64-built twiddles), two radix-2 levels per pass (radix-4
+//    butterflies, half the barriers), and the kept modes are multiplied by the
+//    deconvolution and destination phase.  Small workgroups let several fields
+//    share a CU and hide each other's barriers.
 #include <hip/hip_runtime.h>
 
 #include "asf_internal.h"
@@ -28,7 +33,8 @@
 namespace asf {
 namespace {
 
-constexpr int kLineThreads = 1024;
+constexpr int kLineThreads = 1024;      // setup (one workgroup, sorting)
+constexpr int kLineFwdThreads = 256;    // forward (one workgroup per field)
 
 struct LinePoint {
     int c;          // first footprint cell, wrapped into [0, nf)
@@ -105,8 +111,14 @@ __global__ __launch_bounds__(kLineThreads) void line_setup_kernel(LineGeo g, Lin
         const int c = (int)(key >> kLineKeyBits);
         const LinePoint p = line_point(g, x[i], d[i]);   // same function: same cell
         b.perm[j] = i;
-        b.off[j] = p.off;
-        b.phase[j] = p.phase;
+        b.cell[j] = (uint32_t)c;
+        for (int a = 0; a < g.w; ++a) {
+            // psi at footprint cell a: z = (a - (w-1)/2 - off) 2/w
+            const double z = ((double)a - 0.5 * (double)(g.w - 1) - (double)p.off) * 2.0 / (double)g.w;
+            const double t = 1.0 - z * z;
+            const float psi = t > 0.0 ? (float)exp(g.beta * (sqrt(t) - 1.0)) : 0.f;
+            b.coef[(size_t)j * g.w + a] = make_float2(psi * p.phase.x, psi * p.phase.y);
+        }
         const int cprev = j == 0 ? -1 : (int)(keys[j - 1] >> kLineKeyBits);
         for (int q = cprev + 1; q <= c; ++q) b.first[q] = (uint32_t)j;
         if (j == n - 1)
@@ -118,55 +130,94 @@ __device__ inline float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-__global__ __launch_bounds__(kLineThreads) void line_forward_kernel(LineGeo g, LineBins b,
-                                                                     const float2 *__restrict__ tw,
-                                                                     const float2 *__restrict__ dd,
-                                                                     const float2 *__restrict__ u1,
-                                                                     float2 *__restrict__ u2) {
-    extern __shared__ float2 line[];   // nf cells
+// Sum over sorted points j0 <= j < j1 (their footprints start at or left of
+// cell qq and cover it) of coef(j, qq - cell_j) times the field at j.
+template <bool STAGED>
+__device__ __forceinline__ void gather_cell(const LineBins &b, int w, const float2 *__restrict__ u,
+                                            const float2 *vs, uint32_t j0, uint32_t j1, int qq,
+                                            float &ar, float &ai) {
+    for (uint32_t j = j0; j < j1; ++j) {
+        const float2 k = b.coef[(size_t)j * w + (qq - (int)b.cell[j])];
+        const float2 v = STAGED ? vs[j] : u[b.perm[j]];
+        ar = __builtin_fmaf(k.x, v.x, ar);
+        ar = __builtin_fmaf(-k.y, v.y, ar);
+        ai = __builtin_fmaf(k.x, v.y, ai);
+        ai = __builtin_fmaf(k.y, v.x, ai);
+    }
+}
+
+// STAGED: the field is first copied into LDS in sorted order (when it fits),
+// so that the gather reads it there instead of through the index.
+template <bool STAGED>
+__global__ __launch_bounds__(kLineFwdThreads) void line_forward_kernel(LineGeo g, LineBins b,
+                                                                        const float2 *__restrict__ tw,
+                                                                        const float2 *__restrict__ dd,
+                                                                        const float2 *__restrict__ u1,
+                                                                        float2 *__restrict__ u2) {
+    extern __shared__ float2 line[];   // nf cells, then (STAGED) the n field values
     const float2 *u = u1 + (size_t)blockIdx.x * g.n;
     const int nf = g.nf, w = g.w, lg = g.log_nf;
-    const float two_over_w = 2.f / (float)w;
-    const float centre = 0.5f * (float)(w - 1);
+    float2 *vs = line + nf;
+    if constexpr (STAGED) {
+        for (int j = threadIdx.x; j < g.n; j += kLineFwdThreads) vs[j] = u[b.perm[j]];
+        __syncthreads();
+    }
 
-    // spreading as a gather: cell q is cell i = q - c of the footprints starting at c
-    for (int q = threadIdx.x; q < nf; q += kLineThreads) {
+    // spreading as a gather: the points whose footprints cover cell q are those
+    // starting in cells q-w+1 .. q, one contiguous run of the sorted list (two
+    // when the run wraps past cell 0)
+    for (int q = threadIdx.x; q < nf; q += kLineFwdThreads) {
         float ar = 0.f, ai = 0.f;
-        for (int i = 0; i < w; ++i) {
-            int c = q - i;
-            if (c < 0) c += nf;
-            const uint32_t j1 = b.first[c + 1];
-            for (uint32_t j = b.first[c]; j < j1; ++j) {
-                const float z = ((float)i - centre - b.off[j]) * two_over_w;
-                const float a = 1.f - z * z;
-                const float psi = a > 0.f ? exp2f(g.beta_log2e * (sqrtf(a) - 1.f)) : 0.f;
-                const float2 v = cmul(u[b.perm[j]], b.phase[j]);
-                ar = __builtin_fmaf(psi, v.x, ar);
-                ai = __builtin_fmaf(psi, v.y, ai);
-            }
+        const int lo = q - w + 1;
+        const uint32_t jq = b.first[q + 1];
+        if (lo >= 0) {
+            gather_cell<STAGED>(b, w, u, vs, b.first[lo], jq, q, ar, ai);
+        } else {
+            gather_cell<STAGED>(b, w, u, vs, b.first[lo + nf], (uint32_t)g.n, q + nf, ar, ai);
+            gather_cell<STAGED>(b, w, u, vs, b.first[0], jq, q, ar, ai);
         }
         line[__brev((unsigned)q) >> (32 - lg)] = make_float2(ar, ai);
     }
     __syncthreads();
 
-    // in-place radix-2 decimation-in-time FFT, exp(-2 pi i k q / nf)
-    for (int st = 1; st <= lg; ++st) {
-        const int half = 1 << (st - 1);
-        const int stride = nf >> st;
-        for (int t = threadIdx.x; t < (nf >> 1); t += kLineThreads) {
-            const int pos = t & (half - 1);
-            const int a = ((t >> (st - 1)) << st) + pos;
-            const float2 x0 = line[a];
-            const float2 y0 = cmul(line[a + half], tw[pos * stride]);
-            line[a] = make_float2(x0.x + y0.x, x0.y + y0.y);
-            line[a + half] = make_float2(x0.x - y0.x, x0.y - y0.y);
+    // in-place decimation-in-time FFT, exp(-2 pi i k q / nf), on bit-reversed input:
+    // an odd number of levels starts with one radix-2 level, the rest go two at a
+    // time (a radix-4 butterfly on a, a+h, a+2h, a+3h does levels h and 2h)
+    int h = 1;
+    if (lg & 1) {
+        for (int t = threadIdx.x; t < (nf >> 1); t += kLineFwdThreads) {
+            const float2 x0 = line[2 * t], x1 = line[2 * t + 1];
+            line[2 * t] = make_float2(x0.x + x1.x, x0.y + x1.y);
+            line[2 * t + 1] = make_float2(x0.x - x1.x, x0.y - x1.y);
+        }
+        __syncthreads();
+        h = 2;
+    }
+    for (; h < nf; h <<= 2) {
+        const int s2 = nf / (2 * h), s4 = nf / (4 * h);   // twiddle strides of the two levels
+        for (int t = threadIdx.x; t < (nf >> 2); t += kLineFwdThreads) {
+            const int pos = t & (h - 1);
+            const int a = (t - pos) * 4 + pos;             // (t / h) 4h + pos
+            const float2 w2 = tw[pos * s2];
+            const float2 w4a = tw[pos * s4], w4b = tw[(pos + h) * s4];
+            // level h: (a, a+h) and (a+2h, a+3h), twiddle w2
+            const float2 p0 = line[a], p1 = cmul(line[a + h], w2);
+            const float2 p2 = line[a + 2 * h], p3 = cmul(line[a + 3 * h], w2);
+            const float2 q0 = make_float2(p0.x + p1.x, p0.y + p1.y), q1 = make_float2(p0.x - p1.x, p0.y - p1.y);
+            const float2 q2 = make_float2(p2.x + p3.x, p2.y + p3.y), q3 = make_float2(p2.x - p3.x, p2.y - p3.y);
+            // level 2h: (a, a+2h) with w4a, (a+h, a+3h) with w4b
+            const float2 r2 = cmul(q2, w4a), r3 = cmul(q3, w4b);
+            line[a] = make_float2(q0.x + r2.x, q0.y + r2.y);
+            line[a + 2 * h] = make_float2(q0.x - r2.x, q0.y - r2.y);
+            line[a + h] = make_float2(q1.x + r3.x, q1.y + r3.y);
+            line[a + 3 * h] = make_float2(q1.x - r3.x, q1.y - r3.y);
         }
         __syncthreads();
     }
 
     // kept modes k = ix - m/2 at FFT index k mod nf, times the deconvolution and phase
     float2 *out = u2 + (size_t)blockIdx.x * g.m;
-    for (int ix = threadIdx.x; ix < g.m; ix += kLineThreads) {
+    for (int ix = threadIdx.x; ix < g.m; ix += kLineFwdThreads) {
         const int k = ix - (g.m >> 1);
         out[ix] = cmul(line[k < 0 ? k + nf : k], dd[ix]);
     }
@@ -185,15 +236,23 @@ hipError_t launch_line_forward(const LineGeo &g, const LineBins &b, const float2
                                int batch, const float2 *u1, float2 *u2, hipStream_t s) {
     if (batch < 1 || g.nf < 2 || g.nf > (1 << kLineKeyBits) || (1 << g.log_nf) != g.nf)
         return hipErrorInvalidValue;
-    const size_t lds = sizeof(float2) * (size_t)g.nf;
-    static size_t enabled = 0;
-    if (lds > 65536 && lds > enabled) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(line_forward_kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        enabled = lds;
+    // stage the field in LDS when line and field together stay within 64 KB
+    const size_t line_bytes = sizeof(float2) * (size_t)g.nf;
+    const size_t staged_bytes = line_bytes + sizeof(float2) * (size_t)g.n;
+    if (staged_bytes <= 65536) {
+        hipLaunchKernelGGL(line_forward_kernel<true>, dim3(batch), dim3(kLineFwdThreads), staged_bytes, s,
+                           g, b, tw, dd, u1, u2);
+        return hipGetLastError();
     }
-    hipLaunchKernelGGL(line_forward_kernel, dim3(batch), dim3(kLineThreads), lds, s, g, b, tw, dd, u1, u2);
+    static size_t enabled = 0;
+    if (line_bytes > 65536 && line_bytes > enabled) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(line_forward_kernel<false>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)line_bytes);
+        if (e != hipSuccess) return e;
+        enabled = line_bytes;
+    }
+    hipLaunchKernelGGL(line_forward_kernel<false>, dim3(batch), dim3(kLineFwdThreads), line_bytes, s,
+                       g, b, tw, dd, u1, u2);
     return hipGetLastError();
 }
 

@@ -131,9 +131,10 @@ def test_line_workspace_and_null_pointers(asf):
     lib = asf.lib()
     p = asf.make_line_params(633e-9, 1.0, 10e-6, 1024)
     b = asf.lib().asf_line_workspace_bytes(1024, ctypes.byref(p))
-    # records (index 4, offset 4, phase 8 B per point), first point per fine cell (4 B per cell + 1),
-    # twiddles (nf / 2) and the output table (m), complex64; each segment 256-byte aligned
-    lower = 16 * 1024 + 4 * (2048 + 1) + 8 * 1024 + 8 * 1024
+    # per point its index and first cell (4 B each) and w = 7 spreading coefficients
+    # (complex64), first point per fine cell (4 B per cell + 1), twiddles (nf / 2) and the
+    # output table (m), complex64; each segment 256-byte aligned
+    lower = (8 + 8 * 7) * 1024 + 4 * (2048 + 1) + 8 * 1024 + 8 * 1024
     assert lower <= b <= lower + 7 * 256
     assert b % 256 == 0
     h = ctypes.c_void_p()
