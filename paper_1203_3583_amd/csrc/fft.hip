@@ -183,15 +183,46 @@ __device__ __forceinline__ void first_stage(float2 *lds, const float2 *w16s) {
     }
 }
 
-// One radix-16 Stockham stage with span NS, in place in LDS.  tw points at this
-// stage's table: entry (k, g, i) = exp(-2 pi i (g + 4 i) k / (16 NS)).
-template <int LOGL, int BATCH, int NT, int NS, class Engine>
-__device__ __forceinline__ void radix16_stage(float2 *lds, const float4 *__restrict__ tw, const Engine &eng) {
-    using S = Len<LOGL>;
-    constexpr int BLOCKS = BATCH * S::LQ / 16;     // 16-instance blocks in the stage
-    constexpr int WAVES = NT / 64;
-    constexpr int BPW = BLOCKS / WAVES;
+// 16-instance blocks of a radix-16 stage per wave
+template <int LOGL, int BATCH, int NT>
+struct StageBlocks {
+    static constexpr int BLOCKS = BATCH * Len<LOGL>::LQ / 16;
+    static constexpr int WAVES = NT / 64;
+    static constexpr int BPW = BLOCKS / WAVES;
     static_assert(BLOCKS % WAVES == 0 && BPW >= 1, "blocks must divide among waves");
+};
+
+// This lane's twiddles of a stage with span NS (table entry (k, g, i) =
+// exp(-2 pi i (g + 4 i) k / (16 NS))): two 16-byte loads per block.  A stage's
+// twiddles are fetched during the previous stage, before its last barrier, so
+// that their latency hides behind the barrier instead of stalling the stage.
+template <int LOGL, int BATCH, int NT, int NS>
+__device__ __forceinline__ void load_twiddles(const float4 *__restrict__ tw,
+                                              float4 (&t)[StageBlocks<LOGL, BATCH, NT>::BPW][2]) {
+    using S = Len<LOGL>;
+    constexpr int BPW = StageBlocks<LOGL, BATCH, NT>::BPW;
+    if constexpr (NS > 1) {
+        const int lane = threadIdx.x & 63;
+        const int g = lane >> 4, jj = lane & 15, wave = threadIdx.x >> 6;
+#pragma unroll
+        for (int b = 0; b < BPW; ++b) {
+            const int j = ((wave * BPW + b) * 16 + jj) & (S::LQ - 1);
+            const float4 *p = tw + ((j & (NS - 1)) * 16 + g * 4) / 2;
+            t[b][0] = p[0];
+            t[b][1] = p[1];
+        }
+    }
+}
+
+// One radix-16 Stockham stage with span NS, in place in LDS, with this stage's
+// twiddles already in registers (tcur); fetches the next stage's (span NSN,
+// table twn) into tnext.
+template <int LOGL, int BATCH, int NT, int NS, int NSN, class Engine>
+__device__ __forceinline__ void radix16_stage(
+    float2 *lds, const float4 (&tcur)[StageBlocks<LOGL, BATCH, NT>::BPW][2], const float4 *__restrict__ twn,
+    float4 (&tnext)[StageBlocks<LOGL, BATCH, NT>::BPW][2], const Engine &eng) {
+    using S = Len<LOGL>;
+    constexpr int BPW = StageBlocks<LOGL, BATCH, NT>::BPW;
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, jj = lane & 15;
     const int wave = threadIdx.x >> 6;
@@ -212,9 +243,7 @@ __device__ __forceinline__ void radix16_stage(float2 *lds, const float4 *__restr
             for (int i = 0; i < 4; ++i) v[b][i] = col[lds_pos<S::PS>(j + (g + 4 * i) * S::LQ)];
         }
         if constexpr (NS > 1) {
-            const int k = j & (NS - 1);
-            const float4 *t = tw + (k * 16 + g * 4) / 2;
-            const float4 t01 = t[0], t23 = t[1];
+            const float4 t01 = tcur[b][0], t23 = tcur[b][1];
             v[b][0] = cmul(v[b][0], make_float2(t01.x, t01.y));
             v[b][1] = cmul(v[b][1], make_float2(t01.z, t01.w));
             v[b][2] = cmul(v[b][2], make_float2(t23.x, t23.y));
@@ -240,6 +269,7 @@ __device__ __forceinline__ void radix16_stage(float2 *lds, const float4 *__restr
             for (int i = 0; i < 4; ++i) col[lds_pos<S::PS>(base + (g + 4 * i) * NS)] = v[b][i];
         }
     }
+    load_twiddles<LOGL, BATCH, NT, NSN>(twn, tnext);
     __syncthreads();
 }
 
@@ -255,21 +285,30 @@ constexpr int twiddle_offset(int stage) {
     return off;
 }
 
+template <int LOGL>
+__device__ __forceinline__ const float4 *stage_table(const float4 *tw, int stage) {
+    return reinterpret_cast<const float4 *>(reinterpret_cast<const float2 *>(tw) + twiddle_offset<LOGL>(stage));
+}
+
 template <int LOGL, int BATCH, int NT, int STAGE, class Engine>
-__device__ __forceinline__ void stages_from(float2 *lds, const float4 *tw, const Engine &eng) {
+__device__ __forceinline__ void stages_from(float2 *lds, const float4 *tw, const Engine &eng,
+                                            const float4 (&tcur)[StageBlocks<LOGL, BATCH, NT>::BPW][2]) {
     using S = Len<LOGL>;
     if constexpr (STAGE < S::N16) {
         constexpr int NS = S::R0 << (4 * STAGE);
-        constexpr int OFF = twiddle_offset<LOGL>(STAGE);
-        radix16_stage<LOGL, BATCH, NT, NS, Engine>(lds, reinterpret_cast<const float4 *>(
-                                                            reinterpret_cast<const float2 *>(tw) + OFF), eng);
-        stages_from<LOGL, BATCH, NT, STAGE + 1, Engine>(lds, tw, eng);
+        constexpr int NSN = STAGE + 1 < S::N16 ? NS * 16 : 1;   // 1: no next stage to fetch for
+        float4 tnext[StageBlocks<LOGL, BATCH, NT>::BPW][2];
+        radix16_stage<LOGL, BATCH, NT, NS, NSN, Engine>(lds, tcur, stage_table<LOGL>(tw, STAGE + 1), tnext, eng);
+        stages_from<LOGL, BATCH, NT, STAGE + 1, Engine>(lds, tw, eng, tnext);
     }
 }
 
 template <int LOGL, int BATCH, int NT, bool SPLIT>
 __device__ __forceinline__ void transform_all(float2 *lds, const float2 *tw, const float2 *w16) {
     __shared__ float2 w16s[16];
+    const float4 *tw4 = reinterpret_cast<const float4 *>(tw);
+    float4 t0[StageBlocks<LOGL, BATCH, NT>::BPW][2];
+    load_twiddles<LOGL, BATCH, NT, Len<LOGL>::R0>(stage_table<LOGL>(tw4, 0), t0);   // first radix-16 stage
     if (threadIdx.x < 16) w16s[threadIdx.x] = w16[threadIdx.x];
     __syncthreads();
     first_stage<LOGL, BATCH, NT>(lds, w16s);
@@ -277,11 +316,11 @@ __device__ __forceinline__ void transform_all(float2 *lds, const float2 *tw, con
     if constexpr (SPLIT) {
         Dft16Split16 eng;
         eng.init(w16s, lane >> 4, lane & 15);
-        stages_from<LOGL, BATCH, NT, 0, Dft16Split16>(lds, reinterpret_cast<const float4 *>(tw), eng);
+        stages_from<LOGL, BATCH, NT, 0, Dft16Split16>(lds, tw4, eng, t0);
     } else {
         Dft16F32 eng;
         eng.init(w16s, lane >> 4, lane & 15);
-        stages_from<LOGL, BATCH, NT, 0, Dft16F32>(lds, reinterpret_cast<const float4 *>(tw), eng);
+        stages_from<LOGL, BATCH, NT, 0, Dft16F32>(lds, tw4, eng, t0);
     }
 }
 
