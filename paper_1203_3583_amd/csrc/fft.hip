@@ -139,8 +139,8 @@ struct Dft16Split16 {
 };
 
 // Radix-R0 first stage (Ns = 1, no twiddles) on the vector ALU, in place.
-template <int LOGL, int BATCH, int NT>
-__device__ __forceinline__ void first_stage(float2 *lds, const float2 *w16s) {
+template <int LOGL, int BATCH, int NT, bool SCALE>
+__device__ __forceinline__ void first_stage(float2 *lds, const float2 *w16s, float inv) {
     using S = Len<LOGL>;
     constexpr int R0 = S::R0;
     if constexpr (R0 > 1) {
@@ -155,7 +155,10 @@ __device__ __forceinline__ void first_stage(float2 *lds, const float2 *w16s) {
                 const int c = inst / PER, j = inst % PER;
                 float2 x[R0];
 #pragma unroll
-                for (int r = 0; r < R0; ++r) x[r] = lds[c * S::STRIDE + lds_pos<S::PS>(j + r * PER)];
+                for (int r = 0; r < R0; ++r) {
+                    x[r] = lds[c * S::STRIDE + lds_pos<S::PS>(j + r * PER)];
+                    if constexpr (SCALE) x[r] = make_float2(x[r].x * inv, x[r].y * inv);
+                }
 #pragma unroll
                 for (int p = 0; p < R0; ++p) {
                     float2 acc = x[0];
@@ -217,10 +220,10 @@ __device__ __forceinline__ void load_twiddles(const float4 *__restrict__ tw,
 // One radix-16 Stockham stage with span NS, in place in LDS, with this stage's
 // twiddles already in registers (tcur); fetches the next stage's (span NSN,
 // table twn) into tnext.
-template <int LOGL, int BATCH, int NT, int NS, int NSN, class Engine>
+template <int LOGL, int BATCH, int NT, int NS, int NSN, bool SCALE, class Engine>
 __device__ __forceinline__ void radix16_stage(
     float2 *lds, const float4 (&tcur)[StageBlocks<LOGL, BATCH, NT>::BPW][2], const float4 *__restrict__ twn,
-    float4 (&tnext)[StageBlocks<LOGL, BATCH, NT>::BPW][2], const Engine &eng) {
+    float4 (&tnext)[StageBlocks<LOGL, BATCH, NT>::BPW][2], const Engine &eng, float inv) {
     using S = Len<LOGL>;
     constexpr int BPW = StageBlocks<LOGL, BATCH, NT>::BPW;
     const int lane = threadIdx.x & 63;
@@ -241,6 +244,10 @@ __device__ __forceinline__ void radix16_stage(
         } else {
 #pragma unroll
             for (int i = 0; i < 4; ++i) v[b][i] = col[lds_pos<S::PS>(j + (g + 4 * i) * S::LQ)];
+        }
+        if constexpr (SCALE) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[b][i] = make_float2(v[b][i].x * inv, v[b][i].y * inv);
         }
         if constexpr (NS > 1) {
             const float4 t01 = tcur[b][0], t23 = tcur[b][1];
@@ -290,37 +297,43 @@ __device__ __forceinline__ const float4 *stage_table(const float4 *tw, int stage
     return reinterpret_cast<const float4 *>(reinterpret_cast<const float2 *>(tw) + twiddle_offset<LOGL>(stage));
 }
 
-template <int LOGL, int BATCH, int NT, int STAGE, class Engine>
+// SCALE: multiply the transform's input by inv as the first stage reads it
+template <int LOGL, int BATCH, int NT, int STAGE, bool SCALE, class Engine>
 __device__ __forceinline__ void stages_from(float2 *lds, const float4 *tw, const Engine &eng,
-                                            const float4 (&tcur)[StageBlocks<LOGL, BATCH, NT>::BPW][2]) {
+                                            const float4 (&tcur)[StageBlocks<LOGL, BATCH, NT>::BPW][2],
+                                            float inv) {
     using S = Len<LOGL>;
     if constexpr (STAGE < S::N16) {
         constexpr int NS = S::R0 << (4 * STAGE);
         constexpr int NSN = STAGE + 1 < S::N16 ? NS * 16 : 1;   // 1: no next stage to fetch for
+        constexpr bool SC = SCALE && STAGE == 0 && S::R0 == 1;   // else first_stage scaled
         float4 tnext[StageBlocks<LOGL, BATCH, NT>::BPW][2];
-        radix16_stage<LOGL, BATCH, NT, NS, NSN, Engine>(lds, tcur, stage_table<LOGL>(tw, STAGE + 1), tnext, eng);
-        stages_from<LOGL, BATCH, NT, STAGE + 1, Engine>(lds, tw, eng, tnext);
+        radix16_stage<LOGL, BATCH, NT, NS, NSN, SC, Engine>(lds, tcur, stage_table<LOGL>(tw, STAGE + 1), tnext,
+                                                            eng, inv);
+        stages_from<LOGL, BATCH, NT, STAGE + 1, SCALE, Engine>(lds, tw, eng, tnext, inv);
     }
 }
 
+// The workgroup's transforms, in place in LDS; with SPLIT the input is scaled by
+// inv (a power of two) on its way into the first stage.
 template <int LOGL, int BATCH, int NT, bool SPLIT>
-__device__ __forceinline__ void transform_all(float2 *lds, const float2 *tw, const float2 *w16) {
+__device__ __forceinline__ void transform_all(float2 *lds, const float2 *tw, const float2 *w16, float inv) {
     __shared__ float2 w16s[16];
     const float4 *tw4 = reinterpret_cast<const float4 *>(tw);
     float4 t0[StageBlocks<LOGL, BATCH, NT>::BPW][2];
     load_twiddles<LOGL, BATCH, NT, Len<LOGL>::R0>(stage_table<LOGL>(tw4, 0), t0);   // first radix-16 stage
     if (threadIdx.x < 16) w16s[threadIdx.x] = w16[threadIdx.x];
     __syncthreads();
-    first_stage<LOGL, BATCH, NT>(lds, w16s);
+    first_stage<LOGL, BATCH, NT, SPLIT>(lds, w16s, inv);
     const int lane = threadIdx.x & 63;
     if constexpr (SPLIT) {
         Dft16Split16 eng;
         eng.init(w16s, lane >> 4, lane & 15);
-        stages_from<LOGL, BATCH, NT, 0, Dft16Split16>(lds, tw4, eng, t0);
+        stages_from<LOGL, BATCH, NT, 0, true, Dft16Split16>(lds, tw4, eng, t0, inv);
     } else {
         Dft16F32 eng;
         eng.init(w16s, lane >> 4, lane & 15);
-        stages_from<LOGL, BATCH, NT, 0, Dft16F32>(lds, tw4, eng, t0);
+        stages_from<LOGL, BATCH, NT, 0, false, Dft16F32>(lds, tw4, eng, t0, inv);
     }
 }
 
@@ -359,20 +372,16 @@ __global__ void __launch_bounds__(NT) fft_pass1_kernel(const float2 *__restrict_
         lds[c * S::STRIDE + lds_pos<S::PS>(ly)] = v;
         if constexpr (SPLIT) big = fmaxf(big, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
-    float unscale = 1.f;
+    // split products: scale the workgroup's data by a power of two into FP16 range
+    // (applied as the first stage reads it); the block maximum's barrier also
+    // completes the LDS writes above, as transform_all's first barrier does otherwise
+    float unscale = 1.f, inv = 1.f;
     if constexpr (SPLIT) {
         const int e = range_exponent(block_max(big, scratch));
-        const float inv = ldexpf(1.f, -e);
+        inv = ldexpf(1.f, -e);
         unscale = ldexpf(1.f, e);
-        __syncthreads();
-        for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
-            const int ly = t / BATCH, c = t % BATCH;
-            float2 &x = lds[c * S::STRIDE + lds_pos<S::PS>(ly)];
-            x = make_float2(x.x * inv, x.y * inv);
-        }
     }
-    __syncthreads();
-    transform_all<LOGL, BATCH, NT, SPLIT>(lds, tw, w16);
+    transform_all<LOGL, BATCH, NT, SPLIT>(lds, tw, w16, inv);
     const int half = my >> 1;
     float2 *dst = mid + (size_t)pc * my * BATCH;   // this panel's block of mid
     for (int t = threadIdx.x; t < my * BATCH; t += NT) {
@@ -412,20 +421,16 @@ __global__ void __launch_bounds__(NT) fft_pass2_kernel(const float2 *__restrict_
         lds[c * S::STRIDE + lds_pos<S::PS>(lx)] = v;
         if constexpr (SPLIT) big = fmaxf(big, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
-    float unscale = 1.f;
+    // split products: scale the workgroup's data by a power of two into FP16 range
+    // (applied as the first stage reads it); the block maximum's barrier also
+    // completes the LDS writes above, as transform_all's first barrier does otherwise
+    float unscale = 1.f, inv = 1.f;
     if constexpr (SPLIT) {
         const int e = range_exponent(block_max(big, scratch));
-        const float inv = ldexpf(1.f, -e);
+        inv = ldexpf(1.f, -e);
         unscale = ldexpf(1.f, e);
-        __syncthreads();
-        for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
-            const int c = t >> LOGL, lx = t & (S::L - 1);
-            float2 &x = lds[c * S::STRIDE + lds_pos<S::PS>(lx)];
-            x = make_float2(x.x * inv, x.y * inv);
-        }
     }
-    __syncthreads();
-    transform_all<LOGL, BATCH, NT, SPLIT>(lds, tw, w16);
+    transform_all<LOGL, BATCH, NT, SPLIT>(lds, tw, w16, inv);
     const int half = mx >> 1;
     for (int t = threadIdx.x; t < mx * BATCH; t += NT) {
         const int c = t / mx, ix = t - c * mx;
@@ -479,20 +484,16 @@ __global__ void __launch_bounds__(NT) fft_adj_rows_kernel(const float2 *__restri
         lds[c * S::STRIDE + lds_pos<S::PS>(l)] = v;
         if constexpr (SPLIT) big = fmaxf(big, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
-    float unscale = 1.f;
+    // split products: scale the workgroup's data by a power of two into FP16 range
+    // (applied as the first stage reads it); the block maximum's barrier also
+    // completes the LDS writes above, as transform_all's first barrier does otherwise
+    float unscale = 1.f, inv = 1.f;
     if constexpr (SPLIT) {
         const int e = range_exponent(block_max(big, scratch));
-        const float inv = ldexpf(1.f, -e);
+        inv = ldexpf(1.f, -e);
         unscale = ldexpf(1.f, e);
-        __syncthreads();
-        for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
-            const int c = t >> LOGL, l = t & (S::L - 1);
-            float2 &x = lds[c * S::STRIDE + lds_pos<S::PS>(l)];
-            x = make_float2(x.x * inv, x.y * inv);
-        }
     }
-    __syncthreads();
-    transform_all<LOGL, BATCH, NT, SPLIT>(lds, tw, w16);
+    transform_all<LOGL, BATCH, NT, SPLIT>(lds, tw, w16, inv);
     float2 *dst = mid + (size_t)row0 * S::L;
     for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
         const int c = t >> LOGL, l = t & (S::L - 1);
@@ -533,20 +534,16 @@ __global__ void __launch_bounds__(NT) fft_adj_cols_kernel(const float2 *__restri
         lds[c * S::STRIDE + lds_pos<S::PS>(l)] = v;
         if constexpr (SPLIT) big = fmaxf(big, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
-    float unscale = 1.f;
+    // split products: scale the workgroup's data by a power of two into FP16 range
+    // (applied as the first stage reads it); the block maximum's barrier also
+    // completes the LDS writes above, as transform_all's first barrier does otherwise
+    float unscale = 1.f, inv = 1.f;
     if constexpr (SPLIT) {
         const int e = range_exponent(block_max(big, scratch));
-        const float inv = ldexpf(1.f, -e);
+        inv = ldexpf(1.f, -e);
         unscale = ldexpf(1.f, e);
-        __syncthreads();
-        for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
-            const int l = t / BATCH, c = t % BATCH;
-            float2 &x = lds[c * S::STRIDE + lds_pos<S::PS>(l)];
-            x = make_float2(x.x * inv, x.y * inv);
-        }
     }
-    __syncthreads();
-    transform_all<LOGL, BATCH, NT, SPLIT>(lds, tw, w16);
+    transform_all<LOGL, BATCH, NT, SPLIT>(lds, tw, w16, inv);
     float2 *dst = fine + (size_t)pc * S::L * BATCH;
     for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
         const int l = t / BATCH, c = t % BATCH;
