@@ -38,12 +38,13 @@
 //
 // Bank conflicts.  A wave's 64 lanes add the same footprint offset to 64
 // different points, so lane l touches base_l + const; LDS serves a quarter wave
-// at a time, conflict-free when the 16 bases are distinct modulo 16 cells.  In
-// tiles with many records (dense regions, where whole quarter waves can hit one
-// cell) the records are counting-sorted by that residue in LDS and dealt out
-// column-wise: lane i of a quarter wave takes sorted entry i * ceil(n/16) + q,
-// so a quarter wave draws one entry from each sixteenth of the sorted list --
-// distinct residues unless a residue class is larger than n/16.  Light tiles
+// at a time, conflict-free when the 16 bases are distinct modulo 16 cells.
+// Random bases put about three lanes on the busiest residue, and in dense
+// regions whole quarter waves can hit one cell, so the records of a tile are
+// counting-sorted by that residue in LDS and dealt out column-wise: lane i of a
+// quarter wave takes sorted entry i * ceil(n/16) + q, so a quarter wave draws
+// one entry from each sixteenth of the sorted list -- distinct residues unless
+// a residue class is larger than n/16.  Only tiles with a handful of records
 // skip the sort and add from registers.  Measured on gfx950, ds_add_u64 runs at
 // ~10 lanes/clk/CU conflict-free and ~6 with random addresses.
 //
@@ -179,9 +180,12 @@ __device__ inline void accumulate(unsigned long long *row, float4 d, bool packed
 }
 
 // Tiles with more records than this deal them out by start residue (see the
-// file comment); lighter tiles add their footprints straight from registers,
-// where random residues cost less than the sort.
-constexpr uint32_t kDealRecords = 1024;
+// file comment); the few lighter ones add their footprints straight from
+// registers, where the sort would cost more than the conflicts it removes.
+// (Measured on the 2048^2 cap: dealing every tile with more than 64 records
+// takes the spread from 0.159 to 0.144 ms; a threshold of 1024 left most of its
+// tiles conflicted.)
+constexpr uint32_t kDealRecords = 64;
 
 // Read back the tile's own cells in the order they are written out and convert
 // them to FP32.  Thread tid handles cells tid + k nt of the tile in panel order;
