@@ -121,6 +121,25 @@ def test_sinusoid_4096_full_size(fft):
         assert err <= TOL[fft], name
 
 
+@pytest.mark.parametrize("fft", ["fp32", "split_fp16"])
+def test_largest_destination_grid(fft):
+    """The largest destination grid (8192 x 8192: a 16384^2 fine grid, 131072 tiles,
+    16384-point transforms) with a million scattered points, on crops and random pixels."""
+    rng = np.random.default_rng(21)
+    n = 1 << 20
+    x = rng.uniform(-5e-3, 5e-3, n)
+    y = rng.uniform(-4e-3, 4e-3, n)
+    d = synth.sinusoidal_relief(x, y, 25e-6, 0.7e-3)
+    u = (rng.uniform(0, 1, n) * np.exp(2j * np.pi * rng.uniform(0, 1, n))).astype(np.complex64)
+    w = synth.Workload("largest", x, y, d, u, 633e-9, 0.3, 4e-6, 4e-6, 8192, 8192, 1e-5, "plane")
+    got, info = gpu_forward(w, fft)
+    assert info["nfx"] == info["nfy"] == 16384 and info["ntiles"] == 131072
+    for name, (ix, iy) in eval_sets(w, n_random=96, crop=6).items():
+        err = rel_l2(got[iy, ix], _oracle(w, ix, iy))
+        print(f"largest {fft} {name}: {err:.3e}")
+        assert err <= TOL[fft], name
+
+
 def test_linearity_and_repeat():
     torch = torch_gpu()
     import paper_1203_3583_amd as asf
