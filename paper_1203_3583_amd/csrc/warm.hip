@@ -1,0 +1,400 @@
+// Kernels of the learned warm start (include/asf_warm.h): a small convolutional
+// encoder-decoder that maps (target intensity, surface height) to a source
+// phase, trained through the forward and adjoint of the diffraction method.
+//
+// The convolutions are implicit GEMMs on the matrix cores,
+// v_mfma_f32_16x16x16_bf16 (BF16 operands, FP32 accumulation):
+//   forward  D[pixel][cout] = sum_k A[pixel][k] W[k][cout],  k = (ky 3 + kx) cin + ci,
+//            A[p][k] the input pixel p shifted by (ky-1, kx-1) (zero outside);
+//   wgrad    D[cout][k]     = sum_p dOut[p][cout] A[p][k]   (contraction over pixels);
+//   input gradient: the forward with flipped, transposed weights.
+// Channels-last storage makes every operand fetch contiguous: in a 16 x 16 x 16
+// step, lane l (row or column l % 16, k group l / 16) reads four consecutive
+// channels of one pixel (16 bytes of FP32 activations) or four consecutive k of
+// one weight row (8 bytes of BF16).  The accumulator tile of lane l holds rows
+// 4 (l / 16) + i, column l % 16.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "asf_warm.h"
+
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (finite inputs)
+__device__ __forceinline__ short bf16(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+__device__ __forceinline__ v4s bf16x4(float4 v) {
+    v4s r;
+    r[0] = bf16(v.x);
+    r[1] = bf16(v.y);
+    r[2] = bf16(v.z);
+    r[3] = bf16(v.w);
+    return r;
+}
+
+// ---- forward convolution -----------------------------------------------------
+// A wave computes 64 consecutive pixels (flattened b, y, x) x 32 output
+// channels: 4 x 2 accumulator tiles.  Four waves per workgroup, on consecutive
+// pixel tiles of the same channel block; no LDS, no barriers.
+constexpr int kConvWaves = 4;
+
+__global__ __launch_bounds__(64 * kConvWaves) void conv3x3_kernel(
+    const float *__restrict__ in, const uint16_t *__restrict__ w, const float *__restrict__ bias,
+    float *__restrict__ out, int B, int H, int W, int cin, int cout, int relu) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t npix = (int64_t)B * H * W;
+    const int64_t p0 = ((int64_t)blockIdx.x * kConvWaves + wave) * 64;
+    if (p0 >= npix) return;   // uniform over the wave
+    const int co0 = blockIdx.y * 32;
+    const int r = lane & 15, g = lane >> 4;
+    // the four pixels whose A rows this lane supplies
+    int py[4], px[4];
+    int64_t pimg[4];   // b H W of the pixel's image, or -1 past the end
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb) {
+        const int64_t p = p0 + pb * 16 + r;
+        if (p < npix) {
+            const int64_t bi = p / ((int64_t)H * W);
+            const int rest = (int)(p - bi * H * W);
+            py[pb] = rest / W;
+            px[pb] = rest - py[pb] * W;
+            pimg[pb] = bi * H * W;
+        } else {
+            py[pb] = px[pb] = 0;
+            pimg[pb] = -1;
+        }
+    }
+    v4f acc[4][2];
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc[pb][cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+    const int kin = 9 * cin;
+    const uint16_t *wrow0 = w + (size_t)(co0 + r) * kin;
+    const uint16_t *wrow1 = w + (size_t)(co0 + 16 + r) * kin;
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const float *src[4];
+        bool ok[4];
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) {
+            const int yy = py[pb] + dy, xx = px[pb] + dx;
+            ok[pb] = pimg[pb] >= 0 && yy >= 0 && yy < H && xx >= 0 && xx < W;
+            src[pb] = in + ((size_t)(ok[pb] ? pimg[pb] + (int64_t)yy * W + xx : 0)) * cin + g * 4;
+        }
+        for (int c0 = 0; c0 < cin; c0 += 16) {
+            v4s a[4];
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) {
+                const float4 v = ok[pb] ? *reinterpret_cast<const float4 *>(src[pb] + c0) : make_float4(0.f, 0.f, 0.f, 0.f);
+                a[pb] = bf16x4(v);
+            }
+            const int k = tap * cin + c0 + g * 4;
+            const v4s b0 = *reinterpret_cast<const v4s *>(wrow0 + k);
+            const v4s b1 = *reinterpret_cast<const v4s *>(wrow1 + k);
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) {
+                acc[pb][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[pb], b0, acc[pb][0], 0, 0, 0);
+                acc[pb][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[pb], b1, acc[pb][1], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const int co = co0 + cb * 16 + r;
+        const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t p = p0 + pb * 16 + g * 4 + i;
+                if (p >= npix) continue;
+                float v = acc[pb][cb][i] + bv;
+                if (relu) v = fmaxf(v, 0.f);
+                out[p * cout + co] = v;
+            }
+    }
+}
+
+// ---- weight gradient ----------------------------------------------------------
+// A wave computes a 32 (cout) x 16 (k) block of dw over a chunk of pixels and
+// adds it to dw with FP32 atomics.  k = (tap, c0 .. c0+15): the block covers 16
+// consecutive input channels of one tap.
+constexpr int kWgradChunk = 1024;   // pixels per wave
+
+__global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
+    const float *__restrict__ in, const float *__restrict__ dout, float *__restrict__ dw,
+    float *__restrict__ dbias, int B, int H, int W, int cin, int cout) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t npix = (int64_t)B * H * W;
+    const int64_t pc = ((int64_t)blockIdx.x * 4 + wave) * kWgradChunk;
+    if (pc >= npix) return;
+    const int kblocks = 9 * cin / 16;
+    const int kb = blockIdx.y % kblocks, cb2 = blockIdx.y / kblocks;
+    const int tap = (kb * 16) / cin, c0 = kb * 16 - tap * cin;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int co0 = cb2 * 32;
+    const int r = lane & 15, g = lane >> 4;
+    v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    float bsum0 = 0.f, bsum1 = 0.f;
+    const int64_t pend = pc + kWgradChunk < npix ? pc + kWgradChunk : npix;
+    for (int64_t ps = pc; ps < pend; ps += 16) {
+        // this lane's four pixels of the step: ps + 4 g + j
+        float av0[4], av1[4], bv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t p = ps + g * 4 + j;
+            av0[j] = av1[j] = bv[j] = 0.f;
+            if (p < pend) {
+                av0[j] = dout[p * cout + co0 + r];
+                av1[j] = dout[p * cout + co0 + 16 + r];
+                const int64_t bi = p / ((int64_t)H * W);
+                const int rest = (int)(p - bi * H * W);
+                const int y = rest / W, x = rest - (rest / W) * W;
+                const int yy = y + dy, xx = x + dx;
+                if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    bv[j] = in[(bi * H * W + (int64_t)yy * W + xx) * cin + c0 + r];
+            }
+        }
+        bsum0 += av0[0] + av0[1] + av0[2] + av0[3];
+        bsum1 += av1[0] + av1[1] + av1[2] + av1[3];
+        const v4s a0 = bf16x4(make_float4(av0[0], av0[1], av0[2], av0[3]));
+        const v4s a1 = bf16x4(make_float4(av1[0], av1[1], av1[2], av1[3]));
+        const v4s b = bf16x4(make_float4(bv[0], bv[1], bv[2], bv[3]));
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b, acc1, 0, 0, 0);
+    }
+    // accumulator rows are output channels 4 g + i, column k = c0 + r of this tap
+    const int kin = 9 * cin;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        atomicAdd(&dw[(size_t)(co0 + g * 4 + i) * kin + tap * cin + c0 + r], acc0[i]);
+        atomicAdd(&dw[(size_t)(co0 + 16 + g * 4 + i) * kin + tap * cin + c0 + r], acc1[i]);
+    }
+    if (dbias && kb == 0) {
+        // bias gradient from the same dout values (FP32, not rounded): sum the four
+        // k groups of each output channel
+        bsum0 += __shfl_xor(bsum0, 16);
+        bsum0 += __shfl_xor(bsum0, 32);
+        bsum1 += __shfl_xor(bsum1, 16);
+        bsum1 += __shfl_xor(bsum1, 32);
+        if (g == 0) {
+            atomicAdd(&dbias[co0 + r], bsum0);
+            atomicAdd(&dbias[co0 + 16 + r], bsum1);
+        }
+    }
+}
+
+__global__ void flip_weights_kernel(const uint16_t *__restrict__ w, uint16_t *__restrict__ wt, int cin,
+                                    int cout) {
+    const int64_t n = (int64_t)cout * 9 * cin;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        // i indexes wt[ci][tap][co]
+        const int co = (int)(i % cout);
+        const int64_t rest = i / cout;
+        const int tap = (int)(rest % 9), ci = (int)(rest / 9);
+        wt[i] = w[((int64_t)co * 9 + (8 - tap)) * cin + ci];
+    }
+}
+
+__global__ void relu_backward_kernel(const float *__restrict__ y, const float *__restrict__ dy,
+                                     float *__restrict__ dx, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dx[i] = y[i] > 0.f ? dy[i] : 0.f;
+}
+
+__global__ void pool2_kernel(const float *__restrict__ in, float *__restrict__ out, int B, int H, int W, int C,
+                             int backward) {
+    const int Ho = H / 2, Wo = W / 2;
+    const int64_t n = (int64_t)B * Ho * Wo * C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        int64_t t = i / C;
+        const int xo = (int)(t % Wo);
+        t /= Wo;
+        const int yo = (int)(t % Ho);
+        const int64_t b = t / Ho;
+        const int64_t base = ((b * H + 2 * yo) * W + 2 * xo) * C + c;
+        const int64_t rowc = (int64_t)W * C;
+        if (!backward) {
+            out[i] = 0.25f * (in[base] + in[base + C] + in[base + rowc] + in[base + rowc + C]);
+        } else {
+            // in = dout [B][Ho][Wo][C], out = din [B][H][W][C]
+            const float gq = 0.25f * in[i];
+            out[base] = gq;
+            out[base + C] = gq;
+            out[base + rowc] = gq;
+            out[base + rowc + C] = gq;
+        }
+    }
+}
+
+__global__ void up2_kernel(const float *__restrict__ in, float *__restrict__ out, int B, int H, int W, int C,
+                           int backward) {
+    // H, W: the small side
+    const int64_t n = (int64_t)B * H * W * C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        int64_t t = i / C;
+        const int x = (int)(t % W);
+        t /= W;
+        const int y = (int)(t % H);
+        const int64_t b = t / H;
+        const int64_t W2 = 2 * W;
+        const int64_t base = ((b * 2 * H + 2 * y) * W2 + 2 * x) * C + c;
+        const int64_t rowc = W2 * C;
+        if (!backward) {
+            const float v = in[i];
+            out[base] = v;
+            out[base + C] = v;
+            out[base + rowc] = v;
+            out[base + rowc + C] = v;
+        } else {
+            // in = dout [B][2H][2W][C], out = din [B][H][W][C]
+            out[i] = in[base] + in[base + C] + in[base + rowc] + in[base + rowc + C];
+        }
+    }
+}
+
+__global__ void copy_channels_kernel(const float *__restrict__ src, int src_c, int src_off, float *__restrict__ dst,
+                                     int dst_c, int dst_off, int count, int64_t npix) {
+    const int64_t n = npix * count;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = i / count;
+        const int c = (int)(i - p * count);
+        dst[p * dst_c + dst_off + c] = src[p * src_c + src_off + c];
+    }
+}
+
+__global__ void axpy_kernel(const float *__restrict__ x, float *__restrict__ y, float a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] += a * x[i];
+}
+
+__global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                            float *__restrict__ v, uint16_t *__restrict__ pb, int64_t n, float lr, float b1,
+                            float b2, float eps, float c1, float c2) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        p[i] = pi;
+        if (pb) pb[i] = (uint16_t)bf16(pi);
+    }
+}
+
+inline int grid_for(int64_t n) {
+    const int64_t blocks = (n + 255) / 256;
+    return (int)(blocks < 65536 ? (blocks > 0 ? blocks : 1) : 65536);
+}
+
+inline int done(hipError_t e) { return e == hipSuccess ? 0 : -1; }
+
+}  // namespace
+
+extern "C" {
+
+int asf_warm_conv3x3(const float *in, const uint16_t *w, const float *bias, float *out, int32_t B, int32_t H,
+                     int32_t W, int32_t cin, int32_t cout, int32_t relu, void *stream) {
+    if (!in || !w || !out || B <= 0 || H <= 0 || W <= 0 || cin <= 0 || cout <= 0 || cin % 16 || cout % 32)
+        return -1;
+    const int64_t npix = (int64_t)B * H * W;
+    const int64_t tiles = (npix + 63) / 64;
+    const dim3 grid((unsigned)((tiles + kConvWaves - 1) / kConvWaves), (unsigned)(cout / 32));
+    hipLaunchKernelGGL(conv3x3_kernel, grid, dim3(64 * kConvWaves), 0, static_cast<hipStream_t>(stream), in, w,
+                       bias, out, B, H, W, cin, cout, relu);
+    return done(hipGetLastError());
+}
+
+int asf_warm_conv3x3_wgrad(const float *in, const float *dout, float *dw, float *dbias, int32_t B, int32_t H,
+                           int32_t W, int32_t cin, int32_t cout, void *stream) {
+    if (!in || !dout || !dw || B <= 0 || H <= 0 || W <= 0 || cin <= 0 || cout <= 0 || cin % 16 || cout % 32)
+        return -1;
+    const int64_t npix = (int64_t)B * H * W;
+    const int64_t chunks = (npix + kWgradChunk - 1) / kWgradChunk;
+    const dim3 grid((unsigned)((chunks + 3) / 4), (unsigned)((cout / 32) * (9 * cin / 16)));
+    hipLaunchKernelGGL(conv3x3_wgrad_kernel, grid, dim3(256), 0, static_cast<hipStream_t>(stream), in, dout, dw,
+                       dbias, B, H, W, cin, cout);
+    return done(hipGetLastError());
+}
+
+int asf_warm_flip_weights(const uint16_t *w, uint16_t *wt, int32_t cin, int32_t cout, void *stream) {
+    if (!w || !wt || cin <= 0 || cout <= 0) return -1;
+    hipLaunchKernelGGL(flip_weights_kernel, dim3(grid_for((int64_t)cout * 9 * cin)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), w, wt, cin, cout);
+    return done(hipGetLastError());
+}
+
+int asf_warm_relu_backward(const float *y, const float *dy, float *dx, int64_t n, void *stream) {
+    if (!y || !dy || !dx || n <= 0) return -1;
+    hipLaunchKernelGGL(relu_backward_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), y,
+                       dy, dx, n);
+    return done(hipGetLastError());
+}
+
+int asf_warm_pool2(const float *in, float *out, int32_t B, int32_t H, int32_t W, int32_t C, void *stream) {
+    if (!in || !out || B <= 0 || H <= 1 || W <= 1 || C <= 0 || (H & 1) || (W & 1)) return -1;
+    hipLaunchKernelGGL(pool2_kernel, dim3(grid_for((int64_t)B * H * W * C / 4)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), in, out, B, H, W, C, 0);
+    return done(hipGetLastError());
+}
+
+int asf_warm_pool2_backward(const float *dout, float *din, int32_t B, int32_t H, int32_t W, int32_t C,
+                            void *stream) {
+    if (!dout || !din || B <= 0 || H <= 1 || W <= 1 || C <= 0 || (H & 1) || (W & 1)) return -1;
+    hipLaunchKernelGGL(pool2_kernel, dim3(grid_for((int64_t)B * H * W * C / 4)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), dout, din, B, H, W, C, 1);
+    return done(hipGetLastError());
+}
+
+int asf_warm_up2(const float *in, float *out, int32_t B, int32_t H, int32_t W, int32_t C, void *stream) {
+    if (!in || !out || B <= 0 || H <= 0 || W <= 0 || C <= 0) return -1;
+    hipLaunchKernelGGL(up2_kernel, dim3(grid_for((int64_t)B * H * W * C)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), in, out, B, H, W, C, 0);
+    return done(hipGetLastError());
+}
+
+int asf_warm_up2_backward(const float *dout, float *din, int32_t B, int32_t H, int32_t W, int32_t C,
+                          void *stream) {
+    if (!dout || !din || B <= 0 || H <= 0 || W <= 0 || C <= 0) return -1;
+    hipLaunchKernelGGL(up2_kernel, dim3(grid_for((int64_t)B * H * W * C)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), dout, din, B, H, W, C, 1);
+    return done(hipGetLastError());
+}
+
+int asf_warm_copy_channels(const float *src, int32_t src_c, int32_t src_off, float *dst, int32_t dst_c,
+                           int32_t dst_off, int32_t count, int64_t npix, void *stream) {
+    if (!src || !dst || count <= 0 || npix <= 0 || src_off < 0 || dst_off < 0 || src_off + count > src_c ||
+        dst_off + count > dst_c)
+        return -1;
+    hipLaunchKernelGGL(copy_channels_kernel, dim3(grid_for(npix * count)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), src, src_c, src_off, dst, dst_c, dst_off, count, npix);
+    return done(hipGetLastError());
+}
+
+int asf_warm_axpy(const float *x, float *y, float a, int64_t n, void *stream) {
+    if (!x || !y || n <= 0) return -1;
+    hipLaunchKernelGGL(axpy_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), x, y, a, n);
+    return done(hipGetLastError());
+}
+
+int asf_warm_adam(float *p, const float *g, float *m, float *v, uint16_t *pb, int64_t n, float lr, float b1,
+                  float b2, float eps, int32_t t, void *stream) {
+    if (!p || !g || !m || !v || n <= 0 || t < 1) return -1;
+    const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+    hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), p, g, m, v,
+                       pb, n, lr, b1, b2, eps, c1, c2);
+    return done(hipGetLastError());
+}
+
+}  // extern "C"

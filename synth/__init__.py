@@ -38,6 +38,9 @@ __all__ = [
     "quadratic_profile",
     "line_config",
     "LINE_CONFIG_NAMES",
+    "zernike_height",
+    "smooth_phase",
+    "warm_pair_geometry",
 ]
 
 
@@ -294,3 +297,56 @@ LINE_CONFIG_NAMES = tuple(_LINE_CONFIGS)
 def line_config(name: str, **kw) -> LineWorkload:
     """Build a named 1D profile (keyword overrides go to its generator)."""
     return _LINE_CONFIGS[name](**kw)
+
+
+# ---------------------------------------------------------------------------
+# Inputs of the learned warm start: random surfaces (Zernike height maps) and
+# random smooth source phases whose intensities the forward method produces.
+# ---------------------------------------------------------------------------
+
+def _zernike_radial(n: int, m: int, rho: np.ndarray) -> np.ndarray:
+    from math import factorial
+    out = np.zeros_like(rho)
+    for k in range((n - m) // 2 + 1):
+        c = (-1) ** k * factorial(n - k) / (factorial(k) * factorial((n + m) // 2 - k) * factorial((n - m) // 2 - k))
+        out += c * rho ** (n - 2 * k)
+    return out
+
+
+def zernike_height(rng: np.random.Generator, x: np.ndarray, y: np.ndarray, radius: float,
+                   max_order: int = 6, max_abs: float = 60e-6) -> np.ndarray:
+    """Height map d1(x, y): a sum of the Zernike polynomials of radial order <= max_order
+    (piston excluded) on the disc of the given radius (continued outside it), with
+    standard-normal coefficients, scaled so that max |d1| = max_abs * U(0.2, 1)."""
+    rho = np.hypot(x, y) / radius
+    th = np.arctan2(y, x)
+    d = np.zeros_like(rho)
+    for n in range(1, max_order + 1):
+        for m in range(-n, n + 1, 2):
+            r = _zernike_radial(n, abs(m), rho)
+            ang = np.cos(m * th) if m >= 0 else np.sin(-m * th)
+            d += rng.standard_normal() * r * ang
+    scale = max_abs * rng.uniform(0.2, 1.0) / max(np.abs(d).max(), 1e-30)
+    return d * scale
+
+
+def smooth_phase(rng: np.random.Generator, nx: int, ny: int, sigma_px: float = 6.0,
+                 amplitude: float = 3.0) -> np.ndarray:
+    """Phase (ny, nx) float64: standard-normal noise filtered by a periodic Gaussian of
+    sigma_px pixels, scaled to standard deviation `amplitude` radians."""
+    noise = rng.standard_normal((ny, nx))
+    fy = np.fft.fftfreq(ny)[:, None]
+    fx = np.fft.fftfreq(nx)[None, :]
+    gain = np.exp(-2.0 * (np.pi * sigma_px) ** 2 * (fx * fx + fy * fy))
+    ph = np.real(np.fft.ifft2(np.fft.fft2(noise) * gain))
+    return ph * (amplitude / max(ph.std(), 1e-30))
+
+
+def warm_pair_geometry(side: int = 512, seed: int = 0):
+    """Source grid of the warm-start problems: side^2 samples at 8 um with +-0.3 pitch
+    jitter, lambda = 532 nm, z0 = 0.1 m, side^2 destination at 8 um.  Returns
+    (x, y, lam, z0, p2, m); heights come from zernike_height on this grid."""
+    rng = np.random.default_rng(seed)
+    p = 8e-6
+    x, y = jittered_grid(rng, side, side, p, 0.3 * p)
+    return x, y, 532e-9, 0.1, p, side

@@ -9,12 +9,15 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "asf.h")
+HEADERS = [HEADER, os.path.join(ROOT, "include", "asf_warm.h")]
 
 
-def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(asf_[a-z_]+)\s*\(", text)))
+def declared_functions(headers=(HEADER,)):
+    names = set()
+    for h in headers:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(asf_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -37,7 +40,9 @@ def test_header_declares_the_boundary():
 
 def test_library_exports_every_declared_symbol(asf):
     lib = ctypes.CDLL(asf.asf.LIB_PATH)
-    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    names = declared_functions(HEADERS)
+    assert "asf_warm_conv3x3" in names and "asf_warm_adam" in names
+    missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
 
 
