@@ -8,8 +8,9 @@ One step is the whole hot path over one batch of synthetic input already
 resident in HBM: the FP64 pre-phase and tile binning (asf_setpts) and the
 spreading plus both FFT passes with the fused deconvolution (asf_forward).
 The line also reports the geometry-cached forward alone (``fwd``), the
-adjoint of the same plan (``adjoint``, the type-2 direction used for gradients)
-and the one-dimensional path on a batch of the quadratic profile (``line_1d``).
+adjoint of the same plan (``adjoint``, the type-2 direction used for gradients),
+the one-dimensional path on a batch of the quadratic profile (``line_1d``) and one
+training sample and one inference of the learned warm start (``warm_start``).
 
 Prints one JSON line.  ``value`` is NU points/s (source points per second of
 whole-step time).  Both FFT precisions are timed; the headline is the faster
@@ -123,6 +124,51 @@ def line_bench(torch, asf, synth, steps, warmup, batch=4096):
             "algorithmic_bytes": alg, "hbm_frac": alg / sec / (HBM_PEAK_GBS * 1e9)}
 
 
+def warm_bench(torch, steps=3):
+    """The learned warm start at its working size: one training sample of the
+    encoder-decoder on a 512^2 problem (network forward, the diffraction forward and
+    adjoint for the intensity loss, network backward), timed with HIP events."""
+    import numpy as np
+    import paper_1203_3583_amd.warmstart as ws
+
+    pr = ws.HoloProblems(side=512, seed=0)
+    d, inten, _ = pr.make(np.random.default_rng(1))
+    net = ws.WarmNet(base=32, seed=0)
+
+    def sample():
+        out, cache = net.forward(pr.net_input(d, inten))
+        loss, dphi = ws.physics_loss_and_grad(pr, d, inten, out[0, :, :, 0].contiguous())
+        dout = torch.zeros_like(out)
+        dout[0, :, :, 0] = dphi
+        net.backward(dout, cache)
+        return out
+
+    sample()
+    start, mid, stop = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    torch.cuda.synchronize()
+    fwd = 0.0
+    start.record()
+    for _ in range(steps):
+        sample()
+    stop.record()
+    torch.cuda.synchronize()
+    total = start.elapsed_time(stop) / steps
+    start.record()
+    for _ in range(steps):
+        net.forward(pr.net_input(d, inten))
+    stop.record()
+    torch.cuda.synchronize()
+    fwd = start.elapsed_time(stop) / steps
+    # forward FLOPs of the 15 convolutions (2 per multiply-add) at 512^2 and below
+    flops = 0
+    hw = {0: 1, 1: 1, 2: 4, 3: 4, 4: 16, 5: 16, 6: 64, 7: 64, 8: 16, 9: 16, 10: 4, 11: 4, 12: 1, 13: 1, 14: 1}
+    for i, (ci, co, _) in enumerate(net.shapes):
+        flops += 2 * 9 * ci * co * (512 * 512 // hw[i])
+    return {"workload": "encoder-decoder (4 levels, base 32) on a 512x512 phase-hologram problem",
+            "train_sample_ms": total, "inference_ms": fwd,
+            "inference_tflops": flops / (fwd * 1e-3) / 1e12, "unit": "ms per sample"}
+
+
 def time_steps(torch, plan, x, y, d, u, out, steps, warmup, stage_events):
     for _ in range(warmup):
         plan.setpts(x, y, d)
@@ -185,6 +231,7 @@ def main():
         plan.close()
 
     line = line_bench(torch, asf, synth, args.steps, args.warmup)
+    warm = warm_bench(torch)
 
     if args.copy_calibration:
         a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
@@ -228,6 +275,7 @@ def main():
         "adjoint": {"ms_per_call": r["adj_sec"] * 1e3, "value": n / r["adj_sec"], "unit": "NU points/s",
                     "stages_ms": {s: round(t, 4) for s, t in r["adj_stages"].items()}},
         "line_1d": line,
+        "warm_start": warm,
         "roofline": {
             "kernel": "spread",
             "bound": "hbm",
