@@ -39,6 +39,7 @@ __all__ = [
     "line_config",
     "LINE_CONFIG_NAMES",
     "zernike_height",
+    "zernike_basis",
     "smooth_phase",
     "warm_pair_geometry",
 ]
@@ -313,19 +314,27 @@ def _zernike_radial(n: int, m: int, rho: np.ndarray) -> np.ndarray:
     return out
 
 
-def zernike_height(rng: np.random.Generator, x: np.ndarray, y: np.ndarray, radius: float,
-                   max_order: int = 6, max_abs: float = 60e-6) -> np.ndarray:
-    """Height map d1(x, y): a sum of the Zernike polynomials of radial order <= max_order
-    (piston excluded) on the disc of the given radius (continued outside it), with
-    standard-normal coefficients, scaled so that max |d1| = max_abs * U(0.2, 1)."""
+def zernike_basis(x: np.ndarray, y: np.ndarray, radius: float, max_order: int = 6) -> np.ndarray:
+    """The Zernike polynomials of radial orders 1 .. max_order (piston excluded) on the disc
+    of the given radius (continued outside it) at the points (x, y): array (terms, n)."""
     rho = np.hypot(x, y) / radius
     th = np.arctan2(y, x)
-    d = np.zeros_like(rho)
+    rows = []
     for n in range(1, max_order + 1):
         for m in range(-n, n + 1, 2):
             r = _zernike_radial(n, abs(m), rho)
-            ang = np.cos(m * th) if m >= 0 else np.sin(-m * th)
-            d += rng.standard_normal() * r * ang
+            rows.append(r * (np.cos(m * th) if m >= 0 else np.sin(-m * th)))
+    return np.array(rows)
+
+
+def zernike_height(rng: np.random.Generator, x: np.ndarray, y: np.ndarray, radius: float,
+                   max_order: int = 6, max_abs: float = 60e-6, basis: np.ndarray | None = None) -> np.ndarray:
+    """Height map d1(x, y): a sum of the Zernike polynomials of radial order <= max_order
+    (piston excluded) with standard-normal coefficients, scaled so that
+    max |d1| = max_abs * U(0.2, 1).  `basis` (from zernike_basis on the same points)
+    saves re-evaluating the polynomials."""
+    z = zernike_basis(x, y, radius, max_order) if basis is None else basis
+    d = rng.standard_normal(z.shape[0]) @ z
     scale = max_abs * rng.uniform(0.2, 1.0) / max(np.abs(d).max(), 1e-30)
     return d * scale
 
