@@ -109,7 +109,7 @@ size_t asf_workspace_bytes(int64_t n_src, const asf_params *p);
  * Create a plan and bin the geometry (Sec. 2: the pre-phase of Eq. (8) and the
  * per-point frequencies of Eq. (9)).
  *   out        receives the plan handle (host pointer to a handle)
- *   n_src      number of source points, >= 1
+ *   n_src      number of source points, in [1, 2^30 - 1]
  *   x1, y1, d1 FP64 [n_src] device arrays: sample positions and surface
  *              displacement d1(x1) (m); read during the call only
  *   p          host pointer to parameters (copied)
@@ -190,8 +190,9 @@ int asf_plan_info(asf_plan_t plan, asf_info *info);
  * asf_set_timing(plan, 1) makes later asf_setpts/asf_forward/asf_adjoint calls
  * record an event pair around each stage; asf_stage_times synchronises on the
  * last pair and writes up to n durations (ms, host array) in the order
- * [count, scan, scatter, spread, fft_pass1, fft_pass2, adj_fft_pass2,
- * adj_fft_pass1, interp], returning how many it wrote (negative on error); a
+ * [bin, scan, scatter, spread, fft_pass1, fft_pass2, adj_fft_pass2,
+ * adj_fft_pass1, interp] (scan and scatter are the binning's fallback for
+ * crowded tiles and take microseconds when it is not needed), returning how many it wrote (negative on error); a
  * stage not run since timing was enabled reads -1.  Timing adds a few
  * microseconds per stage.
  */

@@ -24,7 +24,7 @@ ASF_FFT_FP32 = 0
 ASF_FFT_SPLIT_FP16 = 1
 ASF_INCIDENT_NONE = 2
 
-STAGES = ("count", "scan", "scatter", "spread", "fft_pass1", "fft_pass2",
+STAGES = ("bin", "scan", "scatter", "spread", "fft_pass1", "fft_pass2",
           "adj_fft_pass2", "adj_fft_pass1", "interp")
 
 _CODES = {ASF_EINVAL: "EINVAL", ASF_EDOMAIN: "EDOMAIN", ASF_ENOMEM: "ENOMEM", ASF_EHIP: "EHIP",

@@ -69,7 +69,8 @@ struct Layout {
 
 int check_params(int64_t n, const asf_params *p) {
     if (!p) return fail(ASF_EINVAL, "params is NULL");
-    if (n < 1 || n > (int64_t(1) << 30)) return fail(ASF_EINVAL, "n_src must be in [1, 2^30], got %lld", (long long)n);
+    // slot indices are 32-bit: 4 n_src slots must stay below 2^32
+    if (n < 1 || n >= (int64_t(1) << 30)) return fail(ASF_EINVAL, "n_src must be in [1, 2^30 - 1], got %lld", (long long)n);
     const double v[4] = {p->lambda, p->z0, p->p2x, p->p2y};
     const char *names[4] = {"lambda", "z0", "p2x", "p2y"};
     for (int i = 0; i < 4; ++i)
@@ -207,6 +208,7 @@ struct asf_plan_s {
     FftShape sh1, sh2;
     float2 *fine, *mid, *dx, *dy, *twx, *twy, *w16;
     int timing;
+    bool count_first;   // bin with the compact layout directly (crowded last time)
     bool events;
     hipEvent_t ev[2 * asf::NSTAGES];
     bool recorded[asf::NSTAGES];
@@ -245,12 +247,18 @@ struct StageMark {
 int run_geometry(asf_plan_s *p, const double *x, const double *y, const double *d, hipStream_t s) {
     hipError_t e;
     {
-        StageMark m(p, asf::STAGE_COUNT, s);
+        StageMark m(p, asf::STAGE_BIN, s);
         e = asf::launch_bin_reset(p->bin, p->lay.ntiles, s);
         if (e != hipSuccess) return hip_fail(e, "bin_reset launch");
-        e = asf::launch_bin_count(p->geo, p->bin, p->lay.n, x, y, d, s);
-        if (e != hipSuccess) return hip_fail(e, "bin_count launch");
+        if (p->count_first) {
+            e = asf::launch_bin_count(p->geo, p->bin, p->lay.n, x, y, d, s);
+            if (e != hipSuccess) return hip_fail(e, "bin_count launch");
+        } else {
+            e = asf::launch_bin_fill(p->geo, p->bin, p->lay.n, x, y, d, s);
+            if (e != hipSuccess) return hip_fail(e, "bin_fill launch");
+        }
     }
+    // compact layout: both kernels return at once when the slabs held
     {
         StageMark m(p, asf::STAGE_SCAN, s);
         e = asf::launch_bin_scan(p->bin, p->lay.ntiles, s);
@@ -317,8 +325,13 @@ int read_status(asf_plan_s *p, hipStream_t s) {
     if (e != hipSuccess) return hip_fail(e, "status read");
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    if (st & 1u) return fail(ASF_EDOMAIN, "some point has r0 = z0 - d1 <= 0 or a non-finite coordinate");
-    if (st & 2u) return fail(ASF_EHIP, "internal error: tile bin overflow");
+    // kStatusCompact and kStatusFits only describe the binned layout: the next
+    // binning counts first if this one needed the compact layout, unless its
+    // scan found that every tile would now fit its slab
+    p->count_first = (st & asf::kStatusCompact) && !(st & asf::kStatusFits);
+    if (st & asf::kStatusDomain)
+        return fail(ASF_EDOMAIN, "some point has r0 = z0 - d1 <= 0 or a non-finite coordinate");
+    if (st & asf::kStatusOverflow) return fail(ASF_EHIP, "internal error: tile bin overflow");
     return ASF_OK;
 }
 
@@ -354,13 +367,20 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
     pl->ws = static_cast<char *>(workspace);
     char *w = pl->ws;
     pl->bin.status = reinterpret_cast<uint32_t *>(w + L.off_status);
-    pl->bin.sched = pl->bin.status + 16;   // same 256-byte segment, its own 64-byte line
     pl->bin.tile_start = reinterpret_cast<uint32_t *>(w + L.off_tile_start);
     pl->bin.cursor = reinterpret_cast<uint32_t *>(w + L.off_cursor);
     pl->bin.cell = reinterpret_cast<uint32_t *>(w + L.off_cell);
     pl->bin.frac = reinterpret_cast<float2 *>(w + L.off_frac);
     pl->bin.phase = reinterpret_cast<float2 *>(w + L.off_phase);
     pl->bin.perm = reinterpret_cast<uint32_t *>(w + L.off_perm);
+    {
+        // slab slots per tile: a multiple of 16 but not of 256, so that the tiles'
+        // slabs do not start at power-of-two strides (the workgroups spreading
+        // neighbouring tiles would read the same memory channels)
+        uint32_t cap = (uint32_t)(L.slot_cap / L.ntiles) & ~15u;
+        if (cap >= 256 && cap % 256 == 0) cap -= 16;
+        pl->bin.cap = cap;
+    }
     pl->fine = reinterpret_cast<float2 *>(w + L.off_fine);
     pl->mid = reinterpret_cast<float2 *>(w + L.off_mid);
     pl->dx = reinterpret_cast<float2 *>(w + L.off_dx);

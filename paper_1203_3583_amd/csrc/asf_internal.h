@@ -9,16 +9,37 @@
 namespace asf {
 
 // Binned point list: one slot per (point, fine-grid tile its footprint touches).
+// Two layouts share the slot arrays.  Slab (the normal case): tile t owns the
+// `cap` slots from t * cap, and cursor[t] counts its records (also past cap).
+// Compact (after a slab overflowed): the tiles' records are packed in tile
+// order, tile t in [tile_start[t], tile_start[t + 1]).  Status bit 2 names the
+// layout in use.
 struct Binned {
-    uint32_t *status;      // [1] bit 0: domain error, bit 1: bin overflow
-    uint32_t *sched;       // [2] spreading tile queue: next tile, finished workgroups (zero between launches)
-    uint32_t *tile_start;  // [ntiles + 1] exclusive scan of slot counts per tile
-    uint32_t *cursor;      // [ntiles] counts, then insertion cursors
+    uint32_t *status;      // [1] kStatus* bits
+    uint32_t *tile_start;  // [ntiles + 1] compact layout: exclusive scan of slot counts per tile
+    uint32_t *cursor;      // [ntiles] slot counts; compact layout: then insertion cursors
     uint32_t *cell;        // [slot_cap] first footprint cell, l0x | l0y << 16
     float2 *frac;          // [slot_cap] (gx - l0x - (w-1)/2, gy - l0y - (w-1)/2), in (-1/2, 1/2]
     float2 *phase;         // [slot_cap] exp(i phi_j), the pre-phase of Eq. (8)
     uint32_t *perm;        // [slot_cap] index j of the point in the caller's order
+    uint32_t cap;          // slab slots per tile, slot_cap / ntiles
 };
+
+constexpr uint32_t kStatusDomain = 1u;    // some point has r0 <= 0 or a non-finite coordinate
+constexpr uint32_t kStatusOverflow = 2u;  // compact layout ran out of slots (internal error)
+constexpr uint32_t kStatusCompact = 4u;   // the compact layout is in use
+constexpr uint32_t kStatusFits = 8u;      // compact layout, but every tile would fit its slab
+
+// Slots [s0, s1) of tile t in whichever layout the last binning left.
+__device__ inline void tile_slots(const Binned &b, int t, uint32_t &s0, uint32_t &s1) {
+    if (b.status[0] & kStatusCompact) {
+        s0 = b.tile_start[t];
+        s1 = b.tile_start[t + 1];
+    } else {
+        s0 = (uint32_t)t * b.cap;
+        s1 = s0 + min(b.cursor[t], b.cap);
+    }
+}
 
 // Scalars the geometry kernels need (all FP64 where the paper's phases live).
 struct GeoParams {
@@ -79,15 +100,20 @@ hipError_t launch_line_forward(const LineGeo &g, const LineBins &b, const float2
                                int batch, const float2 *u1, float2 *u2, hipStream_t s);
 
 enum {
-    STAGE_COUNT = 0, STAGE_SCAN, STAGE_SCATTER, STAGE_SPREAD, STAGE_FFT1, STAGE_FFT2,   // forward
+    STAGE_BIN = 0, STAGE_SCAN, STAGE_SCATTER, STAGE_SPREAD, STAGE_FFT1, STAGE_FFT2,   // forward
     STAGE_ADJ_FFT2, STAGE_ADJ_FFT1, STAGE_INTERP,                                      // adjoint
     NSTAGES
 };
 
 // ---- launchers (one per kernel family) ---------------------------------------
 hipError_t launch_bin_reset(const Binned &b, int ntiles, hipStream_t s);
+// binning: the slab pass (bin_fill) or the count of the compact layout
+// (bin_count), then the compact layout's scan and second pass, which return at
+// once unless the status word says the compact layout is in use
 hipError_t launch_bin_count(const GeoParams &g, const Binned &b, int64_t n, const double *x,
                             const double *y, const double *d, hipStream_t s);
+hipError_t launch_bin_fill(const GeoParams &g, const Binned &b, int64_t n, const double *x,
+                           const double *y, const double *d, hipStream_t s);
 hipError_t launch_bin_scan(const Binned &b, int ntiles, hipStream_t s);
 hipError_t launch_bin_scatter(const GeoParams &g, const Binned &b, int64_t n, const double *x,
                               const double *y, const double *d, hipStream_t s);

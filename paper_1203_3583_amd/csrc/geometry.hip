@@ -22,10 +22,20 @@
 //
 // Binning: each point is listed once in every tile its w x w footprint touches
 // (1, 2 or 4 tiles), so the spreading kernel can own its tile outright and write
-// it with plain stores.  Counting and scattering aggregate per wavefront: the
-// lanes are grouped by tile without memory traffic, then one lane per group
-// issues the atomic -- all groups' atomics in the same instruction, so a wave
-// waits for one round trip rather than one per tile.
+// it with plain stores.  When the points cover the fine grid evenly, one pass
+// bins them into fixed slabs of slots, one per tile (the workspace holds 4 slots
+// per point, so a slab has 4 n / ntiles): a per-tile cursor hands out the slots
+// and counts the records.  If some tile receives more records than its slab
+// (points crowded into part of the grid), the compact layout is built instead:
+// an exclusive scan of the per-tile counts, then a second pass that packs the
+// records in tile order.  The scan and that pass are always launched and return
+// at once when the slabs held, so the host never waits for the decision.  A
+// plan whose last synchronised binning needed the compact layout counts first
+// (a lighter pass than the slab pass it would waste) until a scan reports that
+// every tile would fit its slab again.  Slot reservation aggregates per
+// wavefront: the lanes are grouped by tile without memory traffic, then one lane
+// per group issues the atomic -- all groups' atomics in the same instruction, so
+// a wave waits for one round trip rather than one per tile.
 #include "asf_internal.h"
 
 namespace asf {
@@ -115,34 +125,123 @@ __device__ inline WaveGroup wave_group(int key, bool active) {
 __global__ void __launch_bounds__(256) bin_reset_kernel(Binned b, int ntiles) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < ntiles) b.cursor[i] = 0u;
-    if (i == 0) {
-        b.status[0] = 0u;
-        b.sched[0] = 0u;
-        b.sched[1] = 0u;
-    }
+    if (i == 0) b.status[0] = 0u;
 }
 
 constexpr int kGeoThreads = 256;
-// points per thread, their loads in flight together: the count kernel is light on
-// registers and takes four; the scatter kernel takes two, which keeps it at 70
-// VGPRs (measured on the 2048^2 cap: 0.088 ms with four, 0.074 ms with two)
+// points per thread, their loads in flight together: the counting pass is light
+// on registers and takes four; the binning passes take two, which keeps them at
+// 70-85 VGPRs (measured on the 2048^2 cap: 0.088 ms with four, 0.074 ms with two)
 constexpr int kCountPoints = 4;
-constexpr int kScatterPoints = 2;
+constexpr int kBinPoints = 2;
+// workgroups of the compact layout's second pass, which loops over the point
+// blocks: one round of the whole chip at its 5 waves per SIMD, and when no slab
+// overflowed the launch costs only these returning at once
+constexpr int kFallbackBlocks = 1280;
 
-// point j of this thread's k-th batch: consecutive lanes take consecutive points
-template <int P>
-__device__ inline int64_t geo_index(int k) {
-    return ((int64_t)blockIdx.x * P + k) * kGeoThreads + threadIdx.x;
+// point j of this thread's k-th batch in block blk (P batches per block):
+// consecutive lanes take consecutive points
+template <int P = kBinPoints>
+__device__ inline int64_t geo_index(int64_t blk, int k) {
+    return (blk * P + k) * kGeoThreads + threadIdx.x;
 }
 
+// Bin the points of block blk.  SLAB: reserve slots in the tiles' slabs; a
+// record past its slab's end is counted but not written, and selects the
+// compact layout.  Compact: the cursors start at the tiles' scanned offsets.
+// All lanes of the wave must call this together.
+template <bool SLAB>
+__device__ inline void bin_block(const GeoParams &g, const Binned &b, int64_t n, int64_t blk,
+                                 const double *__restrict__ x, const double *__restrict__ y,
+                                 const double *__restrict__ d) {
+    double xv[kBinPoints], yv[kBinPoints], dv[kBinPoints];
+#pragma unroll
+    for (int k = 0; k < kBinPoints; ++k) {
+        const int64_t j = geo_index(blk, k);
+        const bool in = j < n;
+        xv[k] = in ? x[j] : 0.0;
+        yv[k] = in ? y[j] : 0.0;
+        dv[k] = in ? d[j] : 0.0;
+    }
+    PointTiles p[kBinPoints];
+    WaveGroup grp[kBinPoints][4];
+    uint32_t base[kBinPoints][4];
+#pragma unroll
+    for (int k = 0; k < kBinPoints; ++k) {
+        p[k].n = 0;
+        if (geo_index(blk, k) < n) {
+            p[k] = point_tiles(g, xv[k], yv[k], dv[k]);
+            if (SLAB && p[k].n == 0) atomicOr(b.status, kStatusDomain);
+        }
+        // group the replica keys, then let the leaders reserve their groups'
+        // slots; the atomics of all batches and replicas are in flight at once
+#pragma unroll
+        for (int r = 0; r < 4; ++r) grp[k][r] = wave_group(r < p[k].n ? p[k].key[r] : 0, r < p[k].n);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            base[k][r] = (r < p[k].n && grp[k][r].leader == __lane_id())
+                             ? atomicAdd(&b.cursor[p[k].key[r]], grp[k][r].size) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kBinPoints; ++k) {
+        float2 ph = make_float2(0.f, 0.f);
+        if (p[k].n > 0) {
+            // phi / (2 pi) = k (|x|^2 / (2 r0) [- d]) / (2 pi) = |x|^2 s / 2 [- d / lambda]
+            double rev = 0.5 * p[k].s * (xv[k] * xv[k] + yv[k] * yv[k]);
+            if (!g.plane) rev -= dv[k] * g.inv_lambda;
+            // off-axis window: -k (x x0 + y y0) / r0 = -2 pi (x x0 + y y0) s
+            rev -= (xv[k] * g.x0 + yv[k] * g.y0) * p[k].s;
+            const float t = (float)(rev - rint(rev));   // exact in FP64, then one rounding
+            float sn, cs;
+            sincospif(2.f * t, &sn, &cs);
+            ph = make_float2(cs, sn);
+        }
+        const uint32_t cell = (uint32_t)p[k].l0x | ((uint32_t)p[k].l0y << 16);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const bool act = r < p[k].n;
+            const int key = act ? p[k].key[r] : 0;
+            const uint32_t pos = __shfl(base[k][r], grp[k][r].leader) + grp[k][r].rank;
+            uint32_t slot;
+            bool ok;
+            if (SLAB) {
+                slot = (uint32_t)key * b.cap + pos;
+                ok = pos < b.cap;
+                // one flag per wave: a crowded tile can overflow by millions of records
+                if (__ballot(act && !ok) != 0ull && __lane_id() == 0) atomicOr(b.status, kStatusCompact);
+            } else {
+                slot = pos;
+                ok = act && slot < b.tile_start[key + 1];
+                if (act && !ok) atomicOr(b.status, kStatusOverflow);
+            }
+            if (act && ok) {
+                b.cell[slot] = cell;
+                b.frac[slot] = make_float2(p[k].fx, p[k].fy);
+                b.phase[slot] = ph;
+                b.perm[slot] = (uint32_t)geo_index(blk, k);
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kGeoThreads) bin_fill_kernel(GeoParams g, Binned b, int64_t n,
+                                                               const double *__restrict__ x,
+                                                               const double *__restrict__ y,
+                                                               const double *__restrict__ d) {
+    bin_block<true>(g, b, n, blockIdx.x, x, y, d);
+}
+
+// Count-first binning (the compact layout without the slab pass): records per
+// tile, one non-returning atomic per distinct tile per wave and replica.
 __global__ void __launch_bounds__(kGeoThreads) bin_count_kernel(GeoParams g, Binned b, int64_t n,
                                                                 const double *__restrict__ x,
                                                                 const double *__restrict__ y,
                                                                 const double *__restrict__ d) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(b.status, kStatusCompact);
     double xv[kCountPoints], yv[kCountPoints], dv[kCountPoints];
 #pragma unroll
     for (int k = 0; k < kCountPoints; ++k) {
-        const int64_t j = geo_index<kCountPoints>(k);
+        const int64_t j = geo_index<kCountPoints>(blockIdx.x, k);
         const bool in = j < n;
         xv[k] = in ? x[j] : 0.0;
         yv[k] = in ? y[j] : 0.0;
@@ -152,11 +251,10 @@ __global__ void __launch_bounds__(kGeoThreads) bin_count_kernel(GeoParams g, Bin
     for (int k = 0; k < kCountPoints; ++k) {
         PointTiles p;
         p.n = 0;
-        if (geo_index<kCountPoints>(k) < n) {
+        if (geo_index<kCountPoints>(blockIdx.x, k) < n) {
             p = point_tiles(g, xv[k], yv[k], dv[k]);
-            if (p.n == 0) atomicOr(b.status, 1u);
+            if (p.n == 0) atomicOr(b.status, kStatusDomain);
         }
-        // one non-returning atomic per distinct tile per wave and replica
         for (int r = 0; r < 4; ++r) {
             const bool act = r < p.n;
             const WaveGroup grp = wave_group(act ? p.key[r] : 0, act);
@@ -165,7 +263,7 @@ __global__ void __launch_bounds__(kGeoThreads) bin_count_kernel(GeoParams g, Bin
     }
 }
 
-// Exclusive scan of the per-tile counts by one workgroup of 1024 threads, in
+// Compact layout: exclusive scan of the per-tile counts by one workgroup of 1024 threads, in
 // chunks of 8192 tiles: each thread loads 8 consecutive counts at once, the
 // thread sums are scanned within waves by shuffles and across the 16 waves
 // through LDS, and a running carry links the chunks.
@@ -174,7 +272,11 @@ constexpr int kScanPer = 8;
 
 __global__ void __launch_bounds__(kScanThreads) bin_scan_kernel(Binned b, int ntiles) {
     __shared__ uint32_t wsum[kScanThreads / 64];
+    __shared__ uint32_t too_big;
+    if (!(b.status[0] & kStatusCompact)) return;   // every slab held its tile
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    if (t == 0) too_big = 0u;
+    __syncthreads();
     uint32_t carry = 0;
     for (int base = 0; base < ntiles; base += kScanThreads * kScanPer) {
         const int lo = base + t * kScanPer;
@@ -184,6 +286,7 @@ __global__ void __launch_bounds__(kScanThreads) bin_scan_kernel(Binned b, int nt
         for (int k = 0; k < kScanPer; ++k) {
             v[k] = lo + k < ntiles ? b.cursor[lo + k] : 0u;
             s += v[k];
+            if (v[k] > b.cap) too_big = 1u;   // benign race: every writer stores 1
         }
         uint32_t inc = s;   // inclusive scan within the wave
 #pragma unroll
@@ -215,70 +318,21 @@ __global__ void __launch_bounds__(kScanThreads) bin_scan_kernel(Binned b, int nt
         carry += wsum[kScanThreads / 64 - 1];
         __syncthreads();   // wsum is rewritten by the next chunk
     }
-    if (t == 0) b.tile_start[ntiles] = carry;
+    if (t == 0) {
+        b.tile_start[ntiles] = carry;
+        if (!too_big) atomicOr(b.status, kStatusFits);
+    }
 }
 
+// Compact layout, second pass: bin every point again into the scanned layout.
 __global__ void __launch_bounds__(kGeoThreads) bin_scatter_kernel(GeoParams g, Binned b, int64_t n,
                                                                   const double *__restrict__ x,
                                                                   const double *__restrict__ y,
                                                                   const double *__restrict__ d) {
-    double xv[kScatterPoints], yv[kScatterPoints], dv[kScatterPoints];
-#pragma unroll
-    for (int k = 0; k < kScatterPoints; ++k) {
-        const int64_t j = geo_index<kScatterPoints>(k);
-        const bool in = j < n;
-        xv[k] = in ? x[j] : 0.0;
-        yv[k] = in ? y[j] : 0.0;
-        dv[k] = in ? d[j] : 0.0;
-    }
-    PointTiles p[kScatterPoints];
-    WaveGroup grp[kScatterPoints][4];
-    uint32_t base[kScatterPoints][4];
-#pragma unroll
-    for (int k = 0; k < kScatterPoints; ++k) {
-        p[k].n = 0;
-        if (geo_index<kScatterPoints>(k) < n) p[k] = point_tiles(g, xv[k], yv[k], dv[k]);
-        // group the replica keys, then let the leaders reserve their groups'
-        // slots; the atomics of all batches and replicas are in flight at once
-#pragma unroll
-        for (int r = 0; r < 4; ++r) grp[k][r] = wave_group(r < p[k].n ? p[k].key[r] : 0, r < p[k].n);
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            base[k][r] = (r < p[k].n && grp[k][r].leader == __lane_id())
-                             ? atomicAdd(&b.cursor[p[k].key[r]], grp[k][r].size) : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < kScatterPoints; ++k) {
-        float2 ph = make_float2(0.f, 0.f);
-        if (p[k].n > 0) {
-            // phi / (2 pi) = k (|x|^2 / (2 r0) [- d]) / (2 pi) = |x|^2 s / 2 [- d / lambda]
-            double rev = 0.5 * p[k].s * (xv[k] * xv[k] + yv[k] * yv[k]);
-            if (!g.plane) rev -= dv[k] * g.inv_lambda;
-            // off-axis window: -k (x x0 + y y0) / r0 = -2 pi (x x0 + y y0) s
-            rev -= (xv[k] * g.x0 + yv[k] * g.y0) * p[k].s;
-            const float t = (float)(rev - rint(rev));   // exact in FP64, then one rounding
-            float sn, cs;
-            sincospif(2.f * t, &sn, &cs);
-            ph = make_float2(cs, sn);
-        }
-        const uint32_t cell = (uint32_t)p[k].l0x | ((uint32_t)p[k].l0y << 16);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const bool act = r < p[k].n;
-            const int key = act ? p[k].key[r] : 0;
-            const uint32_t slot = __shfl(base[k][r], grp[k][r].leader) + grp[k][r].rank;
-            if (act) {
-                if (slot < b.tile_start[key + 1]) {
-                    b.cell[slot] = cell;
-                    b.frac[slot] = make_float2(p[k].fx, p[k].fy);
-                    b.phase[slot] = ph;
-                    b.perm[slot] = (uint32_t)geo_index<kScatterPoints>(k);
-                } else {
-                    atomicOr(b.status, 2u);
-                }
-            }
-        }
-    }
+    if (!(b.status[0] & kStatusCompact)) return;   // every slab held its tile
+    const int64_t per = (int64_t)kGeoThreads * kBinPoints;
+    const int64_t nblk = (n + per - 1) / per;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) bin_block<false>(g, b, n, blk, x, y, d);
 }
 
 }  // namespace
@@ -286,6 +340,14 @@ __global__ void __launch_bounds__(kGeoThreads) bin_scatter_kernel(GeoParams g, B
 hipError_t launch_bin_reset(const Binned &b, int ntiles, hipStream_t s) {
     const int blocks = (ntiles + 255) / 256;
     hipLaunchKernelGGL(bin_reset_kernel, dim3(blocks), dim3(256), 0, s, b, ntiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_fill(const GeoParams &g, const Binned &b, int64_t n, const double *x,
+                           const double *y, const double *d, hipStream_t s) {
+    const int64_t per = (int64_t)kGeoThreads * kBinPoints;
+    const int64_t blocks = (n + per - 1) / per;
+    hipLaunchKernelGGL(bin_fill_kernel, dim3((unsigned)blocks), dim3(kGeoThreads), 0, s, g, b, n, x, y, d);
     return hipGetLastError();
 }
 
@@ -304,9 +366,10 @@ hipError_t launch_bin_scan(const Binned &b, int ntiles, hipStream_t s) {
 
 hipError_t launch_bin_scatter(const GeoParams &g, const Binned &b, int64_t n, const double *x,
                               const double *y, const double *d, hipStream_t s) {
-    const int64_t per = (int64_t)kGeoThreads * kScatterPoints;
+    const int64_t per = (int64_t)kGeoThreads * kBinPoints;
     const int64_t blocks = (n + per - 1) / per;
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3((unsigned)blocks), dim3(kGeoThreads), 0, s, g, b, n, x, y, d);
+    const int grid = (int)(blocks < kFallbackBlocks ? blocks : kFallbackBlocks);
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3(grid), dim3(kGeoThreads), 0, s, g, b, n, x, y, d);
     return hipGetLastError();
 }
 

@@ -253,7 +253,8 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
         for (int i = tid; i < swx * swy; i += nt) starts[i] = 0;
         if (tid < 16) rcount[tid] = 0u;
     }
-    const uint32_t s0 = b.tile_start[t], s1 = b.tile_start[t + 1];
+    uint32_t s0, s1;
+    tile_slots(b, t, s0, s1);
     const bool reload = s1 - s0 > per_batch;
     const bool deal = s1 - s0 > kDealRecords;
     Batch r;
@@ -475,7 +476,8 @@ __global__ void __launch_bounds__(kInterpThreads) interp_kernel(SpreadParams p, 
         reg[yy * RP + xx] = fine[(((size_t)(gx >> p.log_panel) * p.nfy + gy) << p.log_panel) + (gx & (C - 1))];
     }
     __syncthreads();
-    const uint32_t s0 = b.tile_start[t], s1 = b.tile_start[t + 1];
+    uint32_t s0, s1;
+    tile_slots(b, t, s0, s1);
     for (uint32_t s = s0 + tid; s < s1; s += nt) {
         const uint32_t cell = b.cell[s];
         const int px = (int)(cell & 0xffffu) - x0, py = (int)(cell >> 16) - y0;

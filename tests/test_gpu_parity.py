@@ -99,6 +99,64 @@ def test_hot_tile_all_points_in_one_cell_block():
     assert rel_l2(got, _full_grid(w)) <= 1e-5
 
 
+def test_binning_layout_switches_with_crowding():
+    """One plan re-binned between an even geometry (frequencies wrapping over the
+    whole fine grid: every tile fits its slab of 4 n / ntiles slots) and one with
+    40% of the points in one spot (four tiles overflow their slabs: the compact
+    layout packs the bins).  The status word names the layout; after a crowded
+    binning the plan counts first until a scan finds that the slabs would fit
+    again.  Every binning reproduces a fresh plan bit for bit and the oracle."""
+    torch = torch_gpu()
+    import dataclasses
+    import paper_1203_3583_amd as asf
+
+    even = _custom(128, 128, 8e-6, 2e-6, 128, 128, 80e-6, 80e-6, seed=6)
+    rng = np.random.default_rng(12)
+    x, y = even.x.copy(), even.y.copy()
+    crowd = rng.choice(even.n, size=(2 * even.n) // 5, replace=False)
+    x[crowd] = rng.uniform(-2e-6, 2e-6, crowd.size)
+    y[crowd] = rng.uniform(-2e-6, 2e-6, crowd.size)
+    crowded = dataclasses.replace(even, name="crowded", x=x, y=y)
+
+    xe, ye, de, u = to_dev(torch, even)
+    xc, yc, dc, _ = to_dev(torch, crowded)
+    plan = asf.Plan(xe, ye, de, even.lam, even.z0, even.p2x, even.p2y, even.mx, even.my)
+    info = plan.info()
+    status = plan.workspace_view(info["off_status"], 1, torch.int32)
+    assert crowd.size > info["slot_cap"] // info["ntiles"]   # crowded tiles cannot fit a slab
+
+    def run():
+        plan.status()
+        return int(status.item()), plan.forward(u).cpu().numpy()
+
+    seq = [run()]                                    # slabs
+    for geo in ((xc, yc, dc), (xc, yc, dc), (xe, ye, de), (xe, ye, de)):
+        plan.setpts(*geo)
+        seq.append(run())
+    # slab pass overflowed -> compact; counted first -> compact; counted first and
+    # every tile would fit -> compact + fits; slabs again
+    assert [st for st, _ in seq] == [0, 4, 4, 12, 0]
+    f_even, f_crowd = seq[0][1], seq[1][1]
+    assert np.array_equal(seq[2][1], f_crowd)
+    assert np.array_equal(seq[3][1], f_even) and np.array_equal(seq[4][1], f_even)
+    # the adjoint in the compact layout: <A u, g> = <u, A^H g>
+    plan.setpts(xc, yc, dc)
+    g = torch.from_numpy(synth.random_field(rng, even.mx, even.my)).cuda()
+    au = plan.forward(u)
+    ahg = plan.adjoint(g)
+    lhs = torch.vdot(g.reshape(-1).to(torch.complex128), au.reshape(-1).to(torch.complex128)).item()
+    rhs = torch.vdot(ahg.to(torch.complex128), u.to(torch.complex128)).item()
+    plan.close()
+    fresh_even, _ = gpu_forward(even)
+    fresh_crowd, _ = gpu_forward(crowded)
+    assert np.array_equal(f_even.astype(np.complex128), fresh_even)
+    assert np.array_equal(f_crowd.astype(np.complex128), fresh_crowd)
+    ix, iy = synth.sample_pixels(even.mx, even.my, 256, seed=3)
+    assert rel_l2(f_crowd[iy, ix], _oracle(crowded, ix, iy)) <= 1e-5
+    assert rel_l2(f_even[iy, ix], _oracle(even, ix, iy)) <= 1e-5
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
 @pytest.mark.parametrize("fft", ["fp32", "split_fp16"])
 def test_cap_2048_full_size(fft):
     """The 2048^2 spherical cap at full size on crops and random pixels."""
