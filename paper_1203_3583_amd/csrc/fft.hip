@@ -366,11 +366,17 @@ __global__ void __launch_bounds__(NT) fft_pass1_kernel(const float2 *__restrict_
     const int pc = blockIdx.x;
     const float2 *src = fine + (size_t)pc * S::L * BATCH;
     float big = 0.f;
-    for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
-        const float2 v = src[t];
+    // every load in flight before the first LDS write
+    constexpr int PER = S::L * BATCH / NT;
+    float2 v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) v[k] = src[threadIdx.x + k * NT];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int t = threadIdx.x + k * NT;
         const int ly = t / BATCH, c = t % BATCH;
-        lds[c * S::STRIDE + lds_pos<S::PS>(ly)] = v;
-        if constexpr (SPLIT) big = fmaxf(big, fmaxf(fabsf(v.x), fabsf(v.y)));
+        lds[c * S::STRIDE + lds_pos<S::PS>(ly)] = v[k];
+        if constexpr (SPLIT) big = fmaxf(big, fmaxf(fabsf(v[k].x), fabsf(v[k].y)));
     }
     // split products: scale the workgroup's data by a power of two into FP16 range
     // (applied as the first stage reads it); the block maximum's barrier also
@@ -415,11 +421,22 @@ __global__ void __launch_bounds__(NT) fft_pass2_kernel(const float2 *__restrict_
     const int row0 = g * BATCH;
     const int cmask = (1 << log_panel) - 1;
     float big = 0.f;
-    for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
+    // every load in flight before the first LDS write (a row is gathered from
+    // the panels, one line per element: serial round trips would dominate)
+    constexpr int PER = S::L * BATCH / NT;
+    float2 v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int t = threadIdx.x + k * NT;
         const int c = t >> LOGL, lx = t & (S::L - 1);
-        const float2 v = mid[((((size_t)(lx >> log_panel)) * my + row0 + c) << log_panel) + (lx & cmask)];
-        lds[c * S::STRIDE + lds_pos<S::PS>(lx)] = v;
-        if constexpr (SPLIT) big = fmaxf(big, fmaxf(fabsf(v.x), fabsf(v.y)));
+        v[k] = mid[((((size_t)(lx >> log_panel)) * my + row0 + c) << log_panel) + (lx & cmask)];
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int t = threadIdx.x + k * NT;
+        const int c = t >> LOGL, lx = t & (S::L - 1);
+        lds[c * S::STRIDE + lds_pos<S::PS>(lx)] = v[k];
+        if constexpr (SPLIT) big = fmaxf(big, fmaxf(fabsf(v[k].x), fabsf(v[k].y)));
     }
     // split products: scale the workgroup's data by a power of two into FP16 range
     // (applied as the first stage reads it); the block maximum's barrier also
@@ -471,16 +488,25 @@ __global__ void __launch_bounds__(NT) fft_adj_rows_kernel(const float2 *__restri
     const int row0 = blockIdx.x * BATCH;
     const int half = mx >> 1;
     float big = 0.f;
-    for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
+    // every load in flight before the first LDS write
+    constexpr int PER = S::L * BATCH / NT;
+    float2 gv[PER], dv[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int t = threadIdx.x + k * NT;
         const int c = t >> LOGL, l = t & (S::L - 1);
         const int m = l < S::L / 2 ? l : l - S::L;
         const int ix = m + half;
-        float2 v = make_float2(0.f, 0.f);
-        if (ix >= 0 && ix < mx) {
-            // conj(g conj(Dx Dy)) = conj(g) Dx Dy
-            const float2 g = g2[(size_t)(row0 + c) * mx + ix];
-            v = cmul(cmul(make_float2(g.x, -g.y), dx[ix]), dy[row0 + c]);
-        }
+        const bool in = ix >= 0 && ix < mx;
+        gv[k] = in ? g2[(size_t)(row0 + c) * mx + ix] : make_float2(0.f, 0.f);
+        dv[k] = in ? dx[ix] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int t = threadIdx.x + k * NT;
+        const int c = t >> LOGL, l = t & (S::L - 1);
+        // conj(g conj(Dx Dy)) = conj(g) Dx Dy (zero outside the kept modes)
+        const float2 v = cmul(cmul(make_float2(gv[k].x, -gv[k].y), dv[k]), dy[row0 + c]);
         lds[c * S::STRIDE + lds_pos<S::PS>(l)] = v;
         if constexpr (SPLIT) big = fmaxf(big, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
@@ -522,17 +548,24 @@ __global__ void __launch_bounds__(NT) fft_adj_cols_kernel(const float2 *__restri
     }
     const int half = my >> 1;
     float big = 0.f;
-    for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
+    // every load in flight before the first LDS write
+    constexpr int PER = S::L * BATCH / NT;
+    float2 v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int t = threadIdx.x + k * NT;
         const int l = t / BATCH, c = t % BATCH;
         const int m = l < S::L / 2 ? l : l - S::L;
         const int ky = m + half;
-        float2 v = make_float2(0.f, 0.f);
-        if (ky >= 0 && ky < my) {
-            const float2 g = mid[(size_t)ky * nfx + pc * BATCH + c];
-            v = make_float2(g.x, -g.y);
-        }
-        lds[c * S::STRIDE + lds_pos<S::PS>(l)] = v;
-        if constexpr (SPLIT) big = fmaxf(big, fmaxf(fabsf(v.x), fabsf(v.y)));
+        v[k] = (ky >= 0 && ky < my) ? mid[(size_t)ky * nfx + pc * BATCH + c] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int t = threadIdx.x + k * NT;
+        const int l = t / BATCH, c = t % BATCH;
+        const float2 w = make_float2(v[k].x, -v[k].y);
+        lds[c * S::STRIDE + lds_pos<S::PS>(l)] = w;
+        if constexpr (SPLIT) big = fmaxf(big, fmaxf(fabsf(w.x), fabsf(w.y)));
     }
     // split products: scale the workgroup's data by a power of two into FP16 range
     // (applied as the first stage reads it); the block maximum's barrier also
@@ -567,7 +600,10 @@ hipError_t allow_lds(const void *kernel, size_t lds, size_t &enabled) {
 template <int LOGL, int BATCH>
 constexpr int threads_for() {
     constexpr int blocks = BATCH * (1 << LOGL) / 256;
-    return blocks <= 8 ? 64 * blocks : 512;
+    constexpr int nt = blocks <= 8 ? 64 * blocks : 512;
+    // the kernels' loaders give every thread exactly L * BATCH / NT elements
+    static_assert((BATCH << LOGL) % nt == 0, "whole elements per thread");
+    return nt;
 }
 
 template <int LOGL, int BATCH, bool SPLIT>
