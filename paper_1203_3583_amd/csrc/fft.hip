@@ -448,19 +448,28 @@ __global__ void __launch_bounds__(NT) fft_pass2_kernel(const float2 *__restrict_
         unscale = ldexpf(1.f, e);
     }
     transform_all<LOGL, BATCH, NT, SPLIT>(lds, tw, w16, inv);
-    const int half = mx >> 1;
-    for (int t = threadIdx.x; t < mx * BATCH; t += NT) {
-        const int c = t / mx, ix = t - c * mx;
-        const int l = (ix - half) & (S::L - 1);
+    // mx = L / 2 (the fine grid is twice the destination), so the epilogue's trip
+    // count is a constant too: its table (and accumulated) loads go out together
+    (void)mx;
+    constexpr int MX = S::L / 2, HALF = MX / 2;
+    constexpr int OUT = MX * BATCH / NT;
+    float2 dxv[OUT], prev[OUT];
+#pragma unroll
+    for (int k = 0; k < OUT; ++k) {
+        const int t = threadIdx.x + k * NT;
+        const int c = t / MX, ix = t - c * MX;
+        dxv[k] = dx[ix];
+        prev[k] = accumulate ? u2[(size_t)(row0 + c) * MX + ix] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < OUT; ++k) {
+        const int t = threadIdx.x + k * NT;
+        const int c = t / MX, ix = t - c * MX;
+        const int l = (ix - HALF) & (S::L - 1);
         float2 val = lds[c * S::STRIDE + lds_pos<S::PS>(l)];
         val = make_float2(val.x * unscale, val.y * unscale);
-        float2 r = cmul(cmul(val, dx[ix]), dy[row0 + c]);
-        float2 *dst = u2 + (size_t)(row0 + c) * mx + ix;
-        if (accumulate) {
-            const float2 old = *dst;
-            r = make_float2(old.x + r.x, old.y + r.y);
-        }
-        *dst = r;
+        const float2 r = cmul(cmul(val, dxv[k]), dy[row0 + c]);
+        u2[(size_t)(row0 + c) * MX + ix] = make_float2(prev[k].x + r.x, prev[k].y + r.y);
     }
 }
 
