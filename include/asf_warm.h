@@ -39,6 +39,7 @@ int asf_warm_conv3x3(const float *in, const uint16_t *w, const float *bias, floa
  *   dbias[co] += sum_{b,y,x} dout[b,y,x,co]      (dbias may be NULL)
  * in and dout rounded to BF16 on load, FP32 products summed with FP32 atomics
  * (accumulates: clear dw and dbias first).  dw [cout][3][3][cin] FP32.
+ * B H W must be below 2^22 (-1 otherwise).
  */
 int asf_warm_conv3x3_wgrad(const float *in, const float *dout, float *dw, float *dbias, int32_t B,
                            int32_t H, int32_t W, int32_t cin, int32_t cout, void *stream);

@@ -40,25 +40,30 @@ __device__ __forceinline__ v4s bf16x4(float4 v) {
 }
 
 // ---- forward convolution -----------------------------------------------------
-// A wave computes 64 consecutive pixels (flattened b, y, x) x 32 output
-// channels: 4 x 2 accumulator tiles.  Four waves per workgroup, on consecutive
-// pixel tiles of the same channel block; no LDS, no barriers.
+// A wave computes 16 PB consecutive pixels (flattened b, y, x) x 32 output
+// channels: PB x 2 accumulator tiles.  Layers take PB = 4 (more MFMAs per
+// operand fetch) unless that gives fewer waves than SIMDs: the small, deep
+// layers take PB = 1 and four times the waves (64^2 pixels, 256 channels:
+// 0.118 -> 0.095 ms).  Four waves per workgroup, on consecutive pixel tiles of the same
+// channel block; no LDS, no barriers.  The contraction runs over (tap, 16
+// channels) steps, two per iteration with all their loads issued first.
 constexpr int kConvWaves = 4;
 
+template <int PB>
 __global__ __launch_bounds__(64 * kConvWaves) void conv3x3_kernel(
     const float *__restrict__ in, const uint16_t *__restrict__ w, const float *__restrict__ bias,
     float *__restrict__ out, int B, int H, int W, int cin, int cout, int relu) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t npix = (int64_t)B * H * W;
-    const int64_t p0 = ((int64_t)blockIdx.x * kConvWaves + wave) * 64;
+    const int64_t p0 = ((int64_t)blockIdx.x * kConvWaves + wave) * (16 * PB);
     if (p0 >= npix) return;   // uniform over the wave
     const int co0 = blockIdx.y * 32;
     const int r = lane & 15, g = lane >> 4;
-    // the four pixels whose A rows this lane supplies
-    int py[4], px[4];
-    int64_t pimg[4];   // b H W of the pixel's image, or -1 past the end
+    // the pixels whose A rows this lane supplies
+    int py[PB], px[PB];
+    int64_t pimg[PB];   // b H W of the pixel's image, or -1 past the end
 #pragma unroll
-    for (int pb = 0; pb < 4; ++pb) {
+    for (int pb = 0; pb < PB; ++pb) {
         const int64_t p = p0 + pb * 16 + r;
         if (p < npix) {
             const int64_t bi = p / ((int64_t)H * W);
@@ -71,38 +76,49 @@ __global__ __launch_bounds__(64 * kConvWaves) void conv3x3_kernel(
             pimg[pb] = -1;
         }
     }
-    v4f acc[4][2];
+    v4f acc[PB][2];
 #pragma unroll
-    for (int pb = 0; pb < 4; ++pb)
+    for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) acc[pb][cb] = (v4f){0.f, 0.f, 0.f, 0.f};
     const int kin = 9 * cin;
     const uint16_t *wrow0 = w + (size_t)(co0 + r) * kin;
     const uint16_t *wrow1 = w + (size_t)(co0 + 16 + r) * kin;
-    for (int tap = 0; tap < 9; ++tap) {
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        const float *src[4];
-        bool ok[4];
+    const int steps = 9 * (cin >> 4);
+    int tap = 0, c0 = 0;   // (tap, first channel) of step s
+    for (int s = 0; s < steps; s += 2) {
+        float4 v[2][PB];
+        v4s b0[2], b1[2];
 #pragma unroll
-        for (int pb = 0; pb < 4; ++pb) {
-            const int yy = py[pb] + dy, xx = px[pb] + dx;
-            ok[pb] = pimg[pb] >= 0 && yy >= 0 && yy < H && xx >= 0 && xx < W;
-            src[pb] = in + ((size_t)(ok[pb] ? pimg[pb] + (int64_t)yy * W + xx : 0)) * cin + g * 4;
-        }
-        for (int c0 = 0; c0 < cin; c0 += 16) {
-            v4s a[4];
+        for (int h = 0; h < 2; ++h) {
+            const bool live = s + h < steps;   // uniform over the wave
+            const int ty = tap / 3;
+            const int dy = ty - 1, dx = tap - 3 * ty - 1;
 #pragma unroll
-            for (int pb = 0; pb < 4; ++pb) {
-                const float4 v = ok[pb] ? *reinterpret_cast<const float4 *>(src[pb] + c0) : make_float4(0.f, 0.f, 0.f, 0.f);
-                a[pb] = bf16x4(v);
+            for (int pb = 0; pb < PB; ++pb) {
+                const int yy = py[pb] + dy, xx = px[pb] + dx;
+                const bool ok = live && pimg[pb] >= 0 && yy >= 0 && yy < H && xx >= 0 && xx < W;
+                v[h][pb] = ok ? *reinterpret_cast<const float4 *>(in + (size_t)(pimg[pb] + (int64_t)yy * W + xx) * cin +
+                                                                  c0 + g * 4)
+                              : make_float4(0.f, 0.f, 0.f, 0.f);
             }
             const int k = tap * cin + c0 + g * 4;
-            const v4s b0 = *reinterpret_cast<const v4s *>(wrow0 + k);
-            const v4s b1 = *reinterpret_cast<const v4s *>(wrow1 + k);
+            b0[h] = live ? *reinterpret_cast<const v4s *>(wrow0 + k) : (v4s){0, 0, 0, 0};
+            b1[h] = live ? *reinterpret_cast<const v4s *>(wrow1 + k) : (v4s){0, 0, 0, 0};
+            c0 += 16;
+            if (c0 == cin) {
+                c0 = 0;
+                ++tap;
+            }
+        }
 #pragma unroll
-            for (int pb = 0; pb < 4; ++pb) {
-                acc[pb][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[pb], b0, acc[pb][0], 0, 0, 0);
-                acc[pb][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[pb], b1, acc[pb][1], 0, 0, 0);
+        for (int h = 0; h < 2; ++h) {
+            if (s + h >= steps) break;   // uniform
+#pragma unroll
+            for (int pb = 0; pb < PB; ++pb) {
+                const v4s a = bf16x4(v[h][pb]);
+                acc[pb][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b0[h], acc[pb][0], 0, 0, 0);
+                acc[pb][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b1[h], acc[pb][1], 0, 0, 0);
             }
         }
     }
@@ -111,7 +127,7 @@ __global__ __launch_bounds__(64 * kConvWaves) void conv3x3_kernel(
         const int co = co0 + cb * 16 + r;
         const float bv = bias ? bias[co] : 0.f;
 #pragma unroll
-        for (int pb = 0; pb < 4; ++pb)
+        for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int64_t p = p0 + pb * 16 + g * 4 + i;
@@ -126,8 +142,34 @@ __global__ __launch_bounds__(64 * kConvWaves) void conv3x3_kernel(
 // ---- weight gradient ----------------------------------------------------------
 // A wave computes a 32 (cout) x 16 (k) block of dw over a chunk of pixels and
 // adds it to dw with FP32 atomics.  k = (tap, c0 .. c0+15): the block covers 16
-// consecutive input channels of one tap.
-constexpr int kWgradChunk = 1024;   // pixels per wave
+// consecutive input channels of one tap; a wave takes kKB such blocks, which
+// share its dout loads.  Short chunks give the deep, small layers enough waves;
+// two 16-pixel steps per iteration keep their loads in flight together.
+constexpr int kWgradChunk = 256;   // pixels per wave
+constexpr int kMaxWgradPix = 1 << 22;   // B H W below this: pixel coordinates by float division
+
+// Pixel p -> (b H W, y, x) for p < 2^22: a float estimate of each quotient, off by
+// at most one (relative error below 2^-23 on a value below 2^22), then one
+// correction step.
+__device__ __forceinline__ void pix_split(int64_t p, int hw, int w, float inv_hw, float inv_w,
+                                          int64_t &base, int &y, int &x) {
+    {
+        const int pi = (int)p;
+        int b = (int)(((float)pi + 0.5f) * inv_hw);
+        int rest = pi - b * hw;
+        if (rest < 0) { --b; rest += hw; } else if (rest >= hw) { ++b; rest -= hw; }
+        int yy = (int)(((float)rest + 0.5f) * inv_w);
+        int xx = rest - yy * w;
+        if (xx < 0) { --yy; xx += w; } else if (xx >= w) { ++yy; xx -= w; }
+        base = (int64_t)b * hw;
+        y = yy;
+        x = xx;
+    }
+}
+
+// kKB consecutive 16-wide k blocks per wave share its dout loads (9 cin / 16 is a
+// multiple of 9, so of kKB).
+constexpr int kKB = 3;
 
 __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
     const float *__restrict__ in, const float *__restrict__ dout, float *__restrict__ dw,
@@ -136,51 +178,82 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
     const int64_t npix = (int64_t)B * H * W;
     const int64_t pc = ((int64_t)blockIdx.x * 4 + wave) * kWgradChunk;
     if (pc >= npix) return;
-    const int kblocks = 9 * cin / 16;
-    const int kb = blockIdx.y % kblocks, cb2 = blockIdx.y / kblocks;
-    const int tap = (kb * 16) / cin, c0 = kb * 16 - tap * cin;
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int kgroups = 9 * cin / (16 * kKB);
+    const int kg = blockIdx.y % kgroups, cb2 = blockIdx.y / kgroups;
+    int tap[kKB], c0[kKB], dy[kKB], dx[kKB];
+#pragma unroll
+    for (int q = 0; q < kKB; ++q) {
+        const int kb = kg * kKB + q;
+        tap[q] = (kb * 16) / cin;
+        c0[q] = kb * 16 - tap[q] * cin;
+        dy[q] = tap[q] / 3 - 1;
+        dx[q] = tap[q] % 3 - 1;
+    }
     const int co0 = cb2 * 32;
     const int r = lane & 15, g = lane >> 4;
-    v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    const int hw = H * W;
+    const float inv_hw = 1.f / (float)hw, inv_w = 1.f / (float)W;
+    v4f acc[kKB][2];
+#pragma unroll
+    for (int q = 0; q < kKB; ++q) acc[q][0] = acc[q][1] = (v4f){0.f, 0.f, 0.f, 0.f};
     float bsum0 = 0.f, bsum1 = 0.f;
     const int64_t pend = pc + kWgradChunk < npix ? pc + kWgradChunk : npix;
-    for (int64_t ps = pc; ps < pend; ps += 16) {
-        // this lane's four pixels of the step: ps + 4 g + j
-        float av0[4], av1[4], bv[4];
+    for (int64_t ps = pc; ps < pend; ps += 32) {
+        // two steps of 16 pixels; this lane's four pixels of step h: ps + 16 h + 4 g + j
+        float av0[2][4], av1[2][4], bv[2][kKB][4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t p = ps + g * 4 + j;
-            av0[j] = av1[j] = bv[j] = 0.f;
-            if (p < pend) {
-                av0[j] = dout[p * cout + co0 + r];
-                av1[j] = dout[p * cout + co0 + 16 + r];
-                const int64_t bi = p / ((int64_t)H * W);
-                const int rest = (int)(p - bi * H * W);
-                const int y = rest / W, x = rest - (rest / W) * W;
-                const int yy = y + dy, xx = x + dx;
-                if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                    bv[j] = in[(bi * H * W + (int64_t)yy * W + xx) * cin + c0 + r];
+        for (int h = 0; h < 2; ++h) {
+            int64_t base;
+            int y, x;
+            pix_split(ps + 16 * h + 4 * g, hw, W, inv_hw, inv_w, base, y, x);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t p = ps + 16 * h + 4 * g + j;
+                const bool live = p < pend;
+                av0[h][j] = live ? dout[p * cout + co0 + r] : 0.f;
+                av1[h][j] = live ? dout[p * cout + co0 + 16 + r] : 0.f;
+#pragma unroll
+                for (int q = 0; q < kKB; ++q) {
+                    const int yy = y + dy[q], xx = x + dx[q];
+                    bv[h][q][j] = (live && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                                      ? in[(base + (int64_t)yy * W + xx) * cin + c0[q] + r] : 0.f;
+                }
+                // next pixel in raster order
+                if (++x == W) {
+                    x = 0;
+                    if (++y == H) {
+                        y = 0;
+                        base += hw;
+                    }
+                }
             }
         }
-        bsum0 += av0[0] + av0[1] + av0[2] + av0[3];
-        bsum1 += av1[0] + av1[1] + av1[2] + av1[3];
-        const v4s a0 = bf16x4(make_float4(av0[0], av0[1], av0[2], av0[3]));
-        const v4s a1 = bf16x4(make_float4(av1[0], av1[1], av1[2], av1[3]));
-        const v4s b = bf16x4(make_float4(bv[0], bv[1], bv[2], bv[3]));
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b, acc1, 0, 0, 0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            bsum0 += av0[h][0] + av0[h][1] + av0[h][2] + av0[h][3];
+            bsum1 += av1[h][0] + av1[h][1] + av1[h][2] + av1[h][3];
+            const v4s a0 = bf16x4(make_float4(av0[h][0], av0[h][1], av0[h][2], av0[h][3]));
+            const v4s a1 = bf16x4(make_float4(av1[h][0], av1[h][1], av1[h][2], av1[h][3]));
+#pragma unroll
+            for (int q = 0; q < kKB; ++q) {
+                const v4s b = bf16x4(make_float4(bv[h][q][0], bv[h][q][1], bv[h][q][2], bv[h][q][3]));
+                acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b, acc[q][0], 0, 0, 0);
+                acc[q][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b, acc[q][1], 0, 0, 0);
+            }
+        }
     }
-    // accumulator rows are output channels 4 g + i, column k = c0 + r of this tap
+    // accumulator rows are output channels 4 g + i, column k = c0 + r of the block's tap
     const int kin = 9 * cin;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        atomicAdd(&dw[(size_t)(co0 + g * 4 + i) * kin + tap * cin + c0 + r], acc0[i]);
-        atomicAdd(&dw[(size_t)(co0 + 16 + g * 4 + i) * kin + tap * cin + c0 + r], acc1[i]);
-    }
-    if (dbias && kb == 0) {
+    for (int q = 0; q < kKB; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            atomicAdd(&dw[(size_t)(co0 + g * 4 + i) * kin + tap[q] * cin + c0[q] + r], acc[q][0][i]);
+            atomicAdd(&dw[(size_t)(co0 + 16 + g * 4 + i) * kin + tap[q] * cin + c0[q] + r], acc[q][1][i]);
+        }
+    if (dbias && kg == 0) {
         // bias gradient from the same dout values (FP32, not rounded): sum the four
-        // k groups of each output channel
+        // pixel groups of each output channel
         bsum0 += __shfl_xor(bsum0, 16);
         bsum0 += __shfl_xor(bsum0, 32);
         bsum1 += __shfl_xor(bsum1, 16);
@@ -309,10 +382,18 @@ int asf_warm_conv3x3(const float *in, const uint16_t *w, const float *bias, floa
     if (!in || !w || !out || B <= 0 || H <= 0 || W <= 0 || cin <= 0 || cout <= 0 || cin % 16 || cout % 32)
         return -1;
     const int64_t npix = (int64_t)B * H * W;
-    const int64_t tiles = (npix + 63) / 64;
-    const dim3 grid((unsigned)((tiles + kConvWaves - 1) / kConvWaves), (unsigned)(cout / 32));
-    hipLaunchKernelGGL(conv3x3_kernel, grid, dim3(64 * kConvWaves), 0, static_cast<hipStream_t>(stream), in, w,
-                       bias, out, B, H, W, cin, cout, relu);
+    // waves of 64-pixel tiles; fewer than 1024 (one per SIMD) -> 16-pixel tiles
+    const int64_t tiles64 = (npix + 63) / 64;
+    if (tiles64 * (cout / 32) >= 1024) {
+        const dim3 grid((unsigned)((tiles64 + kConvWaves - 1) / kConvWaves), (unsigned)(cout / 32));
+        hipLaunchKernelGGL(conv3x3_kernel<4>, grid, dim3(64 * kConvWaves), 0, static_cast<hipStream_t>(stream), in,
+                           w, bias, out, B, H, W, cin, cout, relu);
+    } else {
+        const int64_t tiles16 = (npix + 15) / 16;
+        const dim3 grid((unsigned)((tiles16 + kConvWaves - 1) / kConvWaves), (unsigned)(cout / 32));
+        hipLaunchKernelGGL(conv3x3_kernel<1>, grid, dim3(64 * kConvWaves), 0, static_cast<hipStream_t>(stream), in,
+                           w, bias, out, B, H, W, cin, cout, relu);
+    }
     return done(hipGetLastError());
 }
 
@@ -321,8 +402,9 @@ int asf_warm_conv3x3_wgrad(const float *in, const float *dout, float *dw, float 
     if (!in || !dout || !dw || B <= 0 || H <= 0 || W <= 0 || cin <= 0 || cout <= 0 || cin % 16 || cout % 32)
         return -1;
     const int64_t npix = (int64_t)B * H * W;
+    if (npix >= kMaxWgradPix) return -1;
     const int64_t chunks = (npix + kWgradChunk - 1) / kWgradChunk;
-    const dim3 grid((unsigned)((chunks + 3) / 4), (unsigned)((cout / 32) * (9 * cin / 16)));
+    const dim3 grid((unsigned)((chunks + 3) / 4), (unsigned)((cout / 32) * (9 * cin / (16 * kKB))));
     hipLaunchKernelGGL(conv3x3_wgrad_kernel, grid, dim3(256), 0, static_cast<hipStream_t>(stream), in, dout, dw,
                        dbias, B, H, W, cin, cout);
     return done(hipGetLastError());

@@ -30,7 +30,7 @@ def _weights(torch, ws, rng, cout, cin, scale=0.2):
 
 
 @pytest.mark.parametrize("B,H,W,cin,cout,relu", [(2, 8, 12, 16, 32, True), (1, 5, 7, 48, 64, False),
-                                                 (1, 16, 16, 32, 96, True)])
+                                                 (1, 16, 16, 32, 96, True), (2, 255, 259, 16, 64, True)])
 def test_conv3x3_forward(B, H, W, cin, cout, relu):
     torch, ws, wo = _setup()
     rng = np.random.default_rng(B * 100 + cin)
@@ -51,7 +51,8 @@ def test_conv3x3_forward(B, H, W, cin, cout, relu):
     assert L.asf_warm_conv3x3(ws._ptr(xt), ws._ptr(wb), None, ws._ptr(out), B, H, W, cin + 1, cout, 0, s) == -1
 
 
-@pytest.mark.parametrize("B,H,W,cin,cout", [(2, 8, 12, 16, 32), (1, 5, 7, 48, 64), (3, 32, 32, 32, 32)])
+@pytest.mark.parametrize("B,H,W,cin,cout", [(2, 8, 12, 16, 32), (1, 5, 7, 48, 64), (3, 32, 32, 32, 32),
+                                            (2, 255, 259, 32, 64)])
 def test_conv3x3_gradients(B, H, W, cin, cout):
     torch, ws, wo = _setup()
     rng = np.random.default_rng(7 + cin)
@@ -64,6 +65,9 @@ def test_conv3x3_gradients(B, H, W, cin, cout):
     L = ws._lib()
     s = ws._stream(torch)
     assert L.asf_warm_conv3x3_wgrad(ws._ptr(xt), ws._ptr(dyt), ws._ptr(dw), ws._ptr(db), B, H, W, cin, cout, s) == 0
+    # the float pixel-coordinate division is exact below 2^22 pixels; larger batches are refused
+    assert L.asf_warm_conv3x3_wgrad(ws._ptr(xt), ws._ptr(dyt), ws._ptr(dw), ws._ptr(db), 1 << 22, 1, 1, cin, cout,
+                                    s) == -1
     dw_o, db_o = wo.conv3x3_weight_grad(x, dy)
     e_w = _rel(dw.cpu().numpy().reshape(cout, 3, 3, cin), dw_o)
     e_b = _rel(db.cpu().numpy(), db_o)
