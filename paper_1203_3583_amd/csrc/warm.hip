@@ -139,6 +139,88 @@ __global__ __launch_bounds__(64 * kConvWaves) void conv3x3_kernel(
     }
 }
 
+// ---- forward convolution, LDS-tiled ---------------------------------------------
+// Large layers: a workgroup owns an 8 x 32 pixel tile of one image and 32 output
+// channels.  Per 16-channel slice of the input it stages the tile plus its
+// one-pixel halo (BF16, [row][column][16 channels]) and the slice's weights
+// (BF16, [tap][cout][16 channels]) in LDS, then every wave (two rows of the tile,
+// 4 x 2 accumulator tiles) runs the nine taps out of LDS: each input value is
+// fetched from memory once per workgroup instead of once per tap.  A lane's
+// 8-byte LDS reads (4 channels of one pixel, or of one weight row) cover 512
+// contiguous bytes per wave: no bank conflicts.
+constexpr int kTH = 8, kTW = 32;                 // output tile
+constexpr int kHH = kTH + 2, kHWd = kTW + 2;     // tile with halo
+
+__global__ __launch_bounds__(256) void conv3x3_tiled_kernel(
+    const float *__restrict__ in, const uint16_t *__restrict__ w, const float *__restrict__ bias,
+    float *__restrict__ out, int H, int W, int cin, int cout, int relu, int tiles_x, int tiles_y) {
+    __shared__ __align__(16) uint16_t halo[kHH * kHWd * 16];
+    __shared__ __align__(16) uint16_t wl[9 * 32 * 16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int t = blockIdx.x;
+    const int tx = t % tiles_x;
+    t /= tiles_x;
+    const int ty = t % tiles_y;
+    const int b = t / tiles_y;
+    const int y0 = ty * kTH, x0 = tx * kTW;
+    const int co0 = blockIdx.y * 32;
+    const int r = lane & 15, g = lane >> 4;
+    const size_t img = (size_t)b * H * W;
+    v4f acc[4][2];
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb) acc[pb][0] = acc[pb][1] = (v4f){0.f, 0.f, 0.f, 0.f};
+    for (int c0 = 0; c0 < cin; c0 += 16) {
+        __syncthreads();   // the previous slice has been read
+        // the tile and halo: kHH x kHWd pixels x 4 groups of 4 channels
+        for (int i = tid; i < kHH * kHWd * 4; i += 256) {
+            const int q = i & 3, pix = i >> 2;
+            const int hy = pix / kHWd, hx = pix - hy * kHWd;
+            const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                v = *reinterpret_cast<const float4 *>(in + (img + (size_t)yy * W + xx) * cin + c0 + 4 * q);
+            *reinterpret_cast<v4s *>(halo + pix * 16 + 4 * q) = bf16x4(v);
+        }
+        // the slice's weights: 32 couts x 9 taps x 16 channels, 8 per load
+        for (int i = tid; i < 32 * 9 * 2; i += 256) {
+            const int hf = i & 1, rest = i >> 1;
+            const int tap = rest % 9, co = rest / 9;
+            const uint4 v = *reinterpret_cast<const uint4 *>(w + (size_t)(co0 + co) * 9 * cin + tap * cin + c0 + 8 * hf);
+            *reinterpret_cast<uint4 *>(wl + (tap * 32 + co) * 16 + 8 * hf) = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap % 3;   // halo offsets of the tap
+            const v4s bw0 = *reinterpret_cast<const v4s *>(wl + (tap * 32 + r) * 16 + 4 * g);
+            const v4s bw1 = *reinterpret_cast<const v4s *>(wl + (tap * 32 + 16 + r) * 16 + 4 * g);
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) {
+                const int ly = 2 * wave + (pb >> 1), lx = (pb & 1) * 16 + r;
+                const v4s a = *reinterpret_cast<const v4s *>(halo + ((ly + dy) * kHWd + lx + dx) * 16 + 4 * g);
+                acc[pb][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw0, acc[pb][0], 0, 0, 0);
+                acc[pb][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw1, acc[pb][1], 0, 0, 0);
+            }
+        }
+    }
+    // accumulator rows are pixels 4 g + i of the block, column r the output channel
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const int co = co0 + cb * 16 + r;
+        const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int y = y0 + 2 * wave + (pb >> 1), x = x0 + (pb & 1) * 16 + 4 * g + i;
+                if (y >= H || x >= W) continue;
+                float v = acc[pb][cb][i] + bv;
+                if (relu) v = fmaxf(v, 0.f);
+                out[(img + (size_t)y * W + x) * cout + co] = v;
+            }
+    }
+}
+
 // ---- weight gradient ----------------------------------------------------------
 // A wave computes a 32 (cout) x 16 (k) block of dw over a chunk of pixels and
 // adds it to dw with FP32 atomics.  k = (tap, c0 .. c0+15): the block covers 16
@@ -382,9 +464,17 @@ int asf_warm_conv3x3(const float *in, const uint16_t *w, const float *bias, floa
     if (!in || !w || !out || B <= 0 || H <= 0 || W <= 0 || cin <= 0 || cout <= 0 || cin % 16 || cout % 32)
         return -1;
     const int64_t npix = (int64_t)B * H * W;
-    // waves of 64-pixel tiles; fewer than 1024 (one per SIMD) -> 16-pixel tiles
+    // LDS-tiled when its 8 x 32 tiles give at least two workgroups per CU, else
+    // direct: 64-pixel wave tiles, or 16-pixel ones when 64-pixel tiles would
+    // leave SIMDs idle
+    const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + kTH - 1) / kTH;
+    const int64_t tiles = (int64_t)B * tiles_x * tiles_y;
     const int64_t tiles64 = (npix + 63) / 64;
-    if (tiles64 * (cout / 32) >= 1024) {
+    if (tiles * (cout / 32) >= 512 && tiles < (int64_t)1 << 31) {
+        const dim3 grid((unsigned)tiles, (unsigned)(cout / 32));
+        hipLaunchKernelGGL(conv3x3_tiled_kernel, grid, dim3(256), 0, static_cast<hipStream_t>(stream), in, w, bias,
+                           out, H, W, cin, cout, relu, tiles_x, tiles_y);
+    } else if (tiles64 * (cout / 32) >= 1024) {
         const dim3 grid((unsigned)((tiles64 + kConvWaves - 1) / kConvWaves), (unsigned)(cout / 32));
         hipLaunchKernelGGL(conv3x3_kernel<4>, grid, dim3(64 * kConvWaves), 0, static_cast<hipStream_t>(stream), in,
                            w, bias, out, B, H, W, cin, cout, relu);
