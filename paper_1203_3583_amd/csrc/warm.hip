@@ -39,13 +39,12 @@ __device__ __forceinline__ v4s bf16x4(float4 v) {
     return r;
 }
 
-// ---- forward convolution -----------------------------------------------------
+// ---- forward convolution, direct (small layers) -----------------------------------
 // A wave computes 16 PB consecutive pixels (flattened b, y, x) x 32 output
-// channels: PB x 2 accumulator tiles.  Layers take PB = 4 (more MFMAs per
-// operand fetch) unless that gives fewer waves than SIMDs: the small, deep
-// layers take PB = 1 and four times the waves (64^2 pixels, 256 channels:
-// 0.118 -> 0.095 ms).  Four waves per workgroup, on consecutive pixel tiles of the same
-// channel block; no LDS, no barriers.  The contraction runs over (tap, 16
+// channels: PB x 2 accumulator tiles, reading its operands straight from
+// memory (PB = 1 for the small layers this kernel serves: more waves).  Four
+// waves per workgroup, on consecutive pixel tiles of the same channel block; no
+// LDS, no barriers.  The contraction runs over (tap, 16
 // channels) steps, two per iteration with all their loads issued first.
 constexpr int kConvWaves = 4;
 
@@ -464,20 +463,16 @@ int asf_warm_conv3x3(const float *in, const uint16_t *w, const float *bias, floa
     if (!in || !w || !out || B <= 0 || H <= 0 || W <= 0 || cin <= 0 || cout <= 0 || cin % 16 || cout % 32)
         return -1;
     const int64_t npix = (int64_t)B * H * W;
-    // LDS-tiled when its 8 x 32 tiles give at least two workgroups per CU, else
-    // direct: 64-pixel wave tiles, or 16-pixel ones when 64-pixel tiles would
-    // leave SIMDs idle
+    // LDS-tiled unless the layer has fewer than 64 of its 8 x 32 tiles (times the
+    // channel blocks); such small layers take the direct kernel's 16-pixel wave
+    // tiles.  (Measured at 64^2 pixels, 256 -> 256 channels, 128 workgroups:
+    // 0.054 ms tiled against 0.095 ms direct.)
     const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + kTH - 1) / kTH;
     const int64_t tiles = (int64_t)B * tiles_x * tiles_y;
-    const int64_t tiles64 = (npix + 63) / 64;
-    if (tiles * (cout / 32) >= 512 && tiles < (int64_t)1 << 31) {
+    if (tiles * (cout / 32) >= 64 && tiles < (int64_t)1 << 31) {
         const dim3 grid((unsigned)tiles, (unsigned)(cout / 32));
         hipLaunchKernelGGL(conv3x3_tiled_kernel, grid, dim3(256), 0, static_cast<hipStream_t>(stream), in, w, bias,
                            out, H, W, cin, cout, relu, tiles_x, tiles_y);
-    } else if (tiles64 * (cout / 32) >= 1024) {
-        const dim3 grid((unsigned)((tiles64 + kConvWaves - 1) / kConvWaves), (unsigned)(cout / 32));
-        hipLaunchKernelGGL(conv3x3_kernel<4>, grid, dim3(64 * kConvWaves), 0, static_cast<hipStream_t>(stream), in,
-                           w, bias, out, B, H, W, cin, cout, relu);
     } else {
         const int64_t tiles16 = (npix + 15) / 16;
         const dim3 grid((unsigned)((tiles16 + kConvWaves - 1) / kConvWaves), (unsigned)(cout / 32));

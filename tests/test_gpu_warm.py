@@ -29,8 +29,8 @@ def _weights(torch, ws, rng, cout, cin, scale=0.2):
     return wt, ws.bf16_bits(torch, wt), w.reshape(cout, 3, 3, cin)
 
 
-# the three kernels: 16-pixel wave tiles (small), 64-pixel wave tiles (1 x 300 x 250),
-# LDS-tiled (2 x 255 x 259 and 3 x 203 x 100: ragged tiles on both axes, several images)
+# both kernels: direct with 16-pixel wave tiles (the three small cases), LDS-tiled (the
+# three large ones: ragged tiles on both axes, several images)
 @pytest.mark.parametrize("B,H,W,cin,cout,relu", [(2, 8, 12, 16, 32, True), (1, 5, 7, 48, 64, False),
                                                  (1, 16, 16, 32, 96, True), (1, 300, 250, 16, 32, False),
                                                  (2, 255, 259, 16, 64, True), (3, 203, 100, 48, 64, False)])
