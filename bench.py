@@ -169,6 +169,24 @@ def warm_bench(torch, steps=3):
             "inference_tflops": flops / (fwd * 1e-3) / 1e12, "unit": "ms per sample"}
 
 
+def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10):
+    """Achievable HBM bandwidth: a plain device-to-device copy of nbytes, counted as
+    read plus write bytes per second (GB/s), timed with HIP events."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        b.copy_(a)
+    stop.record()
+    torch.cuda.synchronize()
+    sec = start.elapsed_time(stop) * 1e-3 / reps
+    del a, b
+    return 2.0 * nbytes / sec / 1e9
+
+
 def time_steps(torch, plan, x, y, d, u, out, steps, warmup, stage_events):
     for _ in range(warmup):
         plan.setpts(x, y, d)
@@ -232,6 +250,7 @@ def main():
 
     line = line_bench(torch, asf, synth, args.steps, args.warmup)
     warm = warm_bench(torch)
+    copy_gbs = copy_bandwidth(torch, dev)
 
     if args.copy_calibration:
         a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
@@ -283,6 +302,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            # a plain 1 GiB device copy on the same GPU: the bandwidth reachable in practice
+            "copy_gbs": copy_gbs,
+            "frac_of_copy": achieved / copy_gbs if achieved else None,
             "traffic": stored_traffic(),
             "algorithmic_bytes": alg,
             "avg_launch_ms": spread_ms,
