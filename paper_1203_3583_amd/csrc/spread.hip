@@ -25,15 +25,18 @@
 // ~1e9 terms at the lowest modes) and the bit pattern of y is
 // 0x4B400000 + round(t).  One 64-bit integer add of a constant then removes the
 // 0x4B400000 offsets.  Per tile, M = max(|Re c_j|, |Im c_j|) over its points
-// bounds every term's parts, and K = w^2 times the most footprints that start
-// in one cell bounds the terms any cell receives.  Terms are scaled to below
-// 2^22 (rounding step 2^-22 M), and
-//   packed (K <= 511): no cell sum leaves int32 (511 (2^22 + 1/2) < 2^31), so one
-//            64-bit word holds Re + 2^32 Im: a single ds_add_u64 adds both parts
-//            of a term (the carry of the low half into the high half is undone
-//            exactly at unpacking);
-//   split:   denser tiles keep separate 64-bit sums of Re and Im, accumulated in
-//            two sweeps over the same LDS array.
+// bounds every term's parts.  A tile of at most 1023 records gives no cell more
+// than 1023 terms; its terms are scaled to below 2^21 (rounding step 2^-21 M)
+// and packed.  Larger tiles count the footprints starting in each cell: K = w^2
+// times the most of them bounds the terms any cell receives; terms are scaled
+// to below 2^22 (rounding step 2^-22 M), and
+//   packed (K <= 511): no cell sum leaves int32 (511 (2^22 + 1/2) < 2^31, and
+//            1023 (2^21 + 1/2) < 2^31), so one 64-bit word holds Re + 2^32 Im:
+//            a single ds_add_u64 adds both parts of a term (the carry of the low
+//            half into the high half is undone exactly at unpacking);
+//   split:   denser tiles, and grids so small that the padded tile folds onto
+//            itself, keep separate 64-bit sums of Re and Im, accumulated in two
+//            sweeps over the same LDS array.
 // Integer addition is associative, so the spread is bitwise deterministic.
 //
 // Bank conflicts.  A wave's 64 lanes add the same footprint offset to 64
@@ -186,6 +189,9 @@ __device__ inline void accumulate(unsigned long long *row, float4 d, bool packed
 // takes the spread from 0.159 to 0.144 ms; a threshold of 1024 left most of its
 // tiles conflicted.)
 constexpr uint32_t kDealRecords = 64;
+// Tiles of at most this many records skip the start histogram and pack their
+// cells with terms below 2^21: no cell sum can leave int32.
+constexpr uint32_t kFewRecords = 1023;
 
 // Read back the tile's own cells in the order they are written out and convert
 // them to FP32.  Thread tid handles cells tid + k nt of the tile in panel order;
@@ -233,7 +239,7 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
     __shared__ __align__(16) float4 sdat[SDAT];          // dealt records (Re c, Im c, fx, fy)
     __shared__ int sbase[kChunk + 16];                   // their padded start cell
     __shared__ unsigned rcount[16];                      // records per start residue
-    __shared__ float red[2][kThreads / 64];
+    __shared__ unsigned sbig, smost;                     // block maxima
     int *starts = reinterpret_cast<int *>(sdat);         // footprint-start histogram (phase A)
 
     const int t = blockIdx.x;
@@ -247,23 +253,29 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
     const uint32_t per_batch = (uint32_t)(kBatch * nt);
     const int ty = t >> p.log_ntx, tx = t & ((1 << p.log_ntx) - 1);
     const int x0 = tx << p.log_tile_x, y0 = ty << p.log_tile_y;
+    uint32_t s0, s1;
+    tile_slots(b, t, s0, s1);
+    const uint32_t nrec = s1 - s0;
+    const bool reload = nrec > per_batch;
+    const bool deal = nrec > kDealRecords;
+    // a tile of few records needs no start histogram: no cell receives more than
+    // nrec terms (unless the grid folds the padded tile onto itself: split sums)
+    const bool few = nrec <= kFewRecords && !fold_x && !fold_y;
     {
         uint4 *a4 = reinterpret_cast<uint4 *>(acc);
         for (int i = tid; i < G::CELLS / 2; i += nt) a4[i] = make_uint4(0u, 0u, 0u, 0u);
-        for (int i = tid; i < swx * swy; i += nt) starts[i] = 0;
+        if (!few)
+            for (int i = tid; i < swx * swy; i += nt) starts[i] = 0;
         if (tid < 16) rcount[tid] = 0u;
+        if (tid == 0) sbig = smost = 0u;
     }
-    uint32_t s0, s1;
-    tile_slots(b, t, s0, s1);
-    const bool reload = s1 - s0 > per_batch;
-    const bool deal = s1 - s0 > kDealRecords;
     Batch r;
     int rb[kBatch];   // padded start cell of each record, -1 if it does not touch the tile
     __syncthreads();
 
-    // phase A: largest |Re c| or |Im c| and the count of footprint starts per
-    // position.  A tile of at most kBatch * nt records keeps them in registers
-    // for phase B; larger tiles reload them there.
+    // phase A: largest |Re c| or |Im c| (and, for larger tiles, the count of
+    // footprint starts per position).  A tile of at most kBatch * nt records
+    // keeps them in registers for phase B; larger tiles reload them there.
     float big = 0.f;
     for (uint32_t base = s0; base < s1; base += per_batch) {
         load_records(r, b, base + tid, s1, nt);
@@ -275,36 +287,37 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
             if (r.j[k] < p.n && local_start(r.cell[k], x0, y0, PAD, hix, hiy, p.nfx, p.nfy, px, py)) {
                 rb[k] = py * PITCH + px;
                 big = fmaxf(big, fmaxf(fabsf(r.pc[k].x), fabsf(r.pc[k].y)));
-                atomicAdd(&starts[py * swx + px], 1);
+                if (!few) atomicAdd(&starts[py * swx + px], 1);
             }
         }
     }
-    __syncthreads();               // starts[] complete
-    int most = 0;                  // most footprint starts in one cell
-    for (int i = tid; i < swx * swy; i += nt) most = max(most, starts[i]);
-    float mostf = (float)most;
+    // block maximum: non-negative floats order like their bit patterns
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        big = fmaxf(big, __shfl_xor(big, off));
-        mostf = fmaxf(mostf, __shfl_xor(mostf, off));
+    for (int off = 32; off > 0; off >>= 1) big = fmaxf(big, __shfl_xor(big, off));
+    if (lane == 0) atomicMax(&sbig, __float_as_uint(big));
+    __syncthreads();               // sbig and starts[] complete
+    big = __uint_as_float(sbig);
+    bool packed;
+    int emax;                      // terms are bounded by 2^emax
+    if (few) {
+        packed = true;             // kFewRecords (2^21 + 1/2) < 2^31
+        emax = 21;
+    } else {
+        unsigned most = 0u;        // most footprint starts in one cell
+        for (int i = tid; i < swx * swy; i += nt) most = max(most, (unsigned)starts[i]);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) most = max(most, (unsigned)__shfl_xor((int)most, off));
+        if (lane == 0) atomicMax(&smost, most);
+        __syncthreads();
+        // 511 (2^22 + 1/2) < 2^31; grids folding the tile onto itself sum several cells
+        packed = smost * (unsigned)(W * W) <= 511u && !fold_x && !fold_y;
+        emax = 22;
     }
-    if (lane == 0) {
-        red[0][tid >> 6] = big;
-        red[1][tid >> 6] = mostf;
-    }
-    __syncthreads();
-    big = 0.f;
-    mostf = 0.f;
-    for (int i = 0; i < nt / 64; ++i) {
-        big = fmaxf(big, red[0][i]);
-        mostf = fmaxf(mostf, red[1][i]);
-    }
-    const bool packed = mostf * (float)(W * W) <= 511.f;   // 511 (2^22 + 1/2) < 2^31
     int e = 0;
     if (big > 0.f) {
         int em;
         frexpf(big * (1.f + 0x1p-18f), &em);   // margin for rounding in c and psi
-        e = 22 - em;                            // terms bounded by 2^22
+        e = emax - em;
     }
     e = max(-120, min(e, 120));
     const float scale = ldexpf(1.f, e);
