@@ -169,7 +169,7 @@ def warm_bench(torch, steps=3):
             "inference_tflops": flops / (fwd * 1e-3) / 1e12, "unit": "ms per sample"}
 
 
-def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10):
+def copy_bandwidth(torch, dev, nbytes=256 << 20, reps=20):
     """Achievable HBM bandwidth: a plain device-to-device copy of nbytes, counted as
     read plus write bytes per second (GB/s), timed with HIP events."""
     a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -302,7 +302,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            # a plain 1 GiB device copy on the same GPU: the bandwidth reachable in practice
+            # a plain 256 MiB device copy on the same GPU: the bandwidth reachable in practice
             "copy_gbs": copy_gbs,
             "frac_of_copy": achieved / copy_gbs if achieved else None,
             "traffic": stored_traffic(),
