@@ -707,7 +707,7 @@ hipError_t dispatch_adj1(int len, const float2 *mid, float2 *fine, const float2 
         case 9: return launch_adj1<9, 16, SPLIT>(mid, fine, tw, w16, nfx, my, s);
         case 10: return launch_adj1<10, 8, SPLIT>(mid, fine, tw, w16, nfx, my, s);
         case 11: return launch_adj1<11, 4, SPLIT>(mid, fine, tw, w16, nfx, my, s);
-        case 12: return launch_adj1<12, 1, SPLIT>(mid, fine, tw, w16, nfx, my, s);
+        case 12: return launch_adj1<12, 2, SPLIT>(mid, fine, tw, w16, nfx, my, s);
         case 13: return launch_adj1<13, 1, SPLIT>(mid, fine, tw, w16, nfx, my, s);
         case 14: return launch_adj1<14, 1, SPLIT>(mid, fine, tw, w16, nfx, my, s);
         default: return hipErrorInvalidValue;
@@ -731,7 +731,7 @@ hipError_t dispatch1(const FftShape &sh, const float2 *fine, float2 *mid, const 
         case 9: return launch1<9, 16, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
         case 10: return launch1<10, 8, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
         case 11: return launch1<11, 4, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
-        case 12: return launch1<12, 1, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
+        case 12: return launch1<12, 2, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
         case 13: return launch1<13, 1, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
         case 14: return launch1<14, 1, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
         default: return hipErrorInvalidValue;
@@ -762,7 +762,7 @@ hipError_t dispatch2(const FftShape &sh, int log_panel, const float2 *mid, float
 
 int fft_batch_pass1(int len) {
     const int log = __builtin_ctz(len);
-    return log <= 9 ? 16 : log == 10 ? 8 : log == 11 ? 4 : 1;
+    return log <= 9 ? 16 : log == 10 ? 8 : log == 11 ? 4 : log == 12 ? 2 : 1;
 }
 
 int fft_batch_pass2(int len) {
