@@ -476,46 +476,76 @@ __global__ void __launch_bounds__(kInterpThreads) interp_kernel(SpreadParams p, 
     const int C = 1 << p.log_panel;
     const int rxp = (rx + C - 1) & ~(C - 1);
     const float inv_ry = 1.f / (float)ry;
-    for (int i = tid; i < rxp * ry; i += nt) {
-        const int c = i & (C - 1);
-        const int rest = i >> p.log_panel;
-        const int qx = (int)(((float)rest + 0.5f) * inv_ry);   // rest / ry, exact for rest < 2^20
-        const int yy = rest - qx * ry;
-        const int xx = qx * C + c;
-        if (xx >= rx) continue;
-        int gx = x0 + xx, gy = y0 + yy;
-        if (gx >= p.nfx) gx -= p.nfx;
-        if (gy >= p.nfy) gy -= p.nfy;
-        reg[yy * RP + xx] = fine[(((size_t)(gx >> p.log_panel) * p.nfy + gy) << p.log_panel) + (gx & (C - 1))];
+    // kRegionLoads elements per thread in flight before their LDS writes
+    constexpr int kRegionLoads = 6;
+    for (int i0 = tid; i0 < rxp * ry; i0 += kRegionLoads * nt) {
+        float2 v[kRegionLoads];
+        int at[kRegionLoads];
+#pragma unroll
+        for (int q = 0; q < kRegionLoads; ++q) {
+            const int i = i0 + q * nt;
+            const int c = i & (C - 1);
+            const int rest = i >> p.log_panel;
+            const int qx = (int)(((float)rest + 0.5f) * inv_ry);   // rest / ry, exact for rest < 2^20
+            const int yy = rest - qx * ry;
+            const int xx = qx * C + c;
+            at[q] = (i < rxp * ry && xx < rx) ? yy * RP + xx : -1;
+            int gx = x0 + xx, gy = y0 + yy;
+            if (gx >= p.nfx) gx -= p.nfx;
+            if (gy >= p.nfy) gy -= p.nfy;
+            v[q] = at[q] >= 0 ? fine[(((size_t)(gx >> p.log_panel) * p.nfy + gy) << p.log_panel) + (gx & (C - 1))]
+                              : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < kRegionLoads; ++q)
+            if (at[q] >= 0) reg[at[q]] = v[q];
     }
     __syncthreads();
     uint32_t s0, s1;
     tile_slots(b, t, s0, s1);
-    for (uint32_t s = s0 + tid; s < s1; s += nt) {
-        const uint32_t cell = b.cell[s];
-        const int px = (int)(cell & 0xffffu) - x0, py = (int)(cell >> 16) - y0;
-        if (px < 0 || px >= tsx || py < 0 || py >= tsy) continue;   // not this point's home tile
-        const uint32_t j = b.perm[s];
-        const float2 fr = b.frac[s], ph = b.phase[s];
-        float kx[W], ky[W];
-        es_values<W>(fr.x, kx);
-        es_values<W>(fr.y, ky);
-        const float2 *row = reg + py * RP + px;
-        float ar = 0.f, ai = 0.f;
+    // two records per thread and iteration: their loads go out together
+    for (uint32_t sb = s0 + tid; sb < s1; sb += 2 * nt) {
+        uint32_t cell[2];
 #pragma unroll
-        for (int jy = 0; jy < W; ++jy) {
-            float sr = 0.f, si = 0.f;
+        for (int q = 0; q < 2; ++q) cell[q] = sb + q * nt < s1 ? b.cell[sb + q * nt] : 0xffffffffu;
+        bool home[2];
+        int px[2], py[2];
+        uint32_t j[2];
+        float2 fr[2], ph[2];
 #pragma unroll
-            for (int i = 0; i < W; ++i) {
-                const float2 v = row[jy * RP + i];
-                sr = __builtin_fmaf(kx[i], v.x, sr);
-                si = __builtin_fmaf(kx[i], v.y, si);
-            }
-            ar = __builtin_fmaf(ky[jy], sr, ar);
-            ai = __builtin_fmaf(ky[jy], si, ai);
+        for (int q = 0; q < 2; ++q) {
+            px[q] = (int)(cell[q] & 0xffffu) - x0;
+            py[q] = (int)(cell[q] >> 16) - y0;
+            // a point is handled in its home tile only (and past s1 nowhere)
+            home[q] = sb + q * nt < s1 && px[q] >= 0 && px[q] < tsx && py[q] >= 0 && py[q] < tsy;
+            const uint32_t s = sb + q * nt;
+            j[q] = home[q] ? b.perm[s] : 0u;
+            fr[q] = home[q] ? b.frac[s] : make_float2(0.f, 0.f);
+            ph[q] = home[q] ? b.phase[s] : make_float2(0.f, 0.f);
         }
-        // times conj(exp(i phi))
-        g1[j] = make_float2(ar * ph.x + ai * ph.y, ai * ph.x - ar * ph.y);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (!home[q]) continue;
+            float kx[W], ky[W];
+            es_values<W>(fr[q].x, kx);
+            es_values<W>(fr[q].y, ky);
+            const float2 *row = reg + py[q] * RP + px[q];
+            float ar = 0.f, ai = 0.f;
+#pragma unroll
+            for (int jy = 0; jy < W; ++jy) {
+                float sr = 0.f, si = 0.f;
+#pragma unroll
+                for (int i = 0; i < W; ++i) {
+                    const float2 v = row[jy * RP + i];
+                    sr = __builtin_fmaf(kx[i], v.x, sr);
+                    si = __builtin_fmaf(kx[i], v.y, si);
+                }
+                ar = __builtin_fmaf(ky[jy], sr, ar);
+                ai = __builtin_fmaf(ky[jy], si, ai);
+            }
+            // times conj(exp(i phi))
+            g1[j[q]] = make_float2(ar * ph[q].x + ai * ph[q].y, ai * ph[q].x - ar * ph[q].y);
+        }
     }
 }
 
