@@ -63,7 +63,7 @@ struct Layout {
     int mx, my, nfx, nfy, w, tile_x, tile_y, ntx, nty, ntiles;
     double beta;
     int64_t slot_cap;
-    size_t off_status, off_tile_start, off_cursor, off_cell, off_frac, off_phase, off_perm;
+    size_t off_status, off_tile_start, off_cursor, off_slab, off_cell, off_frac, off_phase, off_perm;
     size_t off_fine, off_mid, off_dx, off_dy, off_twx, off_twy, off_w16, total;
 };
 
@@ -115,6 +115,7 @@ int make_layout(int64_t n, const asf_params *p, Layout &L) {
     L.off_status = take(kAlign);
     L.off_tile_start = take(sizeof(uint32_t) * (L.ntiles + 1));
     L.off_cursor = take(sizeof(uint32_t) * L.ntiles);
+    L.off_slab = take(sizeof(uint2) * L.ntiles);
     L.off_cell = take(sizeof(uint32_t) * L.slot_cap);
     L.off_frac = take(sizeof(float2) * L.slot_cap);
     L.off_phase = take(sizeof(float2) * L.slot_cap);
@@ -209,6 +210,7 @@ struct asf_plan_s {
     float2 *fine, *mid, *dx, *dy, *twx, *twy, *w16;
     int timing;
     bool count_first;   // bin with the compact layout directly (crowded last time)
+    bool sized_slabs;   // the slabs were sized from a crowded binning's counts
     bool events;
     hipEvent_t ev[2 * asf::NSTAGES];
     bool recorded[asf::NSTAGES];
@@ -254,7 +256,7 @@ int run_geometry(asf_plan_s *p, const double *x, const double *y, const double *
             e = asf::launch_bin_count(p->geo, p->bin, p->lay.n, x, y, d, s);
             if (e != hipSuccess) return hip_fail(e, "bin_count launch");
         } else {
-            e = asf::launch_bin_fill(p->geo, p->bin, p->lay.n, x, y, d, s);
+            e = asf::launch_bin_fill(p->geo, p->bin, p->lay.n, x, y, d, p->sized_slabs, s);
             if (e != hipSuccess) return hip_fail(e, "bin_fill launch");
         }
     }
@@ -302,7 +304,15 @@ int upload_tables(asf_plan_s *p, hipStream_t s) {
         const double a = 2.0 * kPi * e / 16.0;
         w16[e] = make_float2((float)std::cos(a), (float)-std::sin(a));
     }
+    // the first slabs: uniform, a multiple of 16 slots but not of 256, so that the
+    // tiles' slabs do not start at power-of-two strides (the workgroups spreading
+    // neighbouring tiles would read the same memory channels)
+    uint32_t cap = (uint32_t)(L.slot_cap / L.ntiles) & ~15u;
+    if (cap >= 256 && cap % 256 == 0) cap -= 16;
+    std::vector<uint2> slab(L.ntiles);
+    for (int t = 0; t < L.ntiles; ++t) slab[t] = make_uint2((uint32_t)t * cap, cap);
     struct { void *dst; const void *src; size_t n; } copies[] = {
+        {p->bin.slab, slab.data(), slab.size() * sizeof(uint2)},
         {p->dx, dx.data(), dx.size() * sizeof(float2)},
         {p->dy, dy.data(), dy.size() * sizeof(float2)},
         {p->twx, twx.data(), twx.size() * sizeof(float2)},
@@ -327,8 +337,9 @@ int read_status(asf_plan_s *p, hipStream_t s) {
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     // kStatusCompact and kStatusFits only describe the binned layout: the next
     // binning counts first if this one needed the compact layout, unless its
-    // scan found that every tile would now fit its slab
+    // scan sized new slabs from the counts that fit in the slot arrays
     p->count_first = (st & asf::kStatusCompact) && !(st & asf::kStatusFits);
+    if ((st & asf::kStatusCompact) && (st & asf::kStatusFits)) p->sized_slabs = true;
     if (st & asf::kStatusDomain)
         return fail(ASF_EDOMAIN, "some point has r0 = z0 - d1 <= 0 or a non-finite coordinate");
     if (st & asf::kStatusOverflow) return fail(ASF_EHIP, "internal error: tile bin overflow");
@@ -373,14 +384,8 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
     pl->bin.frac = reinterpret_cast<float2 *>(w + L.off_frac);
     pl->bin.phase = reinterpret_cast<float2 *>(w + L.off_phase);
     pl->bin.perm = reinterpret_cast<uint32_t *>(w + L.off_perm);
-    {
-        // slab slots per tile: a multiple of 16 but not of 256, so that the tiles'
-        // slabs do not start at power-of-two strides (the workgroups spreading
-        // neighbouring tiles would read the same memory channels)
-        uint32_t cap = (uint32_t)(L.slot_cap / L.ntiles) & ~15u;
-        if (cap >= 256 && cap % 256 == 0) cap -= 16;
-        pl->bin.cap = cap;
-    }
+    pl->bin.slab = reinterpret_cast<uint2 *>(w + L.off_slab);
+    pl->bin.slot_cap = (uint32_t)L.slot_cap;
     pl->fine = reinterpret_cast<float2 *>(w + L.off_fine);
     pl->mid = reinterpret_cast<float2 *>(w + L.off_mid);
     pl->dx = reinterpret_cast<float2 *>(w + L.off_dx);

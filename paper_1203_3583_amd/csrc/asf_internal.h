@@ -10,25 +10,28 @@ namespace asf {
 
 // Binned point list: one slot per (point, fine-grid tile its footprint touches).
 // Two layouts share the slot arrays.  Slab (the normal case): tile t owns the
-// `cap` slots from t * cap, and cursor[t] counts its records (also past cap).
-// Compact (after a slab overflowed): the tiles' records are packed in tile
-// order, tile t in [tile_start[t], tile_start[t + 1]).  Status bit 2 names the
-// layout in use.
+// slots [slab[t].x, slab[t].x + slab[t].y), and cursor[t] counts its records
+// (also past the slab's end).  The first slabs are uniform (4 n / ntiles slots
+// each); a binning that needed the compact layout sizes new ones from its tile
+// counts for the next binning.  Compact (after a slab overflowed): the tiles'
+// records are packed in tile order, tile t in [tile_start[t], tile_start[t + 1]).
+// Status bit kStatusCompact names the layout in use.
 struct Binned {
     uint32_t *status;      // [1] kStatus* bits
     uint32_t *tile_start;  // [ntiles + 1] compact layout: exclusive scan of slot counts per tile
     uint32_t *cursor;      // [ntiles] slot counts; compact layout: then insertion cursors
+    uint2 *slab;           // [ntiles] first slot and slot count of each tile's slab
     uint32_t *cell;        // [slot_cap] first footprint cell, l0x | l0y << 16
     float2 *frac;          // [slot_cap] (gx - l0x - (w-1)/2, gy - l0y - (w-1)/2), in (-1/2, 1/2]
     float2 *phase;         // [slot_cap] exp(i phi_j), the pre-phase of Eq. (8)
     uint32_t *perm;        // [slot_cap] index j of the point in the caller's order
-    uint32_t cap;          // slab slots per tile, slot_cap / ntiles
+    uint32_t slot_cap;     // slots in the arrays above (4 n_src)
 };
 
 constexpr uint32_t kStatusDomain = 1u;    // some point has r0 <= 0 or a non-finite coordinate
 constexpr uint32_t kStatusOverflow = 2u;  // compact layout ran out of slots (internal error)
 constexpr uint32_t kStatusCompact = 4u;   // the compact layout is in use
-constexpr uint32_t kStatusFits = 8u;      // compact layout, but every tile would fit its slab
+constexpr uint32_t kStatusFits = 8u;      // compact layout, and new slabs sized from its counts fit
 
 // Slots [s0, s1) of tile t in whichever layout the last binning left.
 __device__ inline void tile_slots(const Binned &b, int t, uint32_t &s0, uint32_t &s1) {
@@ -36,8 +39,9 @@ __device__ inline void tile_slots(const Binned &b, int t, uint32_t &s0, uint32_t
         s0 = b.tile_start[t];
         s1 = b.tile_start[t + 1];
     } else {
-        s0 = (uint32_t)t * b.cap;
-        s1 = s0 + min(b.cursor[t], b.cap);
+        const uint2 sl = b.slab[t];
+        s0 = sl.x;
+        s1 = s0 + min(b.cursor[t], sl.y);
     }
 }
 
@@ -112,8 +116,9 @@ hipError_t launch_bin_reset(const Binned &b, int ntiles, hipStream_t s);
 // once unless the status word says the compact layout is in use
 hipError_t launch_bin_count(const GeoParams &g, const Binned &b, int64_t n, const double *x,
                             const double *y, const double *d, hipStream_t s);
+// crowded: slabs sized from a compact binning's counts (fewer workgroups at a time)
 hipError_t launch_bin_fill(const GeoParams &g, const Binned &b, int64_t n, const double *x,
-                           const double *y, const double *d, hipStream_t s);
+                           const double *y, const double *d, bool crowded, hipStream_t s);
 hipError_t launch_bin_scan(const Binned &b, int ntiles, hipStream_t s);
 hipError_t launch_bin_scatter(const GeoParams &g, const Binned &b, int64_t n, const double *x,
                               const double *y, const double *d, hipStream_t s);

@@ -22,20 +22,22 @@
 //
 // Binning: each point is listed once in every tile its w x w footprint touches
 // (1, 2 or 4 tiles), so the spreading kernel can own its tile outright and write
-// it with plain stores.  When the points cover the fine grid evenly, one pass
-// bins them into fixed slabs of slots, one per tile (the workspace holds 4 slots
-// per point, so a slab has 4 n / ntiles): a per-tile cursor hands out the slots
-// and counts the records.  If some tile receives more records than its slab
-// (points crowded into part of the grid), the compact layout is built instead:
-// an exclusive scan of the per-tile counts, then a second pass that packs the
-// records in tile order.  The scan and that pass are always launched and return
-// at once when the slabs held, so the host never waits for the decision.  A
-// plan whose last synchronised binning needed the compact layout counts first
-// (a lighter pass than the slab pass it would waste) until a scan reports that
-// every tile would fit its slab again.  Slot reservation aggregates per
-// wavefront: the lanes are grouped by tile without memory traffic, then one lane
-// per group issues the atomic -- all groups' atomics in the same instruction, so
-// a wave waits for one round trip rather than one per tile.
+// it with plain stores.  One pass bins the points into slabs of slots, one per
+// tile: a per-tile cursor hands out the slots and counts the records.  The
+// first slabs are uniform (the workspace holds 4 slots per point, so a slab has
+// 4 n / ntiles), which suits points that cover the fine grid evenly.  If some
+// tile receives more records than its slab (points crowded into part of the
+// grid), the compact layout is built instead: an exclusive scan of the per-tile
+// counts, then a second pass that packs the records in tile order.  The scan
+// and that pass are always launched and return at once when the slabs held, so
+// the host never waits for the decision.  The scan also sizes new slabs from
+// the counts (a quarter and 16 slots of headroom each) for the next binning; a
+// plan whose last synchronised binning needed the compact layout bins into
+// those if they fit, and otherwise counts first (a lighter pass than a slab
+// pass it would waste).  Slot reservation aggregates per wavefront: the lanes
+// are grouped by tile without memory traffic, then one lane per group issues
+// the atomic -- all groups' atomics in the same instruction, so a wave waits for
+// one round trip rather than one per tile.
 #include "asf_internal.h"
 
 namespace asf {
@@ -205,8 +207,9 @@ __device__ inline void bin_block(const GeoParams &g, const Binned &b, int64_t n,
             uint32_t slot;
             bool ok;
             if (SLAB) {
-                slot = (uint32_t)key * b.cap + pos;
-                ok = pos < b.cap;
+                const uint2 sl = act ? b.slab[key] : make_uint2(0u, 0u);
+                slot = sl.x + pos;
+                ok = pos < sl.y;
                 // one flag per wave: a crowded tile can overflow by millions of records
                 if (__ballot(act && !ok) != 0ull && __lane_id() == 0) atomicOr(b.status, kStatusCompact);
             } else {
@@ -229,6 +232,18 @@ __global__ void __launch_bounds__(kGeoThreads) bin_fill_kernel(GeoParams g, Binn
                                                                const double *__restrict__ y,
                                                                const double *__restrict__ d) {
     bin_block<true>(g, b, n, blockIdx.x, x, y, d);
+}
+
+// The slab pass for crowded geometries: kFallbackBlocks workgroups loop over the
+// point blocks, fewer at a time contending for the hot tiles' cursors (4096^2
+// relief: 0.35 ms, against 0.64 ms with one workgroup per block).
+__global__ void __launch_bounds__(kGeoThreads) bin_fill_loop_kernel(GeoParams g, Binned b, int64_t n,
+                                                                    const double *__restrict__ x,
+                                                                    const double *__restrict__ y,
+                                                                    const double *__restrict__ d) {
+    const int64_t per = (int64_t)kGeoThreads * kBinPoints;
+    const int64_t nblk = (n + per - 1) / per;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) bin_block<true>(g, b, n, blk, x, y, d);
 }
 
 // Count-first binning (the compact layout without the slab pass): records per
@@ -263,64 +278,88 @@ __global__ void __launch_bounds__(kGeoThreads) bin_count_kernel(GeoParams g, Bin
     }
 }
 
-// Compact layout: exclusive scan of the per-tile counts by one workgroup of 1024 threads, in
-// chunks of 8192 tiles: each thread loads 8 consecutive counts at once, the
-// thread sums are scanned within waves by shuffles and across the 16 waves
-// through LDS, and a running carry links the chunks.
+// Compact layout: exclusive scan of the per-tile counts by one workgroup of
+// 1024 threads, in chunks of 8192 tiles: each thread loads 8 consecutive counts
+// at once, the thread sums are scanned within waves by shuffles and across the
+// 16 waves through LDS, and a running carry links the chunks.  A second scan
+// sizes slabs for the next binning from the same counts, each with a quarter
+// and 16 slots of headroom (a multiple of 16 slots); if they fit in the slot
+// arrays they are written and kStatusFits is set.
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 8;
 
-__global__ void __launch_bounds__(kScanThreads) bin_scan_kernel(Binned b, int ntiles) {
-    __shared__ uint32_t wsum[kScanThreads / 64];
-    __shared__ uint32_t too_big;
-    if (!(b.status[0] & kStatusCompact)) return;   // every slab held its tile
+__device__ inline uint32_t slab_want(uint32_t count) {
+    const uint64_t w = ((uint64_t)count + (count >> 2) + 31u) & ~(uint64_t)15u;
+    return w < 0xfffffff0ull ? (uint32_t)w : 0xfffffff0u;
+}
+
+// Exclusive scan of f(cursor[t]) over the tiles in 64-bit sums; calls put(t,
+// start, value) for each tile and returns the total.  Every thread of the block
+// must call it.
+template <class F, class P>
+__device__ inline uint64_t block_scan(const Binned &b, int ntiles, uint64_t *wsum, F f, P put) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    if (t == 0) too_big = 0u;
-    __syncthreads();
-    uint32_t carry = 0;
+    uint64_t carry = 0;
     for (int base = 0; base < ntiles; base += kScanThreads * kScanPer) {
         const int lo = base + t * kScanPer;
         uint32_t v[kScanPer];
-        uint32_t s = 0;
+        uint64_t s = 0;
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
-            v[k] = lo + k < ntiles ? b.cursor[lo + k] : 0u;
+            v[k] = lo + k < ntiles ? f(b.cursor[lo + k]) : 0u;
             s += v[k];
-            if (v[k] > b.cap) too_big = 1u;   // benign race: every writer stores 1
         }
-        uint32_t inc = s;   // inclusive scan within the wave
+        uint64_t inc = s;   // inclusive scan within the wave
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t u = __shfl_up(inc, off);
+            const uint64_t u = __shfl_up(inc, off);
             if (lane >= off) inc += u;
         }
         if (lane == 63) wsum[wave] = inc;
         __syncthreads();
         if (wave == 0) {
-            uint32_t u = lane < kScanThreads / 64 ? wsum[lane] : 0u;
+            uint64_t u = lane < kScanThreads / 64 ? wsum[lane] : 0u;
 #pragma unroll
             for (int off = 1; off < kScanThreads / 64; off <<= 1) {
-                const uint32_t q = __shfl_up(u, off);
+                const uint64_t q = __shfl_up(u, off);
                 if (lane >= off) u += q;
             }
             if (lane < kScanThreads / 64) wsum[lane] = u;   // inclusive totals of waves 0..lane
         }
         __syncthreads();
-        uint32_t run = carry + (wave ? wsum[wave - 1] : 0u) + inc - s;
+        uint64_t run = carry + (wave ? wsum[wave - 1] : 0u) + inc - s;
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
-            if (lo + k < ntiles) {
-                b.tile_start[lo + k] = run;
-                b.cursor[lo + k] = run;
-            }
+            if (lo + k < ntiles) put(lo + k, run, v[k]);
             run += v[k];
         }
         carry += wsum[kScanThreads / 64 - 1];
         __syncthreads();   // wsum is rewritten by the next chunk
     }
-    if (t == 0) {
-        b.tile_start[ntiles] = carry;
-        if (!too_big) atomicOr(b.status, kStatusFits);
+    return carry;
+}
+
+__global__ void __launch_bounds__(kScanThreads) bin_scan_kernel(Binned b, int ntiles) {
+    __shared__ uint64_t wsum[kScanThreads / 64];
+    if (!(b.status[0] & kStatusCompact)) return;   // every slab held its tile
+    // slabs for the next binning, written only if they fit (the total is uniform
+    // over the block), then the compact layout itself (slot counts never exceed
+    // 4 n < 2^32), which rewrites the counts as insertion cursors
+    const auto want = [](uint32_t c) { return slab_want(c); };
+    const uint64_t need = block_scan(b, ntiles, wsum, want, [](int, uint64_t, uint32_t) {});
+    const bool fits = need <= (uint64_t)b.slot_cap;
+    if (fits)
+        block_scan(b, ntiles, wsum, want,
+                   [&](int t, uint64_t start, uint32_t v) { b.slab[t] = make_uint2((uint32_t)start, v); });
+    const uint64_t total = block_scan(
+        b, ntiles, wsum, [](uint32_t c) { return c; },
+        [&](int t, uint64_t start, uint32_t) {
+            b.tile_start[t] = (uint32_t)start;
+            b.cursor[t] = (uint32_t)start;
+        });
+    if (threadIdx.x == 0) {
+        b.tile_start[ntiles] = (uint32_t)total;
+        if (fits) atomicOr(b.status, kStatusFits);
     }
 }
 
@@ -344,10 +383,15 @@ hipError_t launch_bin_reset(const Binned &b, int ntiles, hipStream_t s) {
 }
 
 hipError_t launch_bin_fill(const GeoParams &g, const Binned &b, int64_t n, const double *x,
-                           const double *y, const double *d, hipStream_t s) {
+                           const double *y, const double *d, bool crowded, hipStream_t s) {
     const int64_t per = (int64_t)kGeoThreads * kBinPoints;
     const int64_t blocks = (n + per - 1) / per;
-    hipLaunchKernelGGL(bin_fill_kernel, dim3((unsigned)blocks), dim3(kGeoThreads), 0, s, g, b, n, x, y, d);
+    if (crowded) {
+        const int grid = (int)(blocks < kFallbackBlocks ? blocks : kFallbackBlocks);
+        hipLaunchKernelGGL(bin_fill_loop_kernel, dim3(grid), dim3(kGeoThreads), 0, s, g, b, n, x, y, d);
+    } else {
+        hipLaunchKernelGGL(bin_fill_kernel, dim3((unsigned)blocks), dim3(kGeoThreads), 0, s, g, b, n, x, y, d);
+    }
     return hipGetLastError();
 }
 

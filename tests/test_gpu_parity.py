@@ -97,15 +97,34 @@ def test_hot_tile_all_points_in_one_cell_block():
     w = synth.Workload("hot", x, y, d, u, 532e-9, 0.1, 8e-6, 8e-6, 64, 64)
     got, _ = gpu_forward(w)
     assert rel_l2(got, _full_grid(w)) <= 1e-5
+    # slabs sized from these counts would not fit in 4 n slots: the plan keeps the
+    # compact layout and re-bins by counting first, with the same result
+    torch = torch_gpu()
+    import paper_1203_3583_amd as asf
+
+    xd, yd, dd, ud = to_dev(torch, w)
+    plan = asf.Plan(xd, yd, dd, w.lam, w.z0, w.p2x, w.p2y, w.mx, w.my)
+    status = plan.workspace_view(plan.info()["off_status"], 1, torch.int32)
+    first = plan.forward(ud).cpu().numpy()
+    st0 = int(status.item())
+    plan.setpts(xd, yd, dd)
+    plan.status()
+    again = plan.forward(ud).cpu().numpy()
+    st1 = int(status.item())
+    plan.close()
+    assert st0 == 4 and st1 == 4
+    assert np.array_equal(first, again)
 
 
 def test_binning_layout_switches_with_crowding():
     """One plan re-binned between an even geometry (frequencies wrapping over the
-    whole fine grid: every tile fits its slab of 4 n / ntiles slots) and one with
-    40% of the points in one spot (four tiles overflow their slabs: the compact
-    layout packs the bins).  The status word names the layout; after a crowded
-    binning the plan counts first until a scan finds that the slabs would fit
-    again.  Every binning reproduces a fresh plan bit for bit and the oracle."""
+    whole fine grid: every tile fits its first, uniform slab of 4 n / ntiles slots)
+    and one with 40% of the points in one spot (four tiles overflow their slabs:
+    the compact layout packs the bins).  The status word names the layout; a
+    compact binning sizes new slabs from its tile counts, which the next binning
+    of the same geometry fills in one pass, and which overflow again when the
+    geometry changes back.  Every binning reproduces a fresh plan bit for bit and
+    the oracle."""
     torch = torch_gpu()
     import dataclasses
     import paper_1203_3583_amd as asf
@@ -133,9 +152,9 @@ def test_binning_layout_switches_with_crowding():
     for geo in ((xc, yc, dc), (xc, yc, dc), (xe, ye, de), (xe, ye, de)):
         plan.setpts(*geo)
         seq.append(run())
-    # slab pass overflowed -> compact; counted first -> compact; counted first and
-    # every tile would fit -> compact + fits; slabs again
-    assert [st for st, _ in seq] == [0, 4, 4, 12, 0]
+    # uniform slabs hold; they overflow -> compact, new slabs fit (12); those hold;
+    # sized for the crowd they overflow on the even geometry -> 12; resized, they hold
+    assert [st for st, _ in seq] == [0, 12, 0, 12, 0]
     f_even, f_crowd = seq[0][1], seq[1][1]
     assert np.array_equal(seq[2][1], f_crowd)
     assert np.array_equal(seq[3][1], f_even) and np.array_equal(seq[4][1], f_even)
