@@ -129,7 +129,10 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
  * Re-bin a new geometry of the same n_src into an existing plan, asynchronously
  * (same kernels as asf_plan; no synchronisation, no host tables rebuilt).
  * Domain errors are latched in the device status word: read them with
- * asf_status().  Returns ASF_OK, ASF_EINVAL or ASF_EHIP.
+ * asf_status().  How points are binned (one pass into per-tile slabs, or
+ * counting first for crowded geometries) follows the status last read by
+ * asf_plan or asf_status; the results do not depend on it, only the time.
+ * Returns ASF_OK, ASF_EINVAL or ASF_EHIP.
  */
 int asf_setpts(asf_plan_t plan, const double *x1, const double *y1, const double *d1,
                void *stream);
