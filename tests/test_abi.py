@@ -152,6 +152,14 @@ def test_line_workspace_and_null_pointers(asf):
     assert lib.asf_line_destroy(None) == asf.asf.ASF_EINVAL
 
 
+def test_point_count_limit(asf):
+    # slot indices are 32-bit: 4 n_src slots must stay below 2^32
+    p = asf.make_params(532e-9, 0.2, 8e-6, 8e-6, 64, 64)
+    assert asf.lib().asf_workspace_bytes((1 << 30) - 1, ctypes.byref(p)) > 0
+    assert asf.lib().asf_workspace_bytes(1 << 30, ctypes.byref(p)) == 0
+    assert "n_src" in asf.last_error()
+
+
 def test_width_from_tolerance(asf):
     # w = ceil(log10(1/tol)) + 2, visible through the workspace of a tiny problem only via the
     # plan; here check the documented mapping indirectly: all tolerances in range are accepted
