@@ -105,22 +105,21 @@ struct WaveGroup {
 __device__ inline WaveGroup wave_group(int key, bool active) {
     const int lane = __lane_id();
     uint64_t todo = __ballot(active);
-    WaveGroup g;
-    g.leader = lane;
-    g.rank = 0u;
-    g.size = 0u;
+    uint64_t mine = 0ull;   // the lanes of this lane's group (0 if inactive)
     while (todo) {
         const int leader = __ffsll((unsigned long long)todo) - 1;
         // leader is wave-uniform: read its key with v_readlane, not an LDS permute
         const int lkey = __builtin_amdgcn_readlane(key, leader);
-        const uint64_t mask = __ballot(active && key == lkey) & todo;
-        if ((mask >> lane) & 1ull) {
-            g.leader = leader;
-            g.rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-            if (lane == leader) g.size = (uint32_t)__popcll(mask);
-        }
+        const bool in = active && key == lkey;
+        const uint64_t mask = __ballot(in);
+        if (in) mine = mask;
         todo &= ~mask;
     }
+    // rank: group lanes below this one (v_mbcnt); the leader is the lowest of them
+    WaveGroup g;
+    g.rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mine >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mine, 0u));
+    g.size = (uint32_t)__popcll(mine);
+    g.leader = mine ? __ffsll((unsigned long long)mine) - 1 : lane;
     return g;
 }
 
