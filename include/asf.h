@@ -96,6 +96,10 @@ typedef struct {
     /* byte offsets into the workspace of buffers tests may inspect */
     size_t off_status, off_tile_start, off_cell, off_frac, off_phase, off_perm, off_fine, off_mid;
     size_t ws_bytes;
+    /* per-tile record counts (u32 [ntiles]) and slabs (u32 pairs [ntiles]: first slot,
+       slot count); a tile's records are slab.first .. + min(count, slab.count) unless
+       status bit 2 says the compact layout (tile_start) is in use */
+    size_t off_cursor, off_slab;
 } asf_info;
 
 /*

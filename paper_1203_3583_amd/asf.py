@@ -54,7 +54,8 @@ class Info(ctypes.Structure):
                 ("off_cell", ctypes.c_size_t), ("off_frac", ctypes.c_size_t),
                 ("off_phase", ctypes.c_size_t), ("off_perm", ctypes.c_size_t),
                 ("off_fine", ctypes.c_size_t), ("off_mid", ctypes.c_size_t),
-                ("ws_bytes", ctypes.c_size_t)]
+                ("ws_bytes", ctypes.c_size_t), ("off_cursor", ctypes.c_size_t),
+                ("off_slab", ctypes.c_size_t)]
 
 
 class LineParams(ctypes.Structure):

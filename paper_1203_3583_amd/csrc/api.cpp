@@ -551,6 +551,8 @@ int asf_plan_info(asf_plan_t plan, asf_info *info) {
     info->off_fine = L.off_fine;
     info->off_mid = L.off_mid;
     info->ws_bytes = L.total;
+    info->off_cursor = L.off_cursor;
+    info->off_slab = L.off_slab;
     return ASF_OK;
 }
 

@@ -1,0 +1,204 @@
+"""Stage-by-stage checks of the HIP forward path, each stage against a host FP64
+model fed with the device's own input to that stage:
+
+  a1/a2  binning: every point's first footprint cell (exact), offsets (FP32 of the
+         FP64 value), pre-phase exp(i phi) (FP32 sincos), and the tile bins (exact
+         multiset of (tile, point) pairs, in both the slab and the compact layout);
+  a3     spreading: the fine grid against a direct FP64 sum of the exponential-of-
+         semicircle footprints of the device's records;
+  a4/a5  column pass: the kept modes against numpy's FFT of the device's fine grid;
+  a6     row pass: u2 against numpy's FFT of the device's column-pass output times
+         the deconvolution and destination phase of Eq. (8), tables built here in FP64.
+
+The host models restate the definitions (Eqs. (7)-(9), the kernel and its Fourier
+transform); they share no code with the kernels.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import rel_l2, to_dev, torch_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _even():
+    """128^2 points whose frequencies wrap over the whole fine grid (slab layout)."""
+    rng = np.random.default_rng(21)
+    x, y = synth.jittered_grid(rng, 128, 128, 8e-6, 2e-6)
+    d = synth.sinusoidal_relief(x, y, 20e-6, 0.8e-3)
+    u = synth.random_field(rng, 128, 128).reshape(-1)
+    return synth.Workload("even", x, y, d, u, 532e-9, 0.1, 80e-6, 80e-6, 128, 128)
+
+
+def _crowded():
+    """The C1 relief: points in 15% of each axis' period (compact layout)."""
+    return synth.config("sinusoid_128")
+
+
+def _plan(torch, w, fft="fp32"):
+    import paper_1203_3583_amd as asf
+
+    x, y, d, u = to_dev(torch, w)
+    plan = asf.Plan(x, y, d, w.lam, w.z0, w.p2x, w.p2y, w.mx, w.my, fft=fft)
+    return plan, u
+
+
+def _view(torch, plan, off, count, dtype):
+    return plan.workspace_view(off, count, dtype).cpu().numpy()
+
+
+def _host_points(w, nf_x, nf_y, wid):
+    """First footprint cell, offsets and exp(i phi) per point in FP64 (Eqs. (7)-(9)),
+    in the same operation order as a plain evaluation of the definitions."""
+    s = (1.0 / w.lam) / (w.z0 - w.d)                       # 1 / (lambda r0)
+
+    def axis(xi, nf):
+        fr = xi - np.floor(xi)
+        g = fr * nf
+        g = np.where(g >= nf, g - nf, g)
+        c = np.ceil(g - 0.5 * wid).astype(np.int64)
+        off = g - c - 0.5 * (wid - 1)
+        return np.where(c < 0, c + nf, c), off
+
+    cx, ox = axis(w.p2x * w.x * s, nf_x)
+    cy, oy = axis(w.p2y * w.y * s, nf_y)
+    rev = 0.5 * s * (w.x * w.x + w.y * w.y)                 # plane-wave incidence
+    t = rev - np.rint(rev)
+    return cx, cy, ox, oy, np.exp(2j * np.pi * t)
+
+
+def _host_bins(cx, cy, wid, nf_x, nf_y, tx, ty, ntx):
+    """(tile, point) pairs: a point is listed in every tile its w x w footprint touches."""
+    pairs = []
+    lx = (cx + wid - 1) % nf_x
+    ly = (cy + wid - 1) % nf_y
+    for j in range(cx.size):
+        xs = {cx[j] // tx, lx[j] // tx}
+        ys = {cy[j] // ty, ly[j] // ty}
+        for a in ys:
+            for b in xs:
+                pairs.append((int(a * ntx + b), j))
+    return sorted(pairs)
+
+
+def _device_bins(torch, plan, info):
+    st = int(_view(torch, plan, info["off_status"], 1, torch.int32)[0])
+    T = info["ntiles"]
+    if st & 4:   # compact
+        start = _view(torch, plan, info["off_tile_start"], T + 1, torch.int32).astype(np.int64)
+        ranges = [(start[t], start[t + 1]) for t in range(T)]
+    else:
+        cnt = _view(torch, plan, info["off_cursor"], T, torch.int32).astype(np.int64)
+        slab = _view(torch, plan, info["off_slab"], 2 * T, torch.int32).astype(np.int64).reshape(T, 2)
+        ranges = [(slab[t, 0], slab[t, 0] + min(cnt[t], slab[t, 1])) for t in range(T)]
+    return st, ranges
+
+
+@pytest.mark.parametrize("which", ["even", "crowded"])
+def test_binning_matches_host(which):
+    torch = torch_gpu()
+    w = _even() if which == "even" else _crowded()
+    plan, _ = _plan(torch, w)
+    info = plan.info()
+    nfx, nfy, wid = info["nfx"], info["nfy"], info["w"]
+    tx, ty = info["tile_x"], info["tile_y"]
+    st, ranges = _device_bins(torch, plan, info)
+    cap = info["slot_cap"]
+    cell = _view(torch, plan, info["off_cell"], cap, torch.int32).view(np.uint32)
+    frac = _view(torch, plan, info["off_frac"], 2 * cap, torch.float32).reshape(-1, 2)
+    phase = _view(torch, plan, info["off_phase"], 2 * cap, torch.float32).reshape(-1, 2)
+    perm = _view(torch, plan, info["off_perm"], cap, torch.int32).astype(np.int64)
+    plan.close()
+    assert (st & 4) == (0 if which == "even" else 4)
+
+    cx, cy, ox, oy, ph = _host_points(w, nfx, nfy, wid)
+    got = sorted((t, int(perm[s])) for t, (a, b) in enumerate(ranges) for s in range(a, b))
+    want = _host_bins(cx, cy, wid, nfx, nfy, tx, ty, nfx // tx)
+    assert got == want                                      # exact tile lists
+    slots = np.concatenate([np.arange(a, b) for a, b in ranges])
+    j = perm[slots]
+    assert np.array_equal(cell[slots] & 0xFFFF, cx[j]) and np.array_equal(cell[slots] >> 16, cy[j])
+    assert np.array_equal(frac[slots, 0], ox[j].astype(np.float32))
+    assert np.array_equal(frac[slots, 1], oy[j].astype(np.float32))
+    dev = phase[slots, 0] + 1j * phase[slots, 1]
+    assert np.max(np.abs(dev - ph[j])) <= 4e-7             # FP32 phase (<= 2e-7 rad) and sincos
+
+
+def _psi(z, wid, beta):
+    a = 1.0 - (2.0 * z / wid) ** 2
+    return np.where(a >= 0.0, np.exp(beta * (np.sqrt(np.maximum(a, 0.0)) - 1.0)), 0.0)
+
+
+def _fine_natural(torch, plan, info):
+    nfx, nfy, C = info["nfx"], info["nfy"], info["col_batch"]
+    raw = _view(torch, plan, info["off_fine"], 2 * nfx * nfy, torch.float32)
+    v = (raw[0::2] + 1j * raw[1::2]).astype(np.complex128)
+    # element (gx, gy) at ((gx / C) nfy + gy) C + gx % C -> [gy, gx]
+    return v.reshape(nfx // C, nfy, C).transpose(1, 0, 2).reshape(nfy, nfx)
+
+
+def test_spread_matches_host_sum():
+    torch = torch_gpu()
+    w = _even()
+    plan, u = _plan(torch, w)
+    plan.forward(u)
+    torch.cuda.synchronize()
+    info = plan.info()
+    fine = _fine_natural(torch, plan, info)
+    plan.close()
+    nfx, nfy, wid, beta = info["nfx"], info["nfy"], info["w"], info["beta"]
+    cx, cy, ox, oy, ph = _host_points(w, nfx, nfy, wid)
+    c = w.u.astype(np.complex128) * ph
+    want = np.zeros((nfy, nfx), dtype=np.complex128)
+    a = np.arange(wid)
+    kx = _psi(a[None, :] - 0.5 * (wid - 1) - ox[:, None], wid, beta)   # [n, w]
+    ky = _psi(a[None, :] - 0.5 * (wid - 1) - oy[:, None], wid, beta)
+    ix = (cx[:, None] + a[None, :]) % nfx
+    iy = (cy[:, None] + a[None, :]) % nfy
+    for r in range(wid):
+        for q in range(wid):
+            np.add.at(want, (iy[:, r], ix[:, q]), c * ky[:, r] * kx[:, q])
+    err = rel_l2(fine, want)
+    print(f"spread: rel-L2 {err:.2e}")
+    assert err <= 2e-6
+
+
+def _psi_hat(m, nf, wid, beta):
+    xq, wq = np.polynomial.legendre.leggauss(200)
+    es = np.exp(beta * (np.sqrt(1.0 - xq * xq) - 1.0))
+    return 0.5 * wid * np.sum(wq * es * np.cos(np.pi * np.outer(m, xq) * wid / nf), axis=1)
+
+
+@pytest.mark.parametrize("fft,bar", [("fp32", 2e-6), ("split_fp16", 1e-4)])
+def test_fft_passes_match_numpy(fft, bar):
+    torch = torch_gpu()
+    w = _even()
+    plan, u = _plan(torch, w, fft)
+    u2 = plan.forward(u).cpu().numpy().astype(np.complex128)
+    info = plan.info()
+    fine = _fine_natural(torch, plan, info)
+    nfx, nfy, mx, my, C = info["nfx"], info["nfy"], w.mx, w.my, info["col_batch"]
+    raw = _view(torch, plan, info["off_mid"], 2 * my * nfx, torch.float32)
+    plan.close()
+    mid = (raw[0::2] + 1j * raw[1::2]).astype(np.complex128)
+    mid = mid.reshape(nfx // C, my, C).transpose(1, 0, 2).reshape(my, nfx)   # [ky, x]
+    # column pass: exp(-i) DFT along y of the device's fine grid, modes -my/2 .. my/2 - 1
+    ky = (np.arange(my) - my // 2) % nfy
+    want_mid = np.fft.fft(fine, axis=0)[ky, :]
+    e1 = rel_l2(mid, want_mid)
+    # row pass: DFT along x of the device's mid, times 1/psi-hat, the destination chirp
+    # and exp(i k z0) / (i lambda z0) (Eq. (8))
+    kx = (np.arange(mx) - mx // 2) % nfx
+    spec = np.fft.fft(mid, axis=1)[:, kx]
+    k = 2.0 * np.pi / w.lam
+    m = np.arange(mx) - mx // 2
+    n = np.arange(my) - my // 2
+    X, Y = w.p2x * m, w.p2y * n
+    dx = np.exp(1j * k * X * X / (2.0 * w.z0)) / _psi_hat(np.abs(m), nfx, info["w"], info["beta"])
+    dy = np.exp(1j * k * Y * Y / (2.0 * w.z0)) / _psi_hat(np.abs(n), nfy, info["w"], info["beta"])
+    pre = np.exp(1j * k * w.z0) / (1j * w.lam * w.z0)
+    want_u2 = pre * spec * dy[:, None] * dx[None, :]
+    e2 = rel_l2(u2, want_u2)
+    print(f"{fft}: column pass {e1:.2e}, row pass {e2:.2e}")
+    assert e1 <= bar and e2 <= bar
