@@ -159,7 +159,28 @@ __global__ __launch_bounds__(kLineFwdThreads) void line_forward_kernel(LineGeo g
     const int nf = g.nf, w = g.w, lg = g.log_nf;
     float2 *vs = line + nf;
     if constexpr (STAGED) {
-        for (int j = threadIdx.x; j < g.n; j += kLineFwdThreads) vs[j] = u[b.perm[j]];
+        // four points per thread at a time: their index loads, then their gathers,
+        // go out together
+        constexpr int B = 4;
+        for (int j0 = threadIdx.x; j0 < g.n; j0 += B * kLineFwdThreads) {
+            uint32_t pj[B];
+            float2 v[B];
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                const int j = j0 + q * kLineFwdThreads;
+                pj[q] = j < g.n ? b.perm[j] : 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                const int j = j0 + q * kLineFwdThreads;
+                v[q] = j < g.n ? u[pj[q]] : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                const int j = j0 + q * kLineFwdThreads;
+                if (j < g.n) vs[j] = v[q];
+            }
+        }
         __syncthreads();
     }
 
