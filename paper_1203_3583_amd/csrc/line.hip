@@ -134,10 +134,11 @@ __device__ inline float2 cmul(float2 a, float2 b) {
 // cell qq and cover it) of coef(j, qq - cell_j) times the field at j.
 template <bool STAGED>
 __device__ __forceinline__ void gather_cell(const LineBins &b, int w, const float2 *__restrict__ u,
-                                            const float2 *vs, uint32_t j0, uint32_t j1, int qq,
-                                            float &ar, float &ai) {
+                                            const float2 *vs, const uint32_t *cs, uint32_t j0, uint32_t j1,
+                                            int qq, float &ar, float &ai) {
     for (uint32_t j = j0; j < j1; ++j) {
-        const float2 k = b.coef[(size_t)j * w + (qq - (int)b.cell[j])];
+        const uint32_t c = STAGED ? cs[j] : b.cell[j];
+        const float2 k = b.coef[(size_t)j * w + (qq - (int)c)];
         const float2 v = STAGED ? vs[j] : u[b.perm[j]];
         ar = __builtin_fmaf(k.x, v.x, ar);
         ar = __builtin_fmaf(-k.y, v.y, ar);
@@ -154,10 +155,14 @@ __global__ __launch_bounds__(kLineFwdThreads) void line_forward_kernel(LineGeo g
                                                                         const float2 *__restrict__ dd,
                                                                         const float2 *__restrict__ u1,
                                                                         float2 *__restrict__ u2) {
-    extern __shared__ float2 line[];   // nf cells, then (STAGED) the n field values
+    // nf cells, then (STAGED) the n field values, the n first cells and the nf + 1
+    // run starts
+    extern __shared__ float2 line[];
     const float2 *u = u1 + (size_t)blockIdx.x * g.n;
     const int nf = g.nf, w = g.w, lg = g.log_nf;
     float2 *vs = line + nf;
+    uint32_t *cs = reinterpret_cast<uint32_t *>(vs + g.n);
+    uint32_t *fs = cs + g.n;
     if constexpr (STAGED) {
         // four points per thread at a time: their index loads, then their gathers,
         // go out together
@@ -181,6 +186,8 @@ __global__ __launch_bounds__(kLineFwdThreads) void line_forward_kernel(LineGeo g
                 if (j < g.n) vs[j] = v[q];
             }
         }
+        for (int j = threadIdx.x; j < g.n; j += kLineFwdThreads) cs[j] = b.cell[j];
+        for (int q = threadIdx.x; q <= nf; q += kLineFwdThreads) fs[q] = b.first[q];
         __syncthreads();
     }
 
@@ -190,12 +197,13 @@ __global__ __launch_bounds__(kLineFwdThreads) void line_forward_kernel(LineGeo g
     for (int q = threadIdx.x; q < nf; q += kLineFwdThreads) {
         float ar = 0.f, ai = 0.f;
         const int lo = q - w + 1;
-        const uint32_t jq = b.first[q + 1];
+        const uint32_t *first = STAGED ? fs : b.first;
+        const uint32_t jq = first[q + 1];
         if (lo >= 0) {
-            gather_cell<STAGED>(b, w, u, vs, b.first[lo], jq, q, ar, ai);
+            gather_cell<STAGED>(b, w, u, vs, cs, first[lo], jq, q, ar, ai);
         } else {
-            gather_cell<STAGED>(b, w, u, vs, b.first[lo + nf], (uint32_t)g.n, q + nf, ar, ai);
-            gather_cell<STAGED>(b, w, u, vs, b.first[0], jq, q, ar, ai);
+            gather_cell<STAGED>(b, w, u, vs, cs, first[lo + nf], (uint32_t)g.n, q + nf, ar, ai);
+            gather_cell<STAGED>(b, w, u, vs, cs, first[0], jq, q, ar, ai);
         }
         line[__brev((unsigned)q) >> (32 - lg)] = make_float2(ar, ai);
     }
@@ -257,9 +265,11 @@ hipError_t launch_line_forward(const LineGeo &g, const LineBins &b, const float2
                                int batch, const float2 *u1, float2 *u2, hipStream_t s) {
     if (batch < 1 || g.nf < 2 || g.nf > (1 << kLineKeyBits) || (1 << g.log_nf) != g.nf)
         return hipErrorInvalidValue;
-    // stage the field in LDS when line and field together stay within 64 KB
+    // stage the field, the first cells and the run starts in LDS when they and the
+    // line together stay within 64 KB
     const size_t line_bytes = sizeof(float2) * (size_t)g.nf;
-    const size_t staged_bytes = line_bytes + sizeof(float2) * (size_t)g.n;
+    const size_t staged_bytes = line_bytes + (sizeof(float2) + sizeof(uint32_t)) * (size_t)g.n +
+                                sizeof(uint32_t) * ((size_t)g.nf + 1);
     if (staged_bytes <= 65536) {
         hipLaunchKernelGGL(line_forward_kernel<true>, dim3(batch), dim3(kLineFwdThreads), staged_bytes, s,
                            g, b, tw, dd, u1, u2);
