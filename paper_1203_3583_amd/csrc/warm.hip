@@ -261,8 +261,7 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
     float *__restrict__ dbias, int B, int H, int W, int cin, int cout, int chunk) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t npix = (int64_t)B * H * W;
-    const int64_t pc = ((int64_t)blockIdx.x * 4 + wave) * chunk;
-    if (pc >= npix) return;
+    const int64_t pc = ((int64_t)blockIdx.x * 4 + wave) * chunk;   // past npix: an empty chunk
     const int kgroups = 9 * cin / (16 * kKB);
     const int kg = blockIdx.y % kgroups, cb2 = blockIdx.y / kgroups;
     int tap[kKB], c0[kKB], dy[kKB], dx[kKB];
@@ -327,26 +326,35 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
             }
         }
     }
-    // accumulator rows are output channels 4 g + i, column k = c0 + r of the block's tap
-    const int kin = 9 * cin;
+    // the four waves' blocks are summed in LDS, then one set of atomics per workgroup
+    // (a quarter of the dw atomics of one set per wave)
+    __shared__ float red[4][kKB * 8 + 2][64];
 #pragma unroll
     for (int q = 0; q < kKB; ++q)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            atomicAdd(&dw[(size_t)(co0 + g * 4 + i) * kin + tap[q] * cin + c0[q] + r], acc[q][0][i]);
-            atomicAdd(&dw[(size_t)(co0 + 16 + g * 4 + i) * kin + tap[q] * cin + c0[q] + r], acc[q][1][i]);
+            red[wave][q * 8 + i][lane] = acc[q][0][i];
+            red[wave][q * 8 + 4 + i][lane] = acc[q][1][i];
         }
-    if (dbias && kg == 0) {
-        // bias gradient from the same dout values (FP32, not rounded): sum the four
-        // pixel groups of each output channel
-        bsum0 += __shfl_xor(bsum0, 16);
-        bsum0 += __shfl_xor(bsum0, 32);
-        bsum1 += __shfl_xor(bsum1, 16);
-        bsum1 += __shfl_xor(bsum1, 32);
-        if (g == 0) {
-            atomicAdd(&dbias[co0 + r], bsum0);
-            atomicAdd(&dbias[co0 + 16 + r], bsum1);
-        }
+    red[wave][kKB * 8][lane] = bsum0;
+    red[wave][kKB * 8 + 1][lane] = bsum1;
+    __syncthreads();
+    // accumulator rows are output channels 4 g + i, column k = c0 + r of the block's tap;
+    // thread t sums entry (v, l) = (t / 64 + 4 m, t % 64) over the waves
+    const int kin = 9 * cin;
+    for (int v = wave; v < kKB * 8; v += 4) {
+        const float sum = red[0][v][lane] + red[1][v][lane] + red[2][v][lane] + red[3][v][lane];
+        const int q = v >> 3, cb = (v >> 2) & 1, i = v & 3;
+        atomicAdd(&dw[(size_t)(co0 + cb * 16 + g * 4 + i) * kin + tap[q] * cin + c0[q] + r], sum);
+    }
+    if (dbias && kg == 0 && wave < 2) {
+        // bias gradient from the same dout values (FP32, not rounded): sum the waves,
+        // then the four pixel groups of each output channel
+        const int v = kKB * 8 + wave;
+        float bs = red[0][v][lane] + red[1][v][lane] + red[2][v][lane] + red[3][v][lane];
+        bs += __shfl_xor(bs, 16);
+        bs += __shfl_xor(bs, 32);
+        if (g == 0) atomicAdd(&dbias[co0 + wave * 16 + r], bs);
     }
 }
 
