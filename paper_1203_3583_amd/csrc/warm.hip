@@ -226,9 +226,9 @@ __global__ __launch_bounds__(256) void conv3x3_tiled_kernel(
 // consecutive input channels of one tap; a wave takes kKB such blocks, which
 // share its dout loads.  Short chunks give the deep, small layers enough waves;
 // two 16-pixel steps per iteration keep their loads in flight together.
-// pixels per wave: longer chunks mean fewer dw atomics, shorter ones more waves;
-// layers of at least 2^16 pixels take 512 (a 512^2 layer, 96 -> 32 channels:
-// 0.353 -> 0.254 ms), smaller ones 256 (64^2, 128 -> 256: 0.046 against 0.059 ms)
+// pixels per wave: longer chunks mean fewer dw atomics, shorter ones more waves
+// (a 512^2 layer, 96 -> 32 channels: 0.198 ms with 512, 0.261 with 256; 512^2,
+// 16 -> 32: 0.047 ms with 256, 0.062 with 512)
 constexpr int kWgradChunkSmall = 256;
 constexpr int kWgradChunkLarge = 512;
 constexpr int kMaxWgradPix = 1 << 22;   // B H W below this: pixel coordinates by float division
@@ -500,7 +500,10 @@ int asf_warm_conv3x3_wgrad(const float *in, const float *dout, float *dw, float 
         return -1;
     const int64_t npix = (int64_t)B * H * W;
     if (npix >= kMaxWgradPix) return -1;
-    const int chunk = npix >= (1 << 16) ? kWgradChunkLarge : kWgradChunkSmall;
+    // the longer chunk where it still leaves at least 1024 workgroups
+    const int64_t kgroups = 9 * cin / (16 * kKB);
+    const int64_t wg_large = (npix + 4 * kWgradChunkLarge - 1) / (4 * kWgradChunkLarge) * (cout / 32) * kgroups;
+    const int chunk = wg_large >= 1024 ? kWgradChunkLarge : kWgradChunkSmall;
     const int64_t chunks = (npix + chunk - 1) / chunk;
     const dim3 grid((unsigned)((chunks + 3) / 4), (unsigned)((cout / 32) * (9 * cin / (16 * kKB))));
     hipLaunchKernelGGL(conv3x3_wgrad_kernel, grid, dim3(256), 0, static_cast<hipStream_t>(stream), in, dout, dw,
