@@ -80,6 +80,33 @@ def test_tolerance_sets_width(tol, bar):
     assert err <= bar
 
 
+@pytest.mark.parametrize("fft", ["fp32", "split_fp16"])
+def test_flat_grid_is_a_centred_dft(fft):
+    """d1 = 0 on a regular grid with p2 = lambda z0 / (N p1): the sum of Eq. (7) is a
+    centred 2D DFT between the chirps (a closed form independent of the oracle)."""
+    torch = torch_gpu()
+    N, lam, z0, p1 = 64, 532e-9, 0.1, 8e-6
+    p2 = lam * z0 / (N * p1)
+    idx = np.arange(N) - N // 2
+    yy, xx = np.meshgrid(idx * p1, idx * p1, indexing="ij")
+    x, y = xx.reshape(-1), yy.reshape(-1)
+    d = np.zeros_like(x)
+    rng = np.random.default_rng(5)
+    u = (rng.standard_normal(N * N) + 1j * rng.standard_normal(N * N)).astype(np.complex64)
+    w = synth.Workload("flat", x, y, d, u, lam, z0, p2, p2, N, N)
+    got, _ = gpu_forward(w, fft)
+    k = 2.0 * np.pi / lam
+    c = u.astype(np.complex128).reshape(N, N) * np.exp(1j * k * (yy ** 2 + xx ** 2) / (2.0 * z0))
+    F = np.exp(-2j * np.pi * np.outer(idx, idx) / N)          # [m, i]: exp(-2 pi i m i / N)
+    S = F @ c @ F.T                                            # rows: Y modes, columns: X modes
+    X = p2 * idx
+    chirp = np.exp(1j * k * (X[:, None] ** 2 + X[None, :] ** 2) / (2.0 * z0))
+    want = np.exp(1j * k * z0) / (1j * lam * z0) * chirp * S
+    err = rel_l2(got, want)
+    print(f"flat grid {fft}: {err:.2e}")
+    assert err <= TOL[fft]
+
+
 def test_single_point():
     w = _custom(1, 1, 8e-6, 3e-6, 32, 32, 8e-6, 8e-6)
     got, _ = gpu_forward(w)
