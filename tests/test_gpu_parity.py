@@ -80,30 +80,35 @@ def test_tolerance_sets_width(tol, bar):
     assert err <= bar
 
 
-@pytest.mark.parametrize("fft", ["fp32", "split_fp16"])
-def test_flat_grid_is_a_centred_dft(fft):
-    """d1 = 0 on a regular grid with p2 = lambda z0 / (N p1): the sum of Eq. (7) is a
-    centred 2D DFT between the chirps (a closed form independent of the oracle)."""
+@pytest.mark.parametrize("fft,d0,incident", [("fp32", 0.0, "plane"), ("split_fp16", 0.0, "plane"),
+                                             ("fp32", 12e-6, "none")])
+def test_flat_grid_is_a_centred_dft(fft, d0, incident):
+    """A flat surface (d1 = d0) on a regular grid with p2 = lambda r0 / (N p1), r0 = z0 - d0:
+    the sum of Eq. (7) is a centred 2D DFT between the chirps (a closed form independent
+    of the oracle); without the incident plane wave the constant phase exp(-i k d0) stays."""
     torch = torch_gpu()
     N, lam, z0, p1 = 64, 532e-9, 0.1, 8e-6
-    p2 = lam * z0 / (N * p1)
+    r0 = z0 - d0
+    p2 = lam * r0 / (N * p1)
     idx = np.arange(N) - N // 2
     yy, xx = np.meshgrid(idx * p1, idx * p1, indexing="ij")
     x, y = xx.reshape(-1), yy.reshape(-1)
-    d = np.zeros_like(x)
+    d = np.full_like(x, d0)
     rng = np.random.default_rng(5)
     u = (rng.standard_normal(N * N) + 1j * rng.standard_normal(N * N)).astype(np.complex64)
-    w = synth.Workload("flat", x, y, d, u, lam, z0, p2, p2, N, N)
+    w = synth.Workload("flat", x, y, d, u, lam, z0, p2, p2, N, N, incident=incident)
     got, _ = gpu_forward(w, fft)
     k = 2.0 * np.pi / lam
-    c = u.astype(np.complex128).reshape(N, N) * np.exp(1j * k * (yy ** 2 + xx ** 2) / (2.0 * z0))
+    c = u.astype(np.complex128).reshape(N, N) * np.exp(1j * k * (yy ** 2 + xx ** 2) / (2.0 * r0))
+    if incident == "none":
+        c = c * np.exp(-1j * k * d0)
     F = np.exp(-2j * np.pi * np.outer(idx, idx) / N)          # [m, i]: exp(-2 pi i m i / N)
     S = F @ c @ F.T                                            # rows: Y modes, columns: X modes
     X = p2 * idx
     chirp = np.exp(1j * k * (X[:, None] ** 2 + X[None, :] ** 2) / (2.0 * z0))
     want = np.exp(1j * k * z0) / (1j * lam * z0) * chirp * S
     err = rel_l2(got, want)
-    print(f"flat grid {fft}: {err:.2e}")
+    print(f"flat grid {fft} d0={d0} {incident}: {err:.2e}")
     assert err <= TOL[fft]
 
 
