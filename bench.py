@@ -182,6 +182,18 @@ WORKLOADS = {
 }
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux), for the CPU baseline's record."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def copy_bandwidth(torch, dev, nbytes=256 << 20, reps=20):
     """Achievable HBM bandwidth: a plain device-to-device copy of nbytes, counted as
     read plus write bytes per second (GB/s), timed with HIP events."""
@@ -355,6 +367,7 @@ def main():
             "value": n / t_full,
             "unit": "NU points/s",
             "cores": oracle.threads(threads),
+            "cpu": cpu_model(),
             "kind": "oracle",
             "sample": f"{len(ix)} random destination pixels of the {w.mx}x{w.my} grid, each a direct FP64 "
                       f"sum over all {n} points ({t_cpu:.1f} s), extrapolated to the full grid",
