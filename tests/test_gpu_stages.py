@@ -8,7 +8,8 @@ model fed with the device's own input to that stage:
          semicircle footprints of the device's records;
   a4/a5  column pass: the kept modes against numpy's FFT of the device's fine grid;
   a6     row pass: u2 against numpy's FFT of the device's column-pass output times
-         the deconvolution and destination phase of Eq. (8), tables built here in FP64.
+         the deconvolution and destination phase of Eq. (8), tables built here in FP64;
+  adjoint: its row pass, column pass and interpolation, each the same way.
 
 The host models restate the definitions (Eqs. (7)-(9), the kernel and its Fourier
 transform); they share no code with the kernels.
@@ -202,3 +203,55 @@ def test_fft_passes_match_numpy(fft, bar):
     e2 = rel_l2(u2, want_u2)
     print(f"{fft}: column pass {e1:.2e}, row pass {e2:.2e}")
     assert e1 <= bar and e2 <= bar
+
+
+@pytest.mark.parametrize("fft,bar", [("fp32", 2e-6), ("split_fp16", 1e-4)])
+def test_adjoint_stages_match_host(fft, bar):
+    """The adjoint's three stages, each from the device's own input to it: the row pass
+    (g2 times conj(Dx Dy), zero-padded, exp(+i) DFT), the column pass (exp(+i) DFT of the
+    kept rows) and the interpolation (conj(exp(i phi)) times the footprint sum)."""
+    torch = torch_gpu()
+    w = _even()
+    plan, u = _plan(torch, w, fft)
+    info = plan.info()
+    nfx, nfy, mx, my, C = info["nfx"], info["nfy"], w.mx, w.my, info["col_batch"]
+    wid, beta = info["w"], info["beta"]
+    rng = np.random.default_rng(8)
+    g2 = torch.from_numpy(synth.random_field(rng, mx, my).reshape(my, mx)).cuda()
+    g1 = plan.adjoint(g2).cpu().numpy().astype(np.complex128)
+    torch.cuda.synchronize()
+    raw = _view(torch, plan, info["off_mid"], 2 * my * nfx, torch.float32)
+    mid = (raw[0::2] + 1j * raw[1::2]).astype(np.complex128).reshape(my, nfx)   # row-major
+    fine = _fine_natural(torch, plan, info)
+    plan.close()
+    k = 2.0 * np.pi / w.lam
+    m = np.arange(mx) - mx // 2
+    n = np.arange(my) - my // 2
+    X, Y = w.p2x * m, w.p2y * n
+    dx = np.exp(1j * k * X * X / (2.0 * w.z0)) / _psi_hat(np.abs(m), nfx, wid, beta)
+    dy = np.exp(1j * k * Y * Y / (2.0 * w.z0)) / _psi_hat(np.abs(n), nfy, wid, beta)
+    pre = np.exp(1j * k * w.z0) / (1j * w.lam * w.z0)
+    g = g2.cpu().numpy().astype(np.complex128) * np.conj(pre * dy[:, None] * dx[None, :])
+    pad = np.zeros((my, nfx), dtype=np.complex128)
+    pad[:, m % nfx] = g
+    want_mid = np.fft.ifft(pad, axis=1) * nfx                 # exp(+i), unnormalised
+    e1 = rel_l2(mid, want_mid)
+    padc = np.zeros((nfy, nfx), dtype=np.complex128)
+    padc[n % nfy, :] = mid
+    want_fine = np.fft.ifft(padc, axis=0) * nfy
+    e2 = rel_l2(fine, want_fine)
+    # interpolation from the device's fine grid, exact kernel values
+    cx, cy, ox, oy, ph = _host_points(w, nfx, nfy, wid)
+    a = np.arange(wid)
+    kx = _psi(a[None, :] - 0.5 * (wid - 1) - ox[:, None], wid, beta)
+    ky = _psi(a[None, :] - 0.5 * (wid - 1) - oy[:, None], wid, beta)
+    ix = (cx[:, None] + a[None, :]) % nfx
+    iy = (cy[:, None] + a[None, :]) % nfy
+    acc = np.zeros(w.n, dtype=np.complex128)
+    for r in range(wid):
+        for q in range(wid):
+            acc += fine[iy[:, r], ix[:, q]] * ky[:, r] * kx[:, q]
+    want_g1 = np.conj(ph) * acc
+    e3 = rel_l2(g1, want_g1)
+    print(f"adjoint {fft}: rows {e1:.2e}, columns {e2:.2e}, interpolation {e3:.2e}")
+    assert e1 <= bar and e2 <= bar and e3 <= 2e-6
