@@ -139,9 +139,23 @@ def _fine_natural(torch, plan, info):
     return v.reshape(nfx // C, nfy, C).transpose(1, 0, 2).reshape(nfy, nfx)
 
 
-def test_spread_matches_host_sum():
+def _hot():
+    """5000 points on a 64 x 64 grid: few tiles, each holding thousands of records."""
+    rng = np.random.default_rng(9)
+    n = 5000
+    x = rng.uniform(-4e-6, 4e-6, n)
+    y = rng.uniform(-4e-6, 4e-6, n)
+    d = rng.uniform(0, 10e-6, n)
+    u = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
+    return synth.Workload("hot", x, y, d, u, 532e-9, 0.1, 8e-6, 8e-6, 64, 64)
+
+
+@pytest.mark.parametrize("which", ["even", "crowded", "hot"])
+def test_spread_matches_host_sum(which):
+    """Even points (slab layout), the crowded relief (compact layout) and a small grid
+    whose tiles hold thousands of records (start histogram, record reloads)."""
     torch = torch_gpu()
-    w = _even()
+    w = {"even": _even, "crowded": _crowded, "hot": _hot}[which]()
     plan, u = _plan(torch, w)
     plan.forward(u)
     torch.cuda.synchronize()
@@ -150,7 +164,7 @@ def test_spread_matches_host_sum():
     plan.close()
     nfx, nfy, wid, beta = info["nfx"], info["nfy"], info["w"], info["beta"]
     cx, cy, ox, oy, ph = _host_points(w, nfx, nfy, wid)
-    c = w.u.astype(np.complex128) * ph
+    c = w.u.astype(np.complex128).reshape(-1) * ph
     want = np.zeros((nfy, nfx), dtype=np.complex128)
     a = np.arange(wid)
     kx = _psi(a[None, :] - 0.5 * (wid - 1) - ox[:, None], wid, beta)   # [n, w]
@@ -161,7 +175,7 @@ def test_spread_matches_host_sum():
         for q in range(wid):
             np.add.at(want, (iy[:, r], ix[:, q]), c * ky[:, r] * kx[:, q])
     err = rel_l2(fine, want)
-    print(f"spread: rel-L2 {err:.2e}")
+    print(f"spread {which}: rel-L2 {err:.2e}")
     assert err <= 2e-6
 
 
