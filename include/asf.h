@@ -93,7 +93,9 @@ typedef struct {
     int32_t col_batch;    /* panel width C of the fine grid and FFT intermediate (adjacent columns
                              stored together; columns per workgroup in the first FFT pass) */
     uint32_t flags;
-    /* byte offsets into the workspace of buffers tests may inspect */
+    /* byte offsets into the workspace of buffers tests may inspect (off_status and
+     * off_cursor: the copy of the counters the latest binning used; two binnings
+     * in a row use alternate copies) */
     size_t off_status, off_tile_start, off_cell, off_frac, off_phase, off_perm, off_fine, off_mid;
     size_t ws_bytes;
     /* per-tile record counts (u32 [ntiles]) and slabs (u32 pairs [ntiles]: first slot,

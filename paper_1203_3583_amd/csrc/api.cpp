@@ -64,6 +64,7 @@ struct Layout {
     double beta;
     int64_t slot_cap;
     size_t off_status, off_tile_start, off_cursor, off_slab, off_cell, off_frac, off_phase, off_perm;
+    size_t off_status2, off_cursor2;   // the counters' second copy
     size_t off_fine, off_mid, off_dx, off_dy, off_twx, off_twy, off_w16, total;
 };
 
@@ -113,8 +114,10 @@ int make_layout(int64_t n, const asf_params *p, Layout &L) {
         return at;
     };
     L.off_status = take(kAlign);
+    L.off_status2 = take(kAlign);
     L.off_tile_start = take(sizeof(uint32_t) * (L.ntiles + 1));
     L.off_cursor = take(sizeof(uint32_t) * L.ntiles);
+    L.off_cursor2 = take(sizeof(uint32_t) * L.ntiles);
     L.off_slab = take(sizeof(uint2) * L.ntiles);
     L.off_cell = take(sizeof(uint32_t) * L.slot_cap);
     L.off_frac = take(sizeof(float2) * L.slot_cap);
@@ -211,6 +214,8 @@ struct asf_plan_s {
     int timing;
     bool count_first;   // bin with the compact layout directly (crowded last time)
     bool sized_slabs;   // the slabs were sized from a crowded binning's counts
+    int copy;           // which copy of status and cursor the last binning used
+    bool clear_both;    // clear both copies first (new plan, or a failed binning launch)
     bool events;
     hipEvent_t ev[2 * asf::NSTAGES];
     bool recorded[asf::NSTAGES];
@@ -246,12 +251,25 @@ struct StageMark {
     }
 };
 
-int run_geometry(asf_plan_s *p, const double *x, const double *y, const double *d, hipStream_t s) {
+// Point bin.status and bin.cursor at copy p->copy of the counters, and the
+// next_ pointers at the other copy.
+void bind_counters(asf_plan_s *p) {
+    const Layout &L = p->lay;
+    const size_t st[2] = {L.off_status, L.off_status2}, cu[2] = {L.off_cursor, L.off_cursor2};
+    p->bin.status = reinterpret_cast<uint32_t *>(p->ws + st[p->copy]);
+    p->bin.cursor = reinterpret_cast<uint32_t *>(p->ws + cu[p->copy]);
+    p->bin.next_status = reinterpret_cast<uint32_t *>(p->ws + st[p->copy ^ 1]);
+    p->bin.next_cursor = reinterpret_cast<uint32_t *>(p->ws + cu[p->copy ^ 1]);
+}
+
+int geometry_launches(asf_plan_s *p, const double *x, const double *y, const double *d, hipStream_t s) {
     hipError_t e;
     {
         StageMark m(p, asf::STAGE_BIN, s);
-        e = asf::launch_bin_reset(p->bin, p->lay.ntiles, s);
-        if (e != hipSuccess) return hip_fail(e, "bin_reset launch");
+        if (p->clear_both) {
+            e = asf::launch_bin_reset(p->bin, p->lay.ntiles, s);
+            if (e != hipSuccess) return hip_fail(e, "bin_reset launch");
+        }
         if (p->count_first) {
             e = asf::launch_bin_count(p->geo, p->bin, p->lay.n, x, y, d, s);
             if (e != hipSuccess) return hip_fail(e, "bin_count launch");
@@ -268,10 +286,19 @@ int run_geometry(asf_plan_s *p, const double *x, const double *y, const double *
     }
     {
         StageMark m(p, asf::STAGE_SCATTER, s);
-        e = asf::launch_bin_scatter(p->geo, p->bin, p->lay.n, x, y, d, s);
+        e = asf::launch_bin_scatter(p->geo, p->bin, p->lay.n, p->lay.ntiles, x, y, d, s);
         if (e != hipSuccess) return hip_fail(e, "bin_scatter launch");
     }
     return ASF_OK;
+}
+
+// One binning, into the counters the previous binning's second pass cleared.
+int run_geometry(asf_plan_s *p, const double *x, const double *y, const double *d, hipStream_t s) {
+    p->copy ^= 1;
+    bind_counters(p);
+    const int rc = geometry_launches(p, x, y, d, s);
+    p->clear_both = rc != ASF_OK;
+    return rc;
 }
 
 int upload_tables(asf_plan_s *p, hipStream_t s) {
@@ -377,9 +404,10 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
     pl->prm = *p;
     pl->ws = static_cast<char *>(workspace);
     char *w = pl->ws;
-    pl->bin.status = reinterpret_cast<uint32_t *>(w + L.off_status);
+    pl->copy = 1;   // the first binning takes copy 0
+    pl->clear_both = true;
+    bind_counters(pl);
     pl->bin.tile_start = reinterpret_cast<uint32_t *>(w + L.off_tile_start);
-    pl->bin.cursor = reinterpret_cast<uint32_t *>(w + L.off_cursor);
     pl->bin.cell = reinterpret_cast<uint32_t *>(w + L.off_cell);
     pl->bin.frac = reinterpret_cast<float2 *>(w + L.off_frac);
     pl->bin.phase = reinterpret_cast<float2 *>(w + L.off_phase);
@@ -542,7 +570,7 @@ int asf_plan_info(asf_plan_t plan, asf_info *info) {
     info->slot_cap = L.slot_cap;
     info->col_batch = plan->sh1.batch;
     info->flags = plan->prm.flags;
-    info->off_status = L.off_status;
+    info->off_status = plan->copy ? L.off_status2 : L.off_status;
     info->off_tile_start = L.off_tile_start;
     info->off_cell = L.off_cell;
     info->off_frac = L.off_frac;
@@ -551,7 +579,7 @@ int asf_plan_info(asf_plan_t plan, asf_info *info) {
     info->off_fine = L.off_fine;
     info->off_mid = L.off_mid;
     info->ws_bytes = L.total;
-    info->off_cursor = L.off_cursor;
+    info->off_cursor = plan->copy ? L.off_cursor2 : L.off_cursor;
     info->off_slab = L.off_slab;
     return ASF_OK;
 }

@@ -26,6 +26,10 @@ struct Binned {
     float2 *phase;         // [slot_cap] exp(i phi_j), the pre-phase of Eq. (8)
     uint32_t *perm;        // [slot_cap] index j of the point in the caller's order
     uint32_t slot_cap;     // slots in the arrays above (4 n_src)
+    // the other copy of status and cursor, which the next binning uses: the last
+    // binning pass clears it, so that a binning needs no clearing launch of its own
+    uint32_t *next_status;
+    uint32_t *next_cursor;
 };
 
 constexpr uint32_t kStatusDomain = 1u;    // some point has r0 <= 0 or a non-finite coordinate
@@ -110,6 +114,7 @@ enum {
 };
 
 // ---- launchers (one per kernel family) ---------------------------------------
+// clears both copies of status and cursor
 hipError_t launch_bin_reset(const Binned &b, int ntiles, hipStream_t s);
 // binning: the slab pass (bin_fill) or the count of the compact layout
 // (bin_count), then the compact layout's scan and second pass, which return at
@@ -120,7 +125,8 @@ hipError_t launch_bin_count(const GeoParams &g, const Binned &b, int64_t n, cons
 hipError_t launch_bin_fill(const GeoParams &g, const Binned &b, int64_t n, const double *x,
                            const double *y, const double *d, bool crowded, hipStream_t s);
 hipError_t launch_bin_scan(const Binned &b, int ntiles, hipStream_t s);
-hipError_t launch_bin_scatter(const GeoParams &g, const Binned &b, int64_t n, const double *x,
+// (and, in every launch, clears next_status and next_cursor)
+hipError_t launch_bin_scatter(const GeoParams &g, const Binned &b, int64_t n, int ntiles, const double *x,
                               const double *y, const double *d, hipStream_t s);
 hipError_t launch_spread(const SpreadParams &p, const Binned &b, const float2 *u1, float2 *fine,
                          hipStream_t s);

@@ -34,7 +34,9 @@
 // the counts (a quarter and 16 slots of headroom each) for the next binning; a
 // plan whose last synchronised binning needed the compact layout bins into
 // those if they fit, and otherwise counts first (a lighter pass than a slab
-// pass it would waste).  Slot reservation aggregates per wavefront: the lanes
+// pass it would waste).  The status word and the cursors exist twice: a
+// binning uses one copy while its second pass clears the other for the next
+// binning, so no launch of its own clears the counters.  Slot reservation aggregates per wavefront: the lanes
 // are grouped by tile without memory traffic, then one lane per group issues
 // the atomic -- all groups' atomics in the same instruction, so a wave waits for
 // one round trip rather than one per tile.
@@ -123,10 +125,11 @@ __device__ inline WaveGroup wave_group(int key, bool active) {
     return g;
 }
 
+// Both copies of the counters (at plan creation, and after a failed launch)
 __global__ void __launch_bounds__(256) bin_reset_kernel(Binned b, int ntiles) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < ntiles) b.cursor[i] = 0u;
-    if (i == 0) b.status[0] = 0u;
+    if (i < ntiles) b.cursor[i] = b.next_cursor[i] = 0u;
+    if (i == 0) b.status[0] = b.next_status[0] = 0u;
 }
 
 constexpr int kGeoThreads = 256;
@@ -363,10 +366,15 @@ __global__ void __launch_bounds__(kScanThreads) bin_scan_kernel(Binned b, int nt
 }
 
 // Compact layout, second pass: bin every point again into the scanned layout.
+// Every launch first clears the next binning's counters.
 __global__ void __launch_bounds__(kGeoThreads) bin_scatter_kernel(GeoParams g, Binned b, int64_t n,
+                                                                  int ntiles,
                                                                   const double *__restrict__ x,
                                                                   const double *__restrict__ y,
                                                                   const double *__restrict__ d) {
+    for (int i = blockIdx.x * kGeoThreads + threadIdx.x; i < ntiles; i += gridDim.x * kGeoThreads)
+        b.next_cursor[i] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) b.next_status[0] = 0u;
     if (!(b.status[0] & kStatusCompact)) return;   // every slab held its tile
     const int64_t per = (int64_t)kGeoThreads * kBinPoints;
     const int64_t nblk = (n + per - 1) / per;
@@ -407,12 +415,12 @@ hipError_t launch_bin_scan(const Binned &b, int ntiles, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_bin_scatter(const GeoParams &g, const Binned &b, int64_t n, const double *x,
+hipError_t launch_bin_scatter(const GeoParams &g, const Binned &b, int64_t n, int ntiles, const double *x,
                               const double *y, const double *d, hipStream_t s) {
     const int64_t per = (int64_t)kGeoThreads * kBinPoints;
     const int64_t blocks = (n + per - 1) / per;
     const int grid = (int)(blocks < kFallbackBlocks ? blocks : kFallbackBlocks);
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3(grid), dim3(kGeoThreads), 0, s, g, b, n, x, y, d);
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3(grid), dim3(kGeoThreads), 0, s, g, b, n, ntiles, x, y, d);
     return hipGetLastError();
 }
 

@@ -136,13 +136,16 @@ def test_hot_tile_all_points_in_one_cell_block():
 
     xd, yd, dd, ud = to_dev(torch, w)
     plan = asf.Plan(xd, yd, dd, w.lam, w.z0, w.p2x, w.p2y, w.mx, w.my)
-    status = plan.workspace_view(plan.info()["off_status"], 1, torch.int32)
+
+    def status():   # the counters' copy of the latest binning
+        return int(plan.workspace_view(plan.info()["off_status"], 1, torch.int32).item())
+
     first = plan.forward(ud).cpu().numpy()
-    st0 = int(status.item())
+    st0 = status()
     plan.setpts(xd, yd, dd)
     plan.status()
     again = plan.forward(ud).cpu().numpy()
-    st1 = int(status.item())
+    st1 = status()
     plan.close()
     assert st0 == 4 and st1 == 4
     assert np.array_equal(first, again)
@@ -173,17 +176,21 @@ def test_binning_layout_switches_with_crowding():
     xc, yc, dc, _ = to_dev(torch, crowded)
     plan = asf.Plan(xe, ye, de, even.lam, even.z0, even.p2x, even.p2y, even.mx, even.my)
     info = plan.info()
-    status = plan.workspace_view(info["off_status"], 1, torch.int32)
     assert crowd.size > info["slot_cap"] // info["ntiles"]   # crowded tiles cannot fit a slab
+    copies = []
 
     def run():
+        # binnings alternate between two copies of the status word and cursors
         plan.status()
-        return int(status.item()), plan.forward(u).cpu().numpy()
+        at = plan.info()["off_status"]
+        copies.append(at)
+        return int(plan.workspace_view(at, 1, torch.int32).item()), plan.forward(u).cpu().numpy()
 
     seq = [run()]                                    # slabs
     for geo in ((xc, yc, dc), (xc, yc, dc), (xe, ye, de), (xe, ye, de)):
         plan.setpts(*geo)
         seq.append(run())
+    assert copies[0] != copies[1] and copies[::2] == [copies[0]] * 3 and copies[1::2] == [copies[1]] * 2
     # uniform slabs hold; they overflow -> compact, new slabs fit (12); those hold;
     # sized for the crowd they overflow on the even geometry -> 12; resized, they hold
     assert [st for st, _ in seq] == [0, 12, 0, 12, 0]
