@@ -95,7 +95,8 @@ typedef struct {
     uint32_t flags;
     /* byte offsets into the workspace of buffers tests may inspect (off_status and
      * off_cursor: the copy of the counters the latest binning used; two binnings
-     * in a row use alternate copies) */
+     * in a row use alternate copies; off_cell and off_perm are the two u32 fields of
+     * 8-byte records, off_frac and off_phase the two float pairs of 16-byte records) */
     size_t off_status, off_tile_start, off_cell, off_frac, off_phase, off_perm, off_fine, off_mid;
     size_t ws_bytes;
     /* per-tile record counts (u32 [ntiles]) and slabs (u32 pairs [ntiles]: first slot,

@@ -119,10 +119,11 @@ int make_layout(int64_t n, const asf_params *p, Layout &L) {
     L.off_cursor = take(sizeof(uint32_t) * L.ntiles);
     L.off_cursor2 = take(sizeof(uint32_t) * L.ntiles);
     L.off_slab = take(sizeof(uint2) * L.ntiles);
-    L.off_cell = take(sizeof(uint32_t) * L.slot_cap);
-    L.off_frac = take(sizeof(float2) * L.slot_cap);
-    L.off_phase = take(sizeof(float2) * L.slot_cap);
-    L.off_perm = take(sizeof(uint32_t) * L.slot_cap);
+    // records: (cell, perm) in 8-byte words, (frac, phase) in 16-byte words
+    L.off_cell = take(sizeof(uint2) * L.slot_cap);
+    L.off_perm = L.off_cell + sizeof(uint32_t);
+    L.off_frac = take(sizeof(float4) * L.slot_cap);
+    L.off_phase = L.off_frac + sizeof(float2);
     L.off_fine = take(sizeof(float2) * (size_t)L.nfx * L.nfy);
     L.off_mid = take(sizeof(float2) * (size_t)L.my * L.nfx);
     L.off_dx = take(sizeof(float2) * L.mx);
@@ -408,10 +409,8 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
     pl->clear_both = true;
     bind_counters(pl);
     pl->bin.tile_start = reinterpret_cast<uint32_t *>(w + L.off_tile_start);
-    pl->bin.cell = reinterpret_cast<uint32_t *>(w + L.off_cell);
-    pl->bin.frac = reinterpret_cast<float2 *>(w + L.off_frac);
-    pl->bin.phase = reinterpret_cast<float2 *>(w + L.off_phase);
-    pl->bin.perm = reinterpret_cast<uint32_t *>(w + L.off_perm);
+    pl->bin.key = reinterpret_cast<uint2 *>(w + L.off_cell);
+    pl->bin.rec = reinterpret_cast<float4 *>(w + L.off_frac);
     pl->bin.slab = reinterpret_cast<uint2 *>(w + L.off_slab);
     pl->bin.slot_cap = (uint32_t)L.slot_cap;
     pl->fine = reinterpret_cast<float2 *>(w + L.off_fine);

@@ -21,10 +21,11 @@ struct Binned {
     uint32_t *tile_start;  // [ntiles + 1] compact layout: exclusive scan of slot counts per tile
     uint32_t *cursor;      // [ntiles] slot counts; compact layout: then insertion cursors
     uint2 *slab;           // [ntiles] first slot and slot count of each tile's slab
-    uint32_t *cell;        // [slot_cap] first footprint cell, l0x | l0y << 16
-    float2 *frac;          // [slot_cap] (gx - l0x - (w-1)/2, gy - l0y - (w-1)/2), in (-1/2, 1/2]
-    float2 *phase;         // [slot_cap] exp(i phi_j), the pre-phase of Eq. (8)
-    uint32_t *perm;        // [slot_cap] index j of the point in the caller's order
+    // a record in two words, each read or written by one instruction:
+    uint2 *key;            // [slot_cap] (first footprint cell l0x | l0y << 16,
+                           //             index j of the point in the caller's order)
+    float4 *rec;           // [slot_cap] (gx - l0x - (w-1)/2, gy - l0y - (w-1)/2), each in
+                           //            (-1/2, 1/2], then exp(i phi_j), the pre-phase of Eq. (8)
     uint32_t slot_cap;     // slots in the arrays above (4 n_src)
     // the other copy of status and cursor, which the next binning uses: the last
     // binning pass clears it, so that a binning needs no clearing launch of its own

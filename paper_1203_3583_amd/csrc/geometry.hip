@@ -220,10 +220,8 @@ __device__ inline void bin_block(const GeoParams &g, const Binned &b, int64_t n,
                 if (act && !ok) atomicOr(b.status, kStatusOverflow);
             }
             if (act && ok) {
-                b.cell[slot] = cell;
-                b.frac[slot] = make_float2(p[k].fx, p[k].fy);
-                b.phase[slot] = ph;
-                b.perm[slot] = (uint32_t)geo_index(blk, k);
+                b.key[slot] = make_uint2(cell, (uint32_t)geo_index(blk, k));
+                b.rec[slot] = make_float4(p[k].fx, p[k].fy, ph.x, ph.y);
             }
         }
     }

@@ -148,10 +148,12 @@ __device__ inline void load_records(Batch &r, const Binned &b, uint32_t base, ui
     for (int k = 0; k < kBatch; ++k) {
         const uint32_t s = base + k * nt;
         const bool in = s < s1;
-        r.j[k] = in ? b.perm[s] : 0xffffffffu;
-        r.cell[k] = in ? b.cell[s] : 0u;
-        r.fr[k] = in ? b.frac[s] : make_float2(0.f, 0.f);
-        r.pc[k] = in ? b.phase[s] : make_float2(0.f, 0.f);
+        const uint2 kv = in ? b.key[s] : make_uint2(0u, 0xffffffffu);
+        const float2 *rv = reinterpret_cast<const float2 *>(b.rec + s);
+        r.j[k] = kv.y;
+        r.cell[k] = kv.x;
+        r.fr[k] = in ? rv[0] : make_float2(0.f, 0.f);
+        r.pc[k] = in ? rv[1] : make_float2(0.f, 0.f);
     }
 }
 
@@ -505,23 +507,24 @@ __global__ void __launch_bounds__(kInterpThreads) interp_kernel(SpreadParams p, 
     tile_slots(b, t, s0, s1);
     // two records per thread and iteration: their loads go out together
     for (uint32_t sb = s0 + tid; sb < s1; sb += 2 * nt) {
-        uint32_t cell[2];
+        uint2 kv[2];   // (cell, point index)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) cell[q] = sb + q * nt < s1 ? b.cell[sb + q * nt] : 0xffffffffu;
+        for (int q = 0; q < 2; ++q) kv[q] = sb + q * nt < s1 ? b.key[sb + q * nt] : make_uint2(0xffffffffu, 0u);
         bool home[2];
         int px[2], py[2];
         uint32_t j[2];
         float2 fr[2], ph[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            px[q] = (int)(cell[q] & 0xffffu) - x0;
-            py[q] = (int)(cell[q] >> 16) - y0;
+            px[q] = (int)(kv[q].x & 0xffffu) - x0;
+            py[q] = (int)(kv[q].x >> 16) - y0;
             // a point is handled in its home tile only (and past s1 nowhere)
             home[q] = sb + q * nt < s1 && px[q] >= 0 && px[q] < tsx && py[q] >= 0 && py[q] < tsy;
             const uint32_t s = sb + q * nt;
-            j[q] = home[q] ? b.perm[s] : 0u;
-            fr[q] = home[q] ? b.frac[s] : make_float2(0.f, 0.f);
-            ph[q] = home[q] ? b.phase[s] : make_float2(0.f, 0.f);
+            const float4 rv = home[q] ? b.rec[s] : make_float4(0.f, 0.f, 0.f, 0.f);
+            j[q] = home[q] ? kv[q].y : 0u;
+            fr[q] = make_float2(rv.x, rv.y);
+            ph[q] = make_float2(rv.z, rv.w);
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {

@@ -106,10 +106,13 @@ def test_binning_matches_host(which):
     tx, ty = info["tile_x"], info["tile_y"]
     st, ranges = _device_bins(torch, plan, info)
     cap = info["slot_cap"]
-    cell = _view(torch, plan, info["off_cell"], cap, torch.int32).view(np.uint32)
-    frac = _view(torch, plan, info["off_frac"], 2 * cap, torch.float32).reshape(-1, 2)
-    phase = _view(torch, plan, info["off_phase"], 2 * cap, torch.float32).reshape(-1, 2)
-    perm = _view(torch, plan, info["off_perm"], cap, torch.int32).astype(np.int64)
+    # records: (cell, perm) as 8-byte words, (frac, phase) as 16-byte words
+    key = _view(torch, plan, info["off_cell"], 2 * cap, torch.int32).reshape(-1, 2)
+    assert info["off_perm"] == info["off_cell"] + 4 and info["off_phase"] == info["off_frac"] + 8
+    rec = _view(torch, plan, info["off_frac"], 4 * cap, torch.float32).reshape(-1, 4)
+    cell = key[:, 0].view(np.uint32)
+    perm = key[:, 1].astype(np.int64)
+    frac, phase = rec[:, 0:2], rec[:, 2:4]
     plan.close()
     assert (st & 4) == (0 if which == "even" else 4)
 
