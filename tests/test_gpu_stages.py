@@ -96,11 +96,37 @@ def _device_bins(torch, plan, info):
     return st, ranges
 
 
-@pytest.mark.parametrize("which", ["even", "crowded"])
+def _hot():
+    """5000 points on a 64 x 64 grid: few tiles, each holding thousands of records."""
+    rng = np.random.default_rng(9)
+    n = 5000
+    x = rng.uniform(-4e-6, 4e-6, n)
+    y = rng.uniform(-4e-6, 4e-6, n)
+    d = rng.uniform(0, 10e-6, n)
+    u = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
+    return synth.Workload("hot", x, y, d, u, 532e-9, 0.1, 8e-6, 8e-6, 64, 64)
+
+
+# (workload, binnings of the same points, status of the last one): uniform slabs;
+# overflow into the compact layout whose counts size new slabs (12 = compact + fit);
+# those sized slabs filled by the looping slab pass (0); a tile too crowded for sized
+# slabs (4 = compact, no fit), after which the plan counts first (4)
+BINNINGS = {"even": (_even, 1, 0), "crowded": (_crowded, 1, 12), "crowded_sized": (_crowded, 2, 0),
+            "hot": (_hot, 1, 4), "hot_count_first": (_hot, 2, 4)}
+
+
+@pytest.mark.parametrize("which", list(BINNINGS))
 def test_binning_matches_host(which):
+    """Every binning path lists exactly the host's (tile, point) pairs, each record
+    holding the host's cell and FP32 offsets and a pre-phase within FP32 rounding."""
     torch = torch_gpu()
-    w = _even() if which == "even" else _crowded()
+    make, times, want_st = BINNINGS[which]
+    w = make()
     plan, _ = _plan(torch, w)
+    for _ in range(times - 1):
+        plan.status()
+        plan.setpts(*to_dev(torch, w)[:3])
+    plan.status()
     info = plan.info()
     nfx, nfy, wid = info["nfx"], info["nfy"], info["w"]
     tx, ty = info["tile_x"], info["tile_y"]
@@ -114,7 +140,7 @@ def test_binning_matches_host(which):
     perm = key[:, 1].astype(np.int64)
     frac, phase = rec[:, 0:2], rec[:, 2:4]
     plan.close()
-    assert (st & 4) == (0 if which == "even" else 4)
+    assert st == want_st
 
     cx, cy, ox, oy, ph = _host_points(w, nfx, nfy, wid)
     got = sorted((t, int(perm[s])) for t, (a, b) in enumerate(ranges) for s in range(a, b))
@@ -140,17 +166,6 @@ def _fine_natural(torch, plan, info):
     v = (raw[0::2] + 1j * raw[1::2]).astype(np.complex128)
     # element (gx, gy) at ((gx / C) nfy + gy) C + gx % C -> [gy, gx]
     return v.reshape(nfx // C, nfy, C).transpose(1, 0, 2).reshape(nfy, nfx)
-
-
-def _hot():
-    """5000 points on a 64 x 64 grid: few tiles, each holding thousands of records."""
-    rng = np.random.default_rng(9)
-    n = 5000
-    x = rng.uniform(-4e-6, 4e-6, n)
-    y = rng.uniform(-4e-6, 4e-6, n)
-    d = rng.uniform(0, 10e-6, n)
-    u = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
-    return synth.Workload("hot", x, y, d, u, 532e-9, 0.1, 8e-6, 8e-6, 64, 64)
 
 
 @pytest.mark.parametrize("which", ["even", "crowded", "hot"])
