@@ -159,6 +159,10 @@ __device__ inline void bin_block(const GeoParams &g, const Binned &b, int64_t n,
                                  const double *__restrict__ x, const double *__restrict__ y,
                                  const double *__restrict__ d) {
     double xv[kBinPoints], yv[kBinPoints], dv[kBinPoints];
+    // kStatusCompact is known set (wave-uniform): a crowded geometry overflows in
+    // nearly every wave, and one status word taking an atomic from each of them
+    // serialises the pass (4.2 ms instead of 0.6 ms on the 4096^2 relief)
+    bool compact_known = false;
 #pragma unroll
     for (int k = 0; k < kBinPoints; ++k) {
         const int64_t j = geo_index(blk, k);
@@ -212,8 +216,14 @@ __device__ inline void bin_block(const GeoParams &g, const Binned &b, int64_t n,
                 const uint2 sl = act ? b.slab[key] : make_uint2(0u, 0u);
                 slot = sl.x + pos;
                 ok = pos < sl.y;
-                // one flag per wave: a crowded tile can overflow by millions of records
-                if (__ballot(act && !ok) != 0ull && __lane_id() == 0) atomicOr(b.status, kStatusCompact);
+                // at most one flag per wave, none once the bit is seen set: a crowded
+                // tile can overflow by millions of records
+                if (!compact_known && __ballot(act && !ok) != 0ull) {
+                    compact_known = true;
+                    if (__lane_id() == 0 &&
+                        !(__hip_atomic_load(b.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kStatusCompact))
+                        atomicOr(b.status, kStatusCompact);
+                }
             } else {
                 slot = pos;
                 ok = act && slot < b.tile_start[key + 1];
