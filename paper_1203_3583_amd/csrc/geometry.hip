@@ -177,10 +177,10 @@ __device__ inline void bin_block(const GeoParams &g, const Binned &b, int64_t n,
 #pragma unroll
     for (int k = 0; k < kBinPoints; ++k) {
         p[k].n = 0;
-        if (geo_index(blk, k) < n) {
-            p[k] = point_tiles(g, xv[k], yv[k], dv[k]);
-            if (SLAB && p[k].n == 0) atomicOr(b.status, kStatusDomain);
-        }
+        const bool in = geo_index(blk, k) < n;
+        if (in) p[k] = point_tiles(g, xv[k], yv[k], dv[k]);
+        // one flag per wave holding invalid points
+        if (SLAB && __ballot(in && p[k].n == 0) != 0ull && __lane_id() == 0) atomicOr(b.status, kStatusDomain);
         // group the replica keys, then let the leaders reserve their groups'
         // slots; the atomics of all batches and replicas are in flight at once
 #pragma unroll
@@ -276,10 +276,9 @@ __global__ void __launch_bounds__(kGeoThreads) bin_count_kernel(GeoParams g, Bin
     for (int k = 0; k < kCountPoints; ++k) {
         PointTiles p;
         p.n = 0;
-        if (geo_index<kCountPoints>(blockIdx.x, k) < n) {
-            p = point_tiles(g, xv[k], yv[k], dv[k]);
-            if (p.n == 0) atomicOr(b.status, kStatusDomain);
-        }
+        const bool in = geo_index<kCountPoints>(blockIdx.x, k) < n;
+        if (in) p = point_tiles(g, xv[k], yv[k], dv[k]);
+        if (__ballot(in && p.n == 0) != 0ull && __lane_id() == 0) atomicOr(b.status, kStatusDomain);
         for (int r = 0; r < 4; ++r) {
             const bool act = r < p.n;
             const WaveGroup grp = wave_group(act ? p.key[r] : 0, act);
