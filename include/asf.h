@@ -139,6 +139,10 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
  * asf_status().  How points are binned (one pass into per-tile slabs, or
  * counting first for crowded geometries) follows the status last read by
  * asf_plan or asf_status; the results do not depend on it, only the time.
+ * Calls on one plan are ordered by the caller's stream: a later forward, adjoint
+ * or asf_status sees this binning, and the binning after it reuses the counters
+ * of the one before (binnings alternate between two copies), so do not issue a
+ * setpts on another stream while work of the same plan is in flight.
  * Returns ASF_OK, ASF_EINVAL or ASF_EHIP.
  */
 int asf_setpts(asf_plan_t plan, const double *x1, const double *y1, const double *d1,
