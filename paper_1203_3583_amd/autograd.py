@@ -66,8 +66,10 @@ def intensity_loss(plan, theta, amp, target):
 
 
 def energy_matched(plan, amp, target, theta=None):
-    """target scaled to the energy sum |u2|^2 of the source amp exp(i theta) (default
-    theta = 0).  A phase-only source keeps its energy, so this is the target's scale."""
+    """target rescaled so that its sum equals the energy sum |u2|^2 over the destination
+    window of the source amp exp(i theta) (default theta = 0).  The window's energy
+    depends on theta (the window is finite), so a caller fixes this scale once per
+    problem and uses the same target for every iteration and every start it compares."""
     torch = _torch()
     th = torch.zeros_like(amp) if theta is None else theta
     with torch.no_grad():
@@ -78,12 +80,15 @@ def energy_matched(plan, amp, target, theta=None):
 
 
 def phase_descent(plan, amp, target, steps=50, lr=0.05, theta0=None, callback=None):
-    """Adam on the source phase theta for ``intensity_loss`` against the energy-matched
-    target, from theta0 (default zero phase); returns (theta, losses)."""
+    """Adam on the source phase theta for ``intensity_loss`` against ``target`` as given
+    (in units of |u2|^2: an intensity the forward method produced, or a target scaled
+    once with ``energy_matched``), from theta0 (default zero phase).  Returns
+    (theta, losses); descents from different starts against the same target are
+    comparable loss for loss."""
     torch = _torch()
     theta = (torch.zeros_like(amp, dtype=torch.float64) if theta0 is None
              else theta0.detach().to(torch.float64).clone())
-    target = energy_matched(plan, amp, target, theta)
+    target = target.double()
     theta.requires_grad_(True)
     opt = torch.optim.Adam([theta], lr=lr)
     losses = []

@@ -112,13 +112,19 @@ def test_flat_grid_is_a_centred_dft(fft, d0, incident):
     assert err <= TOL[fft]
 
 
-def test_single_point():
+@pytest.mark.parametrize("fft", ["fp32", "split_fp16"])
+def test_single_point(fft):
+    """One point: u2 is a plane wave times the chirps, the same magnitude everywhere,
+    so every destination pixel carries the kernel and deconvolution error alone."""
     w = _custom(1, 1, 8e-6, 3e-6, 32, 32, 8e-6, 8e-6)
-    got, _ = gpu_forward(w)
-    assert rel_l2(got, _full_grid(w)) <= 1e-5
+    got, _ = gpu_forward(w, fft)
+    err = rel_l2(got, _full_grid(w))
+    print(f"single point {fft}: {err:.3e}")
+    assert err <= TOL[fft]
 
 
-def test_hot_tile_all_points_in_one_cell_block():
+@pytest.mark.parametrize("fft", ["fp32", "split_fp16"])
+def test_hot_tile_all_points_in_one_cell_block(fft):
     """5000 points within a few fine cells: one tile holds every point."""
     rng = np.random.default_rng(9)
     n = 5000
@@ -127,8 +133,12 @@ def test_hot_tile_all_points_in_one_cell_block():
     d = rng.uniform(0, 10e-6, n)
     u = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
     w = synth.Workload("hot", x, y, d, u, 532e-9, 0.1, 8e-6, 8e-6, 64, 64)
-    got, _ = gpu_forward(w)
-    assert rel_l2(got, _full_grid(w)) <= 1e-5
+    got, _ = gpu_forward(w, fft)
+    err = rel_l2(got, _full_grid(w))
+    print(f"hot tile {fft}: {err:.3e}")
+    assert err <= TOL[fft]
+    if fft != "fp32":
+        return
     # slabs sized from these counts would not fit in 4 n slots: the plan keeps the
     # compact layout and re-bins by counting first, with the same result
     torch = torch_gpu()
@@ -213,28 +223,6 @@ def test_binning_layout_switches_with_crowding():
     assert rel_l2(f_crowd[iy, ix], _oracle(crowded, ix, iy)) <= 1e-5
     assert rel_l2(f_even[iy, ix], _oracle(even, ix, iy)) <= 1e-5
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
-
-
-@pytest.mark.parametrize("fft", ["fp32", "split_fp16"])
-def test_cap_2048_full_size(fft):
-    """The 2048^2 spherical cap at full size on crops and random pixels."""
-    w = synth.config("cap_2048")
-    got, info = gpu_forward(w, fft)
-    for name, (ix, iy) in eval_sets(w, n_random=256, crop=16).items():
-        err = rel_l2(got[iy, ix], _oracle(w, ix, iy))
-        print(f"cap_2048 {fft} {name}: {err:.3e}")
-        assert err <= TOL[fft], name
-
-
-@pytest.mark.parametrize("fft", ["fp32", "split_fp16"])
-def test_sinusoid_4096_full_size(fft):
-    """The 4096^2 sinusoidal relief at full size on small crops and random pixels."""
-    w = synth.config("sinusoid_4096")
-    got, info = gpu_forward(w, fft)
-    for name, (ix, iy) in eval_sets(w, n_random=128, crop=8).items():
-        err = rel_l2(got[iy, ix], _oracle(w, ix, iy))
-        print(f"sinusoid_4096 {fft} {name}: {err:.3e}")
-        assert err <= TOL[fft], name
 
 
 @pytest.mark.parametrize("fft", ["fp32", "split_fp16"])

@@ -215,4 +215,7 @@ def test_trained_network_speeds_up_the_descent():
         print(f"held-out {k}: zero {lz[0]:.3f} -> {lz[-1]:.4f}, warm {lw[0]:.3f} -> {lw[-1]:.4f}, "
               f"warm reaches the zero-phase final loss at iteration {it}")
         assert lw[0] < lz[0]
+    # every held-out problem: the warm descent reaches the zero-phase descent's final
+    # loss (same target, same scale) before the last of its 50 iterations
+    assert all(it is not None and it < 50 for it in iters), iters
     assert np.mean(iters) < 40

@@ -34,7 +34,8 @@ def problem(side=32, seed=0):
 
 
 def test_gradient_matches_central_differences():
-    w, theta, t = problem()
+    """64 x 64 source and destination (the differentiation configuration's check size)."""
+    w, theta, t = problem(side=64)
     g = grad_fp64(w, theta, t)
     rng = np.random.default_rng(3)
     h = 1e-5
