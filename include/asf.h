@@ -52,6 +52,8 @@ extern "C" {
 #define ASF_FFT_FP32 0u             /* FFT stages: FP32 products on MFMA, FP32 accumulation */
 #define ASF_FFT_SPLIT_FP16 1u       /* FFT stages: FP16 hi+lo split products on MFMA, FP32 accumulation */
 #define ASF_FFT_MASK 1u
+/* size of the fixed device scratch array used by asf_forward_static (per GPU) */
+#define ASF_STATIC_SCRATCH_BYTES ((size_t)48 << 20)
 #define ASF_INCIDENT_NONE 2u        /* u_I = 1 instead of the plane wave exp(i k d1) */
 
 typedef struct asf_plan_s *asf_plan_t;
@@ -175,6 +177,27 @@ int asf_forward(asf_plan_t plan, const void *u1, void *u2, void *stream);
  * ordered (the same stream, or synchronised).
  */
 int asf_forward_add(asf_plan_t plan, const void *u1, void *u2, void *stream);
+
+/*
+ * For callers that cannot allocate device memory at call time (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * forward u2 = A u1 of asf_forward, with the same arguments, kernels and result,
+ * whose fine grid and column-pass output live in the library's fixed device
+ * scratch array instead of the plan's workspace.  The plan's workspace still
+ * holds the binned points and tables (it is not written by this call).
+ * Limit: the fine grid and the column-pass output, 8 (4 mx my + 2 mx my) bytes,
+ * must fit in ASF_STATIC_SCRATCH_BYTES (48 MiB: destinations up to 1024 x 1024);
+ * larger plans get ASF_ESIZE and nothing is launched.  Calls nothing that
+ * allocates (no hipMalloc, hipFree or allocating library routine); the scratch
+ * array exists once per GPU for the life of the process, and its address is
+ * looked up on the first call on each device (the plan's device must be
+ * current).  Every call on one GPU shares that GPU's array: calls that overlap
+ * on one GPU (different streams, or different host threads) race and give wrong
+ * results; order them.  The array keeps the last call's contents, which no call
+ * reads before overwriting.  Asynchronous on `stream`; never synchronises.
+ * Returns ASF_OK, ASF_EINVAL, ASF_ESIZE or ASF_EHIP.
+ */
+int asf_forward_static(asf_plan_t plan, const void *u1, void *u2, void *stream);
 
 
 /*

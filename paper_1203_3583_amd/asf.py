@@ -91,6 +91,8 @@ def lib():
         L.asf_forward.argtypes = [vp, vp, vp, vp]
         L.asf_forward_add.restype = i32
         L.asf_forward_add.argtypes = [vp, vp, vp, vp]
+        L.asf_forward_static.restype = i32
+        L.asf_forward_static.argtypes = [vp, vp, vp, vp]
         L.asf_adjoint.restype = i32
         L.asf_adjoint.argtypes = [vp, vp, vp, vp]
         L.asf_plan_info.restype = i32
@@ -222,6 +224,22 @@ class Plan:
             raise ValueError("out must be a contiguous complex64 [my, mx] tensor on the plan's device")
         fn = lib().asf_forward_add if accumulate else lib().asf_forward
         _check(fn(self._h, u1.data_ptr(), out.data_ptr(), _stream_ptr(torch, self.device, stream)))
+        return out
+
+    def forward_static(self, u1, out, stream=None):
+        """asf_forward_static: the forward with the fine grid and column-pass output in the
+        library's fixed device scratch (destinations up to 1024 x 1024; calls on one GPU
+        must not overlap).  ``out`` must be given (nothing is allocated)."""
+        torch = self._torch
+        if not isinstance(u1, torch.Tensor) or u1.dtype != torch.complex64 or u1.device != self.device:
+            raise TypeError(f"u1 must be a complex64 tensor on {self.device}")
+        if u1.numel() != self.n or not u1.is_contiguous():
+            raise ValueError(f"u1 must be contiguous with {self.n} elements")
+        if (out.dtype != torch.complex64 or out.device != self.device or out.numel() != self.mx * self.my
+                or not out.is_contiguous()):
+            raise ValueError("out must be a contiguous complex64 [my, mx] tensor on the plan's device")
+        _check(lib().asf_forward_static(self._h, u1.data_ptr(), out.data_ptr(),
+                                        _stream_ptr(torch, self.device, stream)))
         return out
 
     def adjoint(self, g2, out=None, stream=None):

@@ -491,29 +491,36 @@ int asf_status(asf_plan_t plan, void *stream) {
 
 namespace {
 
-int forward(asf_plan_t plan, const void *u1, void *u2, void *stream, int accumulate) {
-    if (!plan || !u1 || !u2) return fail(ASF_EINVAL, "plan, u1, u2 must be non-NULL");
+// Spread, column pass and row pass into u2; fine and mid are the fine grid and the
+// column pass's output (the plan's workspace, or the static scratch).
+int forward_into(asf_plan_t plan, const void *u1, void *u2, void *stream, int accumulate, float2 *fine,
+                 float2 *mid) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     asf_plan_s *p = plan;
     const int split = (p->prm.flags & ASF_FFT_MASK) == ASF_FFT_SPLIT_FP16;
     hipError_t e;
     {
         StageMark m(p, asf::STAGE_SPREAD, s);
-        e = asf::launch_spread(p->sp, p->bin, static_cast<const float2 *>(u1), p->fine, s);
+        e = asf::launch_spread(p->sp, p->bin, static_cast<const float2 *>(u1), fine, s);
         if (e != hipSuccess) return hip_fail(e, "spread launch");
     }
     {
         StageMark m(p, asf::STAGE_FFT1, s);
-        e = asf::launch_fft_pass1(p->sh1, split, p->fine, p->mid, p->twy, p->w16, p->lay.nfx, p->lay.my, s);
+        e = asf::launch_fft_pass1(p->sh1, split, fine, mid, p->twy, p->w16, p->lay.nfx, p->lay.my, s);
         if (e != hipSuccess) return hip_fail(e, "fft pass 1 launch");
     }
     {
         StageMark m(p, asf::STAGE_FFT2, s);
-        e = asf::launch_fft_pass2(p->sh2, log2i(p->sh1.batch), split, p->mid, static_cast<float2 *>(u2),
+        e = asf::launch_fft_pass2(p->sh2, log2i(p->sh1.batch), split, mid, static_cast<float2 *>(u2),
                                   p->twx, p->w16, p->dx, p->dy, p->lay.mx, p->lay.my, accumulate, s);
         if (e != hipSuccess) return hip_fail(e, "fft pass 2 launch");
     }
     return ASF_OK;
+}
+
+int forward(asf_plan_t plan, const void *u1, void *u2, void *stream, int accumulate) {
+    if (!plan || !u1 || !u2) return fail(ASF_EINVAL, "plan, u1, u2 must be non-NULL");
+    return forward_into(plan, u1, u2, stream, accumulate, plan->fine, plan->mid);
 }
 
 }  // namespace
@@ -524,6 +531,23 @@ int asf_forward(asf_plan_t plan, const void *u1, void *u2, void *stream) {
 
 int asf_forward_add(asf_plan_t plan, const void *u1, void *u2, void *stream) {
     return forward(plan, u1, u2, stream, 1);
+}
+
+int asf_forward_static(asf_plan_t plan, const void *u1, void *u2, void *stream) {
+    if (!plan || !u1 || !u2) return fail(ASF_EINVAL, "plan, u1, u2 must be non-NULL");
+    const Layout &L = plan->lay;
+    const size_t fine_bytes = align_up(sizeof(float2) * (size_t)L.nfx * L.nfy);
+    const size_t mid_bytes = sizeof(float2) * (size_t)L.my * L.nfx;
+    if (fine_bytes + mid_bytes > asf::kStaticScratchBytes)
+        return fail(ASF_ESIZE, "the fine grid and column-pass output of a %d x %d destination need %zu bytes; "
+                    "the static scratch holds %zu (destinations up to 1024 x 1024)", L.mx, L.my,
+                    fine_bytes + mid_bytes, asf::kStaticScratchBytes);
+    void *base = nullptr;
+    hipError_t e = asf::static_scratch(&base);
+    if (e != hipSuccess) return hip_fail(e, "static scratch address");
+    char *b = static_cast<char *>(base);
+    return forward_into(plan, u1, u2, stream, 0, reinterpret_cast<float2 *>(b),
+                        reinterpret_cast<float2 *>(b + fine_bytes));
 }
 
 int asf_adjoint(asf_plan_t plan, const void *g2, void *g1, void *stream) {

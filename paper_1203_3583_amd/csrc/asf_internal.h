@@ -149,6 +149,11 @@ hipError_t launch_fft_adj_cols(int len, int split16, const float2 *mid, float2 *
 // adjoint of spreading: fine grid -> g1[n] (caller's order)
 hipError_t launch_interp(const SpreadParams &p, const Binned &b, const float2 *fine, float2 *g1,
                          hipStream_t s);
+// The library's fixed device scratch (ASF_STATIC_SCRATCH_BYTES on every device it
+// runs on): its address on the current device, looked up on first use.
+constexpr size_t kStaticScratchBytes = ASF_STATIC_SCRATCH_BYTES;
+hipError_t static_scratch(void **out);
+
 int fft_batch_pass1(int len);          // columns per workgroup in pass 1 (fine-grid panel width)
 int fft_batch_pass2(int len);          // rows per workgroup in pass 2
 size_t fft_lds_bytes(int len, int batch);
