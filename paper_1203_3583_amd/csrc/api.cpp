@@ -21,185 +21,19 @@
 
 #include "asf.h"
 #include "asf_internal.h"
+#include "plan_host.h"
 
 using asf::FftShape;
 
 namespace {
 
-thread_local std::string g_err;
-
-int fail(int code, const char *fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return code;
-}
+using namespace asf::host;
 
 int hip_fail(hipError_t e, const char *what) {
     return fail(ASF_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-constexpr double kPi = 3.14159265358979323846;
-constexpr size_t kAlign = 256;
-constexpr int kTileXMax = 64;   // spreading tile: 64 x 32 fine cells
-constexpr int kTileYMax = 32;
-constexpr int kQuadNodes = 200;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
-
-int log2i(int v) {
-    int s = 0;
-    while ((1 << s) < v) ++s;
-    return s;
-}
-
-struct Layout {
-    int64_t n;
-    int mx, my, nfx, nfy, w, tile_x, tile_y, ntx, nty, ntiles;
-    double beta;
-    int64_t slot_cap;
-    size_t off_status, off_tile_start, off_cursor, off_slab, off_cell, off_frac, off_phase, off_perm;
-    size_t off_status2, off_cursor2;   // the counters' second copy
-    size_t off_fine, off_mid, off_dx, off_dy, off_twx, off_twy, off_w16, total;
-};
-
-int check_params(int64_t n, const asf_params *p) {
-    if (!p) return fail(ASF_EINVAL, "params is NULL");
-    // slot indices are 32-bit: 4 n_src slots must stay below 2^32
-    if (n < 1 || n >= (int64_t(1) << 30)) return fail(ASF_EINVAL, "n_src must be in [1, 2^30 - 1], got %lld", (long long)n);
-    const double v[4] = {p->lambda, p->z0, p->p2x, p->p2y};
-    const char *names[4] = {"lambda", "z0", "p2x", "p2y"};
-    for (int i = 0; i < 4; ++i)
-        if (!std::isfinite(v[i]) || !(v[i] > 0.0)) return fail(ASF_EINVAL, "%s must be finite and > 0", names[i]);
-    if (!std::isfinite(p->tol) || p->tol < 1e-7 || p->tol > 1e-1) return fail(ASF_EINVAL, "tol must be in [1e-7, 1e-1]");
-    if (!std::isfinite(p->x0) || !std::isfinite(p->y0)) return fail(ASF_EINVAL, "x0, y0 must be finite");
-    if (p->flags & ~(ASF_FFT_MASK | ASF_INCIDENT_NONE)) return fail(ASF_EINVAL, "unknown flag bits 0x%x", p->flags);
-    if (!is_pow2(p->mx) || !is_pow2(p->my) || p->mx < 16 || p->my < 16 || p->mx > 8192 || p->my > 8192)
-        return fail(ASF_ESIZE, "mx, my must be powers of two in [16, 8192], got %d x %d", p->mx, p->my);
-    return ASF_OK;
-}
-
-int spread_width(double tol) {
-    int w = (int)std::ceil(-std::log10(tol) - 1e-9) + 2;
-    if (w < 2) w = 2;
-    if (w > 9) w = 9;
-    return w;
-}
-
-int make_layout(int64_t n, const asf_params *p, Layout &L) {
-    int rc = check_params(n, p);
-    if (rc) return rc;
-    L.n = n;
-    L.mx = p->mx;
-    L.my = p->my;
-    L.nfx = 2 * p->mx;
-    L.nfy = 2 * p->my;
-    L.w = spread_width(p->tol);
-    L.beta = 2.30 * L.w;
-    L.tile_x = L.nfx < kTileXMax ? L.nfx : kTileXMax;
-    L.tile_y = L.nfy < kTileYMax ? L.nfy : kTileYMax;
-    L.ntx = L.nfx / L.tile_x;
-    L.nty = L.nfy / L.tile_y;
-    L.ntiles = L.ntx * L.nty;
-    L.slot_cap = 4 * n;
-    size_t o = 0;
-    auto take = [&o](size_t bytes) {
-        size_t at = o;
-        o = align_up(o + bytes);
-        return at;
-    };
-    L.off_status = take(kAlign);
-    L.off_status2 = take(kAlign);
-    L.off_tile_start = take(sizeof(uint32_t) * (L.ntiles + 1));
-    L.off_cursor = take(sizeof(uint32_t) * L.ntiles);
-    L.off_cursor2 = take(sizeof(uint32_t) * L.ntiles);
-    L.off_slab = take(sizeof(uint2) * L.ntiles);
-    // records: (cell, perm) in 8-byte words, (frac, phase) in 16-byte words
-    L.off_cell = take(sizeof(uint2) * L.slot_cap);
-    L.off_perm = L.off_cell + sizeof(uint32_t);
-    L.off_frac = take(sizeof(float4) * L.slot_cap);
-    L.off_phase = L.off_frac + sizeof(float2);
-    L.off_fine = take(sizeof(float2) * (size_t)L.nfx * L.nfy);
-    L.off_mid = take(sizeof(float2) * (size_t)L.my * L.nfx);
-    L.off_dx = take(sizeof(float2) * L.mx);
-    L.off_dy = take(sizeof(float2) * L.my);
-    L.off_twx = take(sizeof(float2) * asf::fft_twiddle_entries(L.nfx));
-    L.off_twy = take(sizeof(float2) * asf::fft_twiddle_entries(L.nfy));
-    L.off_w16 = take(sizeof(float2) * 16);
-    L.total = o;
-    return ASF_OK;
-}
-
-// Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_n).
-void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &wq) {
-    x.assign(n, 0.0);
-    wq.assign(n, 0.0);
-    for (int i = 0; i < (n + 1) / 2; ++i) {
-        double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
-        double pp = 0.0;
-        for (int it = 0; it < 100; ++it) {
-            double p1 = 1.0, p2 = 0.0;
-            for (int j = 1; j <= n; ++j) {
-                const double p3 = p2;
-                p2 = p1;
-                p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
-            }
-            pp = n * (z * p1 - p2) / (z * z - 1.0);
-            const double dz = p1 / pp;
-            z -= dz;
-            if (std::fabs(dz) < 1e-16) break;
-        }
-        x[i] = -z;
-        x[n - 1 - i] = z;
-        wq[i] = wq[n - 1 - i] = 2.0 / ((1.0 - z * z) * pp * pp);
-    }
-}
-
-// Fourier transform of psi(z) = exp(beta (sqrt(1 - (2z/w)^2) - 1)) at mode m of an nf grid:
-// int psi(z) exp(-2 pi i m z / nf) dz = (w/2) int_{-1}^{1} es(u) cos(pi m w u / nf) du.
-std::vector<double> psi_hat(int nmodes_half, int nf, int w, double beta) {
-    std::vector<double> xq, wq;
-    gauss_legendre(kQuadNodes, xq, wq);
-    std::vector<double> es(kQuadNodes);
-    for (int q = 0; q < kQuadNodes; ++q) es[q] = std::exp(beta * (std::sqrt(1.0 - xq[q] * xq[q]) - 1.0));
-    std::vector<double> out(nmodes_half + 1);
-    for (int m = 0; m <= nmodes_half; ++m) {
-        double s = 0.0;
-        for (int q = 0; q < kQuadNodes; ++q) s += wq[q] * es[q] * std::cos(kPi * m * w * xq[q] / nf);
-        out[m] = 0.5 * w * s;
-    }
-    return out;
-}
-
-// Twiddle tables of the radix-16 Stockham stages of a length-len FFT, in the
-// order the kernels read them: for each stage with span ns > 1 (ns = r0 16^s),
-// entry (k, g, i) = exp(-2 pi i r k / (16 ns)) with r = g + 4 i, k < ns, g, i < 4.
-std::vector<float2> stage_twiddles(int len) {
-    const int log = log2i(len);
-    const int r0 = 1 << (log % 4), n16 = log / 4;
-    std::vector<float2> t;
-    t.reserve(asf::fft_twiddle_entries(len));
-    for (int s = 0; s < n16; ++s) {
-        const int ns = r0 << (4 * s);
-        if (ns <= 1) continue;
-        for (int k = 0; k < ns; ++k)
-            for (int g = 0; g < 4; ++g)
-                for (int i = 0; i < 4; ++i) {
-                    const int r = g + 4 * i;
-                    const double a = 2.0 * kPi * (double)(r * k) / (16.0 * ns);
-                    t.push_back(make_float2((float)std::cos(a), (float)-std::sin(a)));
-                }
-    }
-    return t;
-}
-
-// Reduce a phase argument (rad) to [-pi, pi] in FP64.
-double reduce(double a) { return std::remainder(a, 2.0 * kPi); }
+static_assert(sizeof(Cf) == sizeof(float2), "host complex values are laid out like float2");
 
 }  // namespace
 
@@ -307,7 +141,7 @@ int upload_tables(asf_plan_s *p, hipStream_t s) {
     const asf_params &q = p->prm;
     const double k = 2.0 * kPi / q.lambda;
     std::vector<float2> dx(L.mx), dy(L.my), w16(16);
-    const std::vector<float2> twx = stage_twiddles(L.nfx), twy = stage_twiddles(L.nfy);
+    const std::vector<Cf> twx = stage_twiddles(L.nfx), twy = stage_twiddles(L.nfy);
     const std::vector<double> phx = psi_hat(L.mx / 2, L.nfx, L.w, L.beta);
     const std::vector<double> phy = psi_hat(L.my / 2, L.nfy, L.w, L.beta);
     // exp(i k z0) / (i lambda z0) = -i exp(i k z0) / (lambda z0)
@@ -343,8 +177,8 @@ int upload_tables(asf_plan_s *p, hipStream_t s) {
         {p->bin.slab, slab.data(), slab.size() * sizeof(uint2)},
         {p->dx, dx.data(), dx.size() * sizeof(float2)},
         {p->dy, dy.data(), dy.size() * sizeof(float2)},
-        {p->twx, twx.data(), twx.size() * sizeof(float2)},
-        {p->twy, twy.data(), twy.size() * sizeof(float2)},
+        {p->twx, twx.data(), twx.size() * sizeof(Cf)},
+        {p->twy, twy.data(), twy.size() * sizeof(Cf)},
         {p->w16, w16.data(), w16.size() * sizeof(float2)},
     };
     for (auto &c : copies) {
@@ -378,7 +212,7 @@ int read_status(asf_plan_s *p, hipStream_t s) {
 
 extern "C" {
 
-const char *asf_last_error(void) { return g_err.c_str(); }
+const char *asf_last_error(void) { return asf::host::last_error(); }
 
 size_t asf_workspace_bytes(int64_t n_src, const asf_params *p) {
     Layout L;
@@ -661,47 +495,6 @@ struct asf_line_s {
 };
 
 namespace {
-
-struct LineLayout {
-    int n, m, nf, w;
-    double beta;
-    size_t off_status, off_first, off_perm, off_cell, off_coef, off_tw, off_dd, total;
-};
-
-int make_line_layout(int64_t n, const asf_line_params *p, LineLayout &L) {
-    if (!p) return fail(ASF_EINVAL, "params is NULL");
-    if (n < 1 || n > asf::kLineMaxPoints)
-        return fail(ASF_EINVAL, "n_src must be in [1, %d], got %lld", asf::kLineMaxPoints, (long long)n);
-    const double v[3] = {p->lambda, p->z0, p->p2};
-    const char *names[3] = {"lambda", "z0", "p2"};
-    for (int i = 0; i < 3; ++i)
-        if (!std::isfinite(v[i]) || !(v[i] > 0.0)) return fail(ASF_EINVAL, "%s must be finite and > 0", names[i]);
-    if (!std::isfinite(p->x0)) return fail(ASF_EINVAL, "x0 must be finite");
-    if (!std::isfinite(p->tol) || p->tol < 1e-7 || p->tol > 1e-1) return fail(ASF_EINVAL, "tol must be in [1e-7, 1e-1]");
-    if (p->flags & ~ASF_INCIDENT_NONE) return fail(ASF_EINVAL, "unknown flag bits 0x%x", p->flags);
-    if (!is_pow2(p->m) || p->m < 16 || p->m > 8192)
-        return fail(ASF_ESIZE, "m must be a power of two in [16, 8192], got %d", p->m);
-    L.n = (int)n;
-    L.m = p->m;
-    L.nf = 2 * p->m;
-    L.w = spread_width(p->tol);
-    L.beta = 2.30 * L.w;
-    size_t o = 0;
-    auto take = [&o](size_t bytes) {
-        size_t at = o;
-        o = align_up(o + bytes);
-        return at;
-    };
-    L.off_status = take(kAlign);
-    L.off_first = take(sizeof(uint32_t) * (L.nf + 1));
-    L.off_perm = take(sizeof(uint32_t) * L.n);
-    L.off_cell = take(sizeof(uint32_t) * L.n);
-    L.off_coef = take(sizeof(float2) * (size_t)L.n * L.w);
-    L.off_tw = take(sizeof(float2) * (L.nf / 2));
-    L.off_dd = take(sizeof(float2) * L.m);
-    L.total = o;
-    return ASF_OK;
-}
 
 int upload_line_tables(asf_line_s *p, const LineLayout &L, hipStream_t s) {
     const asf_line_params &q = p->prm;

@@ -157,7 +157,6 @@ hipError_t static_scratch(void **out);
 int fft_batch_pass1(int len);          // columns per workgroup in pass 1 (fine-grid panel width)
 int fft_batch_pass2(int len);          // rows per workgroup in pass 2
 size_t fft_lds_bytes(int len, int batch);
-size_t fft_twiddle_entries(int len);   // complex entries of one length's stage twiddle tables
 int fft_max_lds_bytes();
 
 }  // namespace asf

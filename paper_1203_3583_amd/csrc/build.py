@@ -13,7 +13,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libasf.so")
-SOURCES = ["geometry.hip", "spread.hip", "fft.hip", "line.hip", "warm.hip", "scratch.hip", "api.cpp"]
+SOURCES = ["geometry.hip", "spread.hip", "fft.hip", "line.hip", "warm.hip", "scratch.hip", "plan_host.cpp", "api.cpp"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", HERE,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function"]
@@ -39,7 +39,7 @@ def _compile(src, obj_dir):
 def build(verbose: bool = False) -> str:
     obj_dir = os.path.join(ROOT, "_build", "asf")
     os.makedirs(obj_dir, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(7, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         results = list(ex.map(lambda s: _compile(s, obj_dir), SOURCES))
     for _, msg in results:
         if verbose and msg.strip():

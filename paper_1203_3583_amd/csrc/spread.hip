@@ -36,7 +36,12 @@
 //            half into the high half is undone exactly at unpacking);
 //   split:   denser tiles, and grids so small that the padded tile folds onto
 //            itself, keep separate 64-bit sums of Re and Im, accumulated in two
-//            sweeps over the same LDS array.
+//            sweeps over the same LDS array, with 42-bit terms (term42: the
+//            rounding remainder of each term kept as a second 20-bit piece).
+// One rounding step for every term of a tile costs a tile whose energy sits in a
+// few records (a bright point among weak ones) more than the others: their
+// rounding error is set by the bright record's amplitude, not by their own.
+// Such tiles (sum |c|^2 below nrec M^2 / 16) take the split sums as well.
 // Integer addition is associative, so the spread is bitwise deterministic.
 //
 // Bank conflicts.  A wave's 64 lanes add the same footprint offset to 64
@@ -117,6 +122,21 @@ __device__ inline unsigned long long term(float ar, float ai, float k) {
     return (((unsigned long long)__float_as_uint(yi) << 32) | __float_as_uint(yr)) - kMagic2;
 }
 
+// round(a k 2^20) as a 64-bit integer to within one unit, for |a k| < 2^22 (the
+// split sums of crowded or high-dynamic-range tiles): round(a k) from the FMA above,
+// then the remainder a k - round(a k) (|.| <= 1/2, formed exactly by a second FMA and
+// rounded once to FP32) scaled by 2^20 and rounded the same way.  Both roundings are
+// to nearest even, so the terms stay unbiased.
+__device__ inline unsigned long long term42(float a, float k) {
+    const float y = __builtin_fmaf(a, k, kMagic);
+    const float h = y - kMagic;
+    const float r = __builtin_fmaf(a, k, -h);
+    const float z = __builtin_fmaf(r, 0x1p20f, kMagic);
+    const long long hi = (int)(__float_as_uint(y) - kMagicBits);
+    const long long lo = (int)(__float_as_uint(z) - kMagicBits);
+    return (unsigned long long)(hi * (1ll << 20) + lo);
+}
+
 __device__ inline void unpack2(unsigned long long v, int &re, int &im) {
     re = (int)(unsigned)(v & 0xffffffffull);
     im = (int)(unsigned)((v - (unsigned long long)(long long)re) >> 32);
@@ -179,7 +199,7 @@ __device__ inline void accumulate(unsigned long long *row, float4 d, bool packed
             for (int i = 0; i < W; ++i) atomicAdd(row + jy * PITCH + i, term(ar, ai, kx[i]));
         } else {
 #pragma unroll
-            for (int i = 0; i < W; ++i) atomicAdd(row + jy * PITCH + i, term1(ar, kx[i]));
+            for (int i = 0; i < W; ++i) atomicAdd(row + jy * PITCH + i, term42(ar, kx[i]));
         }
     }
 }
@@ -228,6 +248,25 @@ __device__ inline void write_tile(const unsigned long long *acc, float2 *__restr
     }
 }
 
+// A tile whose records' energy sits in a few of them: sum |c|^2 < nrec M^2 / 16, with
+// M the largest |Re c|, |Im c|.  The packed sums round every term to 2^-21 M (or
+// 2^-22 M), which costs the tile a relative error of about 9e-7 sqrt(nrec M^2 / sum
+// |c|^2) of its own energy: about 1.5e-6 for a tile of random phases and amplitudes,
+// but 2e-5 for one bright point among 500 points 1e4 times weaker.  Above the
+// threshold (at most 3.6e-6) the tile uses the split sums with 42-bit terms.
+__device__ inline bool high_dynamic_range(uint32_t nrec, float big, float ssum) {
+    return big > 0.f && (double)nrec * (double)big * (double)big > 16.0 * (double)ssum;
+}
+
+// Exponent bound of the terms of a split tile: each record adds at most one term
+// to a cell, so a cell sum of nrec terms below 2^(emax + 20) (term42) stays below
+// 2^62 when emax + 20 + log2(nrec) <= 62.
+__device__ inline int split_emax(uint32_t nrec) {
+    int lg = 0;
+    while (lg < 32 && (1u << lg) < nrec) ++lg;
+    return min(22, 42 - lg);
+}
+
 template <int W>
 __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadParams p, Binned b,
                                                           const float2 *__restrict__ u1,
@@ -242,6 +281,7 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
     __shared__ int sbase[kChunk + 16];                   // their padded start cell
     __shared__ unsigned rcount[16];                      // records per start residue
     __shared__ unsigned sbig, smost;                     // block maxima
+    __shared__ float ssum;                               // sum of |c|^2 over the tile's records
     int *starts = reinterpret_cast<int *>(sdat);         // footprint-start histogram (phase A)
 
     const int t = blockIdx.x;
@@ -269,7 +309,10 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
         if (!few)
             for (int i = tid; i < swx * swy; i += nt) starts[i] = 0;
         if (tid < 16) rcount[tid] = 0u;
-        if (tid == 0) sbig = smost = 0u;
+        if (tid == 0) {
+            sbig = smost = 0u;
+            ssum = 0.f;
+        }
     }
     Batch r;
     int rb[kBatch];   // padded start cell of each record, -1 if it does not touch the tile
@@ -279,6 +322,7 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
     // footprint starts per position).  A tile of at most kBatch * nt records
     // keeps them in registers for phase B; larger tiles reload them there.
     float big = 0.f;
+    float en = 0.f;
     for (uint32_t base = s0; base < s1; base += per_batch) {
         load_records(r, b, base + tid, s1, nt);
         gather_u(r, u1, p.n);
@@ -289,14 +333,21 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
             if (r.j[k] < p.n && local_start(r.cell[k], x0, y0, PAD, hix, hiy, p.nfx, p.nfy, px, py)) {
                 rb[k] = py * PITCH + px;
                 big = fmaxf(big, fmaxf(fabsf(r.pc[k].x), fabsf(r.pc[k].y)));
+                en = __builtin_fmaf(r.pc[k].x, r.pc[k].x, __builtin_fmaf(r.pc[k].y, r.pc[k].y, en));
                 if (!few) atomicAdd(&starts[py * swx + px], 1);
             }
         }
     }
-    // block maximum: non-negative floats order like their bit patterns
+    // block maximum (non-negative floats order like their bit patterns) and energy
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) big = fmaxf(big, __shfl_xor(big, off));
-    if (lane == 0) atomicMax(&sbig, __float_as_uint(big));
+    for (int off = 32; off > 0; off >>= 1) {
+        big = fmaxf(big, __shfl_xor(big, off));
+        en += __shfl_xor(en, off);
+    }
+    if (lane == 0) {
+        atomicMax(&sbig, __float_as_uint(big));
+        atomicAdd(&ssum, en);
+    }
     __syncthreads();               // sbig and starts[] complete
     big = __uint_as_float(sbig);
     bool packed;
@@ -315,6 +366,10 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
         packed = smost * (unsigned)(W * W) <= 511u && !fold_x && !fold_y;
         emax = 22;
     }
+    // a few records dominating the tile's energy: the others would be rounded on the
+    // dominant ones' grid, so the tile takes the split sums with 42-bit terms
+    if (high_dynamic_range(nrec, __uint_as_float(sbig), ssum)) packed = false;
+    if (!packed) emax = split_emax(nrec);
     int e = 0;
     if (big > 0.f) {
         int em;
@@ -323,7 +378,8 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
     }
     e = max(-120, min(e, 120));
     const float scale = ldexpf(1.f, e);
-    const float unscale = ldexpf(1.f, -e);
+    // split sums carry 20 more fractional bits (term42)
+    const float unscale = ldexpf(1.f, packed ? -e : -e - 20);
 
     // phase B: accumulate every footprint (split tiles: two sweeps, Re then Im)
     const int sweeps = packed ? 1 : 2;

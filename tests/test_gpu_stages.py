@@ -37,6 +37,31 @@ def _crowded():
     return synth.config("sinusoid_128")
 
 
+def _sparse():
+    """A 2048^2 destination (4096^2 fine grid, 8192 tiles, several per resident
+    workgroup) with 24 clusters of 1500 points, each cluster within a few tiles:
+    a workgroup walks many tiles, most of them empty, between the non-empty ones."""
+    rng = np.random.default_rng(31)
+    centres = rng.uniform(-5e-3, 5e-3, size=(24, 2))
+    x = (centres[:, 0, None] + rng.uniform(-4e-6, 4e-6, size=(24, 1500))).reshape(-1)
+    y = (centres[:, 1, None] + rng.uniform(-4e-6, 4e-6, size=(24, 1500))).reshape(-1)
+    d = synth.sinusoidal_relief(x, y, 20e-6, 0.8e-3)
+    n = x.size
+    u = (rng.uniform(0, 1, n) * np.exp(2j * np.pi * rng.uniform(0, 1, n))).astype(np.complex64)
+    return synth.Workload("sparse", x, y, d, u, 532e-9, 0.1, 80e-6, 80e-6, 2048, 2048)
+
+
+def _bright():
+    """One bright point over 256^2 points 1e4 times weaker (the tiles holding it take
+    the split sums with 42-bit terms)."""
+    base = synth.config("cap_2048", side=256, out=256)
+    rng = np.random.default_rng(17)
+    u = (1e-4 * synth.random_field(rng, 256, 256)).astype(np.complex64)
+    u[256 * 131 + 97] = 1.0
+    return synth.Workload("bright", base.x, base.y, base.d, u, base.lam, base.z0, base.p2x, base.p2y,
+                          base.mx, base.my)
+
+
 def _plan(torch, w, fft="fp32"):
     import paper_1203_3583_amd as asf
 
@@ -168,12 +193,16 @@ def _fine_natural(torch, plan, info):
     return v.reshape(nfx // C, nfy, C).transpose(1, 0, 2).reshape(nfy, nfx)
 
 
-@pytest.mark.parametrize("which", ["even", "crowded", "hot"])
+@pytest.mark.parametrize("which", ["even", "crowded", "hot", "sparse", "bright"])
 def test_spread_matches_host_sum(which):
-    """Even points (slab layout), the crowded relief (compact layout) and a small grid
-    whose tiles hold thousands of records (start histogram, record reloads)."""
+    """Even points (slab layout), the crowded relief (compact layout), a small grid
+    whose tiles hold thousands of records (start histogram, record reloads), a large
+    grid of mostly empty tiles (each workgroup walks many tiles) and a bright point
+    over a weak field (split sums with 42-bit terms).  The bar is relative to the
+    whole grid; for the bright point the weak field's own part of the grid (the cells
+    the bright point does not reach) is also checked against its own norm."""
     torch = torch_gpu()
-    w = {"even": _even, "crowded": _crowded, "hot": _hot}[which]()
+    w = {"even": _even, "crowded": _crowded, "hot": _hot, "sparse": _sparse, "bright": _bright}[which]()
     plan, u = _plan(torch, w)
     plan.forward(u)
     torch.cuda.synchronize()
@@ -195,6 +224,16 @@ def test_spread_matches_host_sum(which):
     err = rel_l2(fine, want)
     print(f"spread {which}: rel-L2 {err:.2e}")
     assert err <= 2e-6
+    if which == "bright":
+        # the weak field alone, away from the bright point's footprint: 42-bit terms
+        # keep its rounding far below the 2^-21 of the bright point's amplitude
+        j = int(np.argmax(np.abs(w.u)))
+        far = np.ones_like(want, dtype=bool)
+        for r in range(wid):
+            far[iy[j, r], ix[j, :]] = False
+        err_w = rel_l2(fine[far], want[far])
+        print(f"spread bright, weak cells: rel-L2 {err_w:.2e}")
+        assert err_w <= 2e-6
 
 
 def _psi_hat(m, nf, wid, beta):
