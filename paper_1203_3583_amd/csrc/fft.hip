@@ -37,6 +37,8 @@
 // accumulator's rows 4g..4g+3 are those outputs).  The K index of both operands
 // is permuted the same way, (r, re/im) <-> K slot, which the MFMA contraction
 // does not see.
+#include <type_traits>
+
 #include "asf_internal.h"
 
 namespace asf {
@@ -594,6 +596,220 @@ __global__ void __launch_bounds__(NT) fft_adj_cols_kernel(const float2 *__restri
     }
 }
 
+// ---- passes whose first and last stages touch global memory directly ----------
+// For lengths L = 16^a (256 and 4096 points: the first stage is a radix-16 stage)
+// the first stage's four inputs per lane are loaded from global memory straight
+// into the matrix-core lane layout, and the last stage's outputs (only the kept
+// modes) are stored straight to global memory: the data crosses LDS a - 1 times
+// instead of a + 1, with four barriers fewer per pass.
+
+// This lane's inputs of the first radix-16 stage: element j + (g + 4 i) L/16 of
+// transform c, read through load(c, e).
+template <int LOGL, int BATCH, int NT, class Load>
+__device__ __forceinline__ void first_inputs(Load load, float2 (&v)[StageBlocks<LOGL, BATCH, NT>::BPW][4]) {
+    using S = Len<LOGL>;
+    constexpr int BPW = StageBlocks<LOGL, BATCH, NT>::BPW;
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, jj = lane & 15, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+        const int q = (wave * BPW + b) * 16 + jj;
+        const int c = q >> S::LOGLQ, j = q & (S::LQ - 1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[b][i] = load(c, j + (g + 4 * i) * S::LQ);
+    }
+}
+
+// Inputs of a stage with span NS from LDS, times this stage's twiddles, through
+// the 16-point DFTs.
+template <int LOGL, int BATCH, int NT, int NS, class Engine>
+__device__ __forceinline__ void stage_read_run(const float2 *lds,
+                                               const float4 (&t)[StageBlocks<LOGL, BATCH, NT>::BPW][2],
+                                               float2 (&v)[StageBlocks<LOGL, BATCH, NT>::BPW][4],
+                                               const Engine &eng) {
+    using S = Len<LOGL>;
+    constexpr int BPW = StageBlocks<LOGL, BATCH, NT>::BPW;
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, jj = lane & 15, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+        const int q = (wave * BPW + b) * 16 + jj;
+        const int c = q >> S::LOGLQ, j = q & (S::LQ - 1);
+        const float2 *col = lds + c * S::STRIDE;
+        if constexpr (S::LQ >= 64) {
+            const float2 *src = col + lds_pos<S::PS>(j + g * S::LQ);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[b][i] = src[i * (4 * S::LQ + 64)];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[b][i] = col[lds_pos<S::PS>(j + (g + 4 * i) * S::LQ)];
+        }
+        if constexpr (NS > 1) {
+            v[b][0] = cmul(v[b][0], make_float2(t[b][0].x, t[b][0].y));
+            v[b][1] = cmul(v[b][1], make_float2(t[b][0].z, t[b][0].w));
+            v[b][2] = cmul(v[b][2], make_float2(t[b][1].x, t[b][1].y));
+            v[b][3] = cmul(v[b][3], make_float2(t[b][1].z, t[b][1].w));
+        }
+        eng.run(v[b]);
+    }
+}
+
+// A stage's outputs (span NS) to their Stockham positions in LDS.
+template <int LOGL, int BATCH, int NT, int NS>
+__device__ __forceinline__ void stage_write(float2 *lds, const float2 (&v)[StageBlocks<LOGL, BATCH, NT>::BPW][4]) {
+    using S = Len<LOGL>;
+    constexpr int BPW = StageBlocks<LOGL, BATCH, NT>::BPW;
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, jj = lane & 15, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+        const int q = (wave * BPW + b) * 16 + jj;
+        const int c = q >> S::LOGLQ, j = q & (S::LQ - 1);
+        const int k = j & (NS - 1);
+        const int base = (j - k) * 16 + k;
+        float2 *col = lds + c * S::STRIDE;
+        if constexpr (NS >= 64 && (4 * NS) % S::LQ == 0) {
+            float2 *dst = col + lds_pos<S::PS>(base + g * NS);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) dst[i * (4 * NS + ((4 * NS) >> S::PS) * 16)] = v[b][i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) col[lds_pos<S::PS>(base + (g + 4 * i) * NS)] = v[b][i];
+        }
+    }
+}
+
+// Stages STAGE .. a-1 (span 16^STAGE, twiddles tcur already in registers); the
+// last one hands its outputs to store(c, l, value): output l of transform c.
+template <int LOGL, int BATCH, int NT, int STAGE, class Engine, class Store>
+__device__ __forceinline__ void direct_rest(float2 *lds, const float4 *tw4, const Engine &eng,
+                                            const float4 (&tcur)[StageBlocks<LOGL, BATCH, NT>::BPW][2],
+                                            Store store, float unscale) {
+    using S = Len<LOGL>;
+    constexpr int BPW = StageBlocks<LOGL, BATCH, NT>::BPW;
+    constexpr int NS = 1 << (4 * STAGE);
+    float2 v[BPW][4];
+    stage_read_run<LOGL, BATCH, NT, NS, Engine>(lds, tcur, v, eng);
+    if constexpr (STAGE + 1 < S::N16) {
+        float4 tnext[BPW][2];
+        load_twiddles<LOGL, BATCH, NT, NS * 16>(stage_table<LOGL>(tw4, STAGE + 1), tnext);
+        __syncthreads();
+        stage_write<LOGL, BATCH, NT, NS>(lds, v);
+        __syncthreads();
+        direct_rest<LOGL, BATCH, NT, STAGE + 1, Engine, Store>(lds, tw4, eng, tnext, store, unscale);
+    } else {
+        // span NS = L/16: output p = g + 4 i of instance j is element j + p NS
+        const int lane = threadIdx.x & 63;
+        const int g = lane >> 4, jj = lane & 15, wave = threadIdx.x >> 6;
+#pragma unroll
+        for (int b = 0; b < BPW; ++b) {
+            const int q = (wave * BPW + b) * 16 + jj;
+            const int c = q >> S::LOGLQ, j = q & (S::LQ - 1);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                store(c, j + (g + 4 * i) * NS, make_float2(v[b][i].x * unscale, v[b][i].y * unscale));
+        }
+    }
+}
+
+// The workgroup's BATCH transforms of length L = 16^a: inputs through load(c, e),
+// the kept outputs through store(c, l, value).  With SPLIT the inputs are scaled by
+// the power of two that brings the workgroup's largest |Re|, |Im| to at most 1
+// (and the outputs scaled back).
+template <int LOGL, int BATCH, int NT, bool SPLIT, class Load, class Store>
+__device__ __forceinline__ void transform_direct(float2 *lds, const float2 *tw, const float2 *w16,
+                                                 float *scratch, Load load, Store store) {
+    using S = Len<LOGL>;
+    static_assert(S::R0 == 1 && S::N16 >= 2, "lengths 16^a, a >= 2");
+    constexpr int BPW = StageBlocks<LOGL, BATCH, NT>::BPW;
+    const float4 *tw4 = reinterpret_cast<const float4 *>(tw);
+    const int lane = threadIdx.x & 63;
+    float2 v[BPW][4];
+    first_inputs<LOGL, BATCH, NT>(load, v);
+    float4 t1[BPW][2];
+    load_twiddles<LOGL, BATCH, NT, 16>(stage_table<LOGL>(tw4, 1), t1);
+    float unscale = 1.f;
+    if constexpr (SPLIT) {
+        float big = 0.f;
+#pragma unroll
+        for (int b = 0; b < BPW; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) big = fmaxf(big, fmaxf(fabsf(v[b][i].x), fabsf(v[b][i].y)));
+        const int e = range_exponent(block_max(big, scratch));
+        const float inv = ldexpf(1.f, -e);
+        unscale = ldexpf(1.f, e);
+#pragma unroll
+        for (int b = 0; b < BPW; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[b][i] = make_float2(v[b][i].x * inv, v[b][i].y * inv);
+    }
+    using Engine = typename std::conditional<SPLIT, Dft16Split16, Dft16F32>::type;
+    Engine eng;
+    eng.init(w16, lane >> 4, lane & 15);
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) eng.run(v[b]);
+    stage_write<LOGL, BATCH, NT, 1>(lds, v);
+    __syncthreads();
+    direct_rest<LOGL, BATCH, NT, 1, Engine, Store>(lds, tw4, eng, t1, store, unscale);
+}
+
+// Pass 1 for L = 16^a: a workgroup transforms one panel of BATCH adjacent columns.
+template <int LOGL, int BATCH, int NT, bool SPLIT>
+__global__ void __launch_bounds__(NT) fft_pass1_direct_kernel(const float2 *__restrict__ fine,
+                                                              float2 *__restrict__ mid,
+                                                              const float2 *__restrict__ tw,
+                                                              const float2 *__restrict__ w16, int my) {
+    using S = Len<LOGL>;
+    extern __shared__ float2 lds[];
+    __shared__ float scratch[NT / 64];
+    const int pc = blockIdx.x;
+    const float2 *src = fine + (size_t)pc * S::L * BATCH;
+    float2 *dst = mid + (size_t)pc * my * BATCH;   // this panel's block of mid
+    const int half = my >> 1;
+    transform_direct<LOGL, BATCH, NT, SPLIT>(
+        lds, tw, w16, scratch, [&](int c, int e) { return src[e * BATCH + c]; },
+        [&](int c, int l, float2 val) {
+            const int ky = (l + half) & (S::L - 1);
+            if (ky < my) dst[ky * BATCH + c] = val;
+        });
+}
+
+// Pass 2 for L = 16^a: a workgroup transforms BATCH rows of mid; fused deconvolution
+// and destination phase (mx = L / 2).
+template <int LOGL, int BATCH, int NT, bool SPLIT>
+__global__ void __launch_bounds__(NT) fft_pass2_direct_kernel(const float2 *__restrict__ mid,
+                                                              float2 *__restrict__ u2,
+                                                              const float2 *__restrict__ tw,
+                                                              const float2 *__restrict__ w16,
+                                                              const float2 *__restrict__ dx,
+                                                              const float2 *__restrict__ dy, int my,
+                                                              int log_panel, int xcd_group, int accumulate) {
+    using S = Len<LOGL>;
+    extern __shared__ float2 lds[];
+    __shared__ float scratch[NT / 64];
+    int g = blockIdx.x;
+    if (xcd_group > 1) {
+        const int xcd = g & 7, slot = g >> 3;
+        g = ((slot / xcd_group) * 8 + xcd) * xcd_group + slot % xcd_group;
+    }
+    const int row0 = g * BATCH;
+    const int cmask = (1 << log_panel) - 1;
+    constexpr int MX = S::L / 2, HALF = MX / 2;
+    transform_direct<LOGL, BATCH, NT, SPLIT>(
+        lds, tw, w16, scratch,
+        [&](int c, int e) {
+            return mid[((((size_t)(e >> log_panel)) * my + row0 + c) << log_panel) + (e & cmask)];
+        },
+        [&](int c, int l, float2 val) {
+            const int ix = (l + HALF) & (S::L - 1);
+            if (ix < MX) {
+                float2 *o = u2 + (size_t)(row0 + c) * MX + ix;
+                const float2 r = cmul(cmul(val, dx[ix]), dy[row0 + c]);
+                *o = accumulate ? make_float2(o->x + r.x, o->y + r.y) : r;
+            }
+        });
+}
+
 // Kernels needing more than 64 KB of dynamic LDS must say so once per size.
 hipError_t allow_lds(const void *kernel, size_t lds, size_t &enabled) {
     if (lds > 65536 && lds > enabled) {
@@ -622,10 +838,17 @@ hipError_t launch1(const FftShape &sh, const float2 *fine, float2 *mid, const fl
     constexpr int NT = threads_for<LOGL, BATCH>();
     const size_t lds = (size_t)BATCH * Len<LOGL>::STRIDE * sizeof(float2);
     static thread_local size_t enabled = 0;
-    auto k = fft_pass1_kernel<LOGL, BATCH, NT, SPLIT>;
-    hipError_t e = allow_lds((const void *)k, lds, enabled);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(nfx / BATCH), dim3(NT), lds, s, fine, mid, tw, w16, my);
+    if constexpr (LOGL % 4 == 0 && LOGL >= 8) {
+        auto k = fft_pass1_direct_kernel<LOGL, BATCH, NT, SPLIT>;
+        hipError_t e = allow_lds((const void *)k, lds, enabled);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, dim3(nfx / BATCH), dim3(NT), lds, s, fine, mid, tw, w16, my);
+    } else {
+        auto k = fft_pass1_kernel<LOGL, BATCH, NT, SPLIT>;
+        hipError_t e = allow_lds((const void *)k, lds, enabled);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, dim3(nfx / BATCH), dim3(NT), lds, s, fine, mid, tw, w16, my);
+    }
     return hipGetLastError();
 }
 
@@ -636,16 +859,25 @@ hipError_t launch2(const FftShape &sh, const float2 *mid, float2 *u2, const floa
     constexpr int NT = threads_for<LOGL, BATCH>();
     const size_t lds = (size_t)BATCH * Len<LOGL>::STRIDE * sizeof(float2);
     static thread_local size_t enabled = 0;
-    auto k = fft_pass2_kernel<LOGL, BATCH, NT, SPLIT>;
-    hipError_t e = allow_lds((const void *)k, lds, enabled);
-    if (e != hipSuccess) return e;
     (void)sh;
     const int groups = my / BATCH;
     const int rows_per_line = 16 >> log_panel;   // rows of mid that share a 128-byte line
     const int g = rows_per_line > BATCH ? rows_per_line / BATCH : 1;
     const int xcd_group = (g > 1 && groups % (8 * g) == 0) ? g : 1;
-    hipLaunchKernelGGL(k, dim3(groups), dim3(NT), lds, s, mid, u2, tw, w16, dx, dy, mx, my, log_panel,
-                       xcd_group, accumulate);
+    if constexpr (LOGL % 4 == 0 && LOGL >= 8) {
+        auto k = fft_pass2_direct_kernel<LOGL, BATCH, NT, SPLIT>;
+        hipError_t e = allow_lds((const void *)k, lds, enabled);
+        if (e != hipSuccess) return e;
+        if (mx != Len<LOGL>::L / 2) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k, dim3(groups), dim3(NT), lds, s, mid, u2, tw, w16, dx, dy, my, log_panel,
+                           xcd_group, accumulate);
+    } else {
+        auto k = fft_pass2_kernel<LOGL, BATCH, NT, SPLIT>;
+        hipError_t e = allow_lds((const void *)k, lds, enabled);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, dim3(groups), dim3(NT), lds, s, mid, u2, tw, w16, dx, dy, mx, my, log_panel,
+                           xcd_group, accumulate);
+    }
     return hipGetLastError();
 }
 
@@ -775,19 +1007,6 @@ size_t fft_lds_bytes(int len, int batch) {
     const int lq = len / 16;
     const int ps = lq > 16 ? log - 4 : 4;
     return (size_t)batch * (len + (len >> ps) * 16) * sizeof(float2);
-}
-
-size_t fft_twiddle_entries(int len) {
-    // stages with span NS > 1 store 16 NS entries each
-    const int log = __builtin_ctz(len);
-    const int r0 = 1 << (log % 4);
-    const int n16 = log / 4;
-    size_t total = 0;
-    for (int s = 0; s < n16; ++s) {
-        const int ns = r0 << (4 * s);
-        if (ns > 1) total += 16 * (size_t)ns;
-    }
-    return total;
 }
 
 int fft_max_lds_bytes() {
