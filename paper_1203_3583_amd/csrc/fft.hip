@@ -17,26 +17,32 @@
 // A workgroup holds `batch` whole transforms in LDS.  Each transform of length
 // L = r0 * 16^a (a compile-time constant here, so every index is a shift or a
 // constant offset) runs as Stockham stages: one radix-r0 stage (r0 in
-// {1,2,4,8}) on the vector ALU, then a radix-16 stages.  In a radix-16 stage
-// the 16-point DFTs of 16 transform instances form one small GEMM
+// {1,2,4,8}) on the vector ALU, then a radix-16 stages, each a 16-point DFT of
+// 16 transform instances per wave and block, in one of two engines:
+//   FP32 (vector ALU): 4 x 4 -- a 4-point DFT over the four inputs a lane
+//     holds, twiddles W16^(g k1), a transpose of the block's four 16-lane rows
+//     by lane swaps, a second 4-point DFT (about 50 operations per lane);
+//   split FP16 (matrix cores): the 16-point DFT as one small GEMM
 //     [Re Y; Im Y] (32 x 16) = W16 (32 x 32 real form of the DFT matrix) x [Re X; Im X] (32 x 16)
-// on the matrix cores, either with FP32 products (v_mfma_f32_16x16x4_f32, 8
-// K-steps per output half) or with FP16 hi+lo split products
-// (v_mfma_f32_16x16x32_f16: W_hi X_hi + W_hi X_lo + W_lo X_hi, FP32
-// accumulation).  For the split products the workgroup scales its data once,
-// at load, by a power of two that brings the largest |Re|, |Im| to at most 1:
-// FP16 carries its own exponent, so the scale only guards the range, and a
-// transform of length L grows values by at most L <= 16384 < 65504.
+//     with FP16 hi+lo split products (v_mfma_f32_16x16x32_f16: W_hi X_hi +
+//     W_hi X_lo + W_lo X_hi, FP32 accumulation).  The workgroup scales its data
+//     once, at load, by a power of two that brings the largest |Re|, |Im| to at
+//     most 1: FP16 carries its own exponent, so the scale only guards the
+//     range, and a transform of length L grows values by at most L <= 16384 <
+//     65504.
+// On gfx950 the FP32 matrix rate equals the FP32 vector rate, and a dense
+// 16-point DFT costs about six times the operations of the 4 x 4 network, so
+// FP32 products stay on the vector ALU.
 // Twiddles are applied in FP32 on the vector ALU before each stage's DFT, from
 // FP64-computed tables laid out [k][lane group][4] so that a lane fetches its
 // four twiddles with two 16-byte loads.
 //
 // Lane layout of one 16-instance block (wave64): lane = 16 g + jj holds instance
-// jj's inputs r = g, g+4, g+8, g+12 and, after the MFMAs, its outputs
-// p = g, g+4, g+8, g+12 (the DFT matrix rows are permuted so that the 16 x 16
-// accumulator's rows 4g..4g+3 are those outputs).  The K index of both operands
-// is permuted the same way, (r, re/im) <-> K slot, which the MFMA contraction
-// does not see.
+// jj's inputs r = g, g+4, g+8, g+12 and, after the DFT, its outputs
+// p = g, g+4, g+8, g+12 (for the GEMM the DFT matrix rows are permuted so that
+// the 16 x 16 accumulator's rows 4g..4g+3 are those outputs, and the K index of
+// both operands is permuted the same way, (r, re/im) <-> K slot, which the
+// contraction does not see).
 #include <type_traits>
 
 #include "asf_internal.h"
@@ -72,28 +78,53 @@ __device__ __forceinline__ int lds_pos(int e) {
     return (e ^ ((e >> 4) & 15)) + ((e >> PS) << 4);
 }
 
-struct Dft16F32 {
-    float are[8], aim[8];
-    __device__ __forceinline__ void init(const float2 *w16, int g, int jj) {
-        const int p = (jj >> 2) + 4 * (jj & 3);
-#pragma unroll
-        for (int kb = 0; kb < 8; ++kb) {
-            const int r = g + 4 * (kb >> 1);
-            const float2 w = w16[(p * r) & 15];
-            are[kb] = (kb & 1) ? -w.y : w.x;
-            aim[kb] = (kb & 1) ? w.x : w.y;
-        }
+// 16-point DFTs on the vector ALU in FP32, as 4 x 4 (r = g + 4 i,
+// p = k1 + 4 k2):
+//   Y[k1 + 4 k2] = sum_g W4^(g k2) W16^(g k1) sum_i x[g + 4 i] W4^(i k1).
+// A lane holds x[g + 4 i] for i = 0..3, so the inner 4-point DFT and the twiddle
+// W16^(g k1) (g is the lane's row of 16 lanes) stay in its registers; a 4 x 4
+// transpose of (row, register) -- two v_permlane32_swap and two
+// v_permlane16_swap per real component -- gives row k1 the values of all four
+// g, and the outer 4-point DFT leaves Y[g + 4 k2] in register k2 of row g: the
+// layout the matrix-core engine produces.  About 50 VALU operations per lane and
+// block, where the same DFT as a GEMM takes 16 FP32 MFMAs of 32 cycles.
+struct Dft16Valu {
+    float2 w1, w2, w3;   // W16^g, W16^2g, W16^3g for this lane's row g
+    __device__ __forceinline__ void init(const float2 *w16, int g, int) {
+        w1 = w16[g & 15];
+        w2 = w16[(2 * g) & 15];
+        w3 = w16[(3 * g) & 15];
+    }
+    // forward 4-point DFT (W4 = -i) in place
+    static __device__ __forceinline__ void dft4(float2 (&v)[4]) {
+        const float2 a0 = make_float2(v[0].x + v[2].x, v[0].y + v[2].y);
+        const float2 a1 = make_float2(v[0].x - v[2].x, v[0].y - v[2].y);
+        const float2 a2 = make_float2(v[1].x + v[3].x, v[1].y + v[3].y);
+        const float2 a3 = make_float2(v[1].x - v[3].x, v[1].y - v[3].y);
+        v[0] = make_float2(a0.x + a2.x, a0.y + a2.y);
+        v[2] = make_float2(a0.x - a2.x, a0.y - a2.y);
+        v[1] = make_float2(a1.x + a3.y, a1.y - a3.x);   // a1 - i a3
+        v[3] = make_float2(a1.x - a3.y, a1.y + a3.x);   // a1 + i a3
+    }
+    // (row, register) transpose of one real component over the wave's four rows
+    static __device__ __forceinline__ void transpose4(float &r0, float &r1, float &r2, float &r3) {
+        auto s02 = __builtin_amdgcn_permlane32_swap(__float_as_uint(r0), __float_as_uint(r2), false, false);
+        auto s13 = __builtin_amdgcn_permlane32_swap(__float_as_uint(r1), __float_as_uint(r3), false, false);
+        auto s01 = __builtin_amdgcn_permlane16_swap(s02[0], s13[0], false, false);
+        auto s23 = __builtin_amdgcn_permlane16_swap(s02[1], s13[1], false, false);
+        r0 = __uint_as_float(s01[0]);
+        r1 = __uint_as_float(s01[1]);
+        r2 = __uint_as_float(s23[0]);
+        r3 = __uint_as_float(s23[1]);
     }
     __device__ __forceinline__ void run(float2 (&v)[4]) const {
-        v4f accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kb = 0; kb < 8; ++kb) {
-            const float b = (kb & 1) ? v[kb >> 1].y : v[kb >> 1].x;
-            accr = __builtin_amdgcn_mfma_f32_16x16x4f32(are[kb], b, accr, 0, 0, 0);
-            acci = __builtin_amdgcn_mfma_f32_16x16x4f32(aim[kb], b, acci, 0, 0, 0);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) v[i] = make_float2(accr[i], acci[i]);
+        dft4(v);
+        v[1] = cmul(v[1], w1);
+        v[2] = cmul(v[2], w2);
+        v[3] = cmul(v[3], w3);
+        transpose4(v[0].x, v[1].x, v[2].x, v[3].x);
+        transpose4(v[0].y, v[1].y, v[2].y, v[3].y);
+        dft4(v);
     }
 };
 
@@ -333,9 +364,9 @@ __device__ __forceinline__ void transform_all(float2 *lds, const float2 *tw, con
         eng.init(w16s, lane >> 4, lane & 15);
         stages_from<LOGL, BATCH, NT, 0, true, Dft16Split16>(lds, tw4, eng, t0, inv);
     } else {
-        Dft16F32 eng;
+        Dft16Valu eng;
         eng.init(w16s, lane >> 4, lane & 15);
-        stages_from<LOGL, BATCH, NT, 0, false, Dft16F32>(lds, tw4, eng, t0, inv);
+        stages_from<LOGL, BATCH, NT, 0, false, Dft16Valu>(lds, tw4, eng, t0, inv);
     }
 }
 
@@ -743,7 +774,7 @@ __device__ __forceinline__ void transform_direct(float2 *lds, const float2 *tw, 
 #pragma unroll
             for (int i = 0; i < 4; ++i) v[b][i] = make_float2(v[b][i].x * inv, v[b][i].y * inv);
     }
-    using Engine = typename std::conditional<SPLIT, Dft16Split16, Dft16F32>::type;
+    using Engine = typename std::conditional<SPLIT, Dft16Split16, Dft16Valu>::type;
     Engine eng;
     eng.init(w16, lane >> 4, lane & 15);
 #pragma unroll
