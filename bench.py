@@ -38,7 +38,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "spread_cap_2048_traffic.txt")
-PROFILE_MFMA = os.path.join(ROOT, "profiles", "fft_mfma_cap_2048.txt")
+PROFILE_FFT = os.path.join(ROOT, "profiles", "fft_counters_cap_2048.txt")
 CSRC = os.path.join(ROOT, "paper_1203_3583_amd", "csrc")
 SPREAD_SOURCE = os.path.join(CSRC, "spread.hip")
 FFT_SOURCE = os.path.join(CSRC, "fft.hip")
@@ -92,18 +92,19 @@ def stored_traffic():
         return None
 
 
-def stored_mfma():
-    """Matrix-core utilisation of the FFT passes from the committed counter summary
-    (SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE and the CU count), if it was taken
-    on the current FFT source (else None)."""
-    fields = _summary_fields(PROFILE_MFMA)
+def stored_fft_busy():
+    """Busy fraction of the unit each FFT pass computes on, from the committed counter
+    summary (FP32 passes: vector ALU, SQ_ACTIVE_INST_VALU; split-FP16 passes: matrix
+    cores, SQ_VALU_MFMA_BUSY_CYCLES; each over GRBM_GUI_ACTIVE and the SIMD count),
+    if it was taken on the current FFT source (else None)."""
+    fields = _summary_fields(PROFILE_FFT)
     if fields.get("fft_source_sha256") != _sha(FFT_SOURCE):
         return None
     out = {}
     for k, v in fields.items():
-        if k.startswith("mfma_busy_"):
+        if k.startswith("busy_"):
             try:
-                out[k[len("mfma_busy_"):]] = float(v)
+                out[k[len("busy_"):]] = float(v)
             except ValueError:
                 pass
     return out or None
@@ -402,8 +403,9 @@ def main():
             "bytes_model": "28 B per point (u1 8 + record 20) + 8 B per fine cell",
             "avg_launch_ms": spread_ms,
         },
-        # matrix-core busy fraction of the FFT passes, from the committed counter summary
-        "fft_mfma_util": stored_mfma() if args.workload == "cap_2048" else None,
+        # busy fraction of the FFT passes' compute unit (vector ALU for FP32, matrix
+        # cores for split FP16), from the committed counter summary
+        "fft_unit_busy": stored_fft_busy() if args.workload == "cap_2048" else None,
         # rel-L2 against the FP64 oracle on the stored evaluation sets (both precisions)
         "rel_l2_eval_sets": eval_set_errors(args.workload, {k: v["u2"] for k, v in results.items()}),
         "cpu_baseline": None,

@@ -49,8 +49,8 @@ extern "C" {
 #define ASF_ENOSYS (-6)   /* operation not implemented */
 
 /* ---- flags ----------------------------------------------------------------- */
-#define ASF_FFT_FP32 0u             /* FFT stages: FP32 products on MFMA, FP32 accumulation */
-#define ASF_FFT_SPLIT_FP16 1u       /* FFT stages: FP16 hi+lo split products on MFMA, FP32 accumulation */
+#define ASF_FFT_FP32 0u             /* FFT stages: FP32 radix-4 x 4 on the vector ALU */
+#define ASF_FFT_SPLIT_FP16 1u       /* FFT stages: DFT-16 GEMMs of FP16 hi+lo split products on MFMA, FP32 accumulation */
 #define ASF_FFT_MASK 1u
 /* size of the fixed device scratch array used by asf_forward_static (per GPU) */
 #define ASF_STATIC_SCRATCH_BYTES ((size_t)48 << 20)
@@ -105,6 +105,12 @@ typedef struct {
        slot count); a tile's records are slab.first .. + min(count, slab.count) unless
        status bit 2 says the compact layout (tile_start) is in use */
     size_t off_cursor, off_slab;
+    /* crowded tiles cut into slices of records (u32 [ntiles]: 0, or first partial slot
+       << 8 | slices, meaningful for tiles of more records than split_meta[0]; u32 [2]:
+       that threshold and the partial slots in use; u32 [512]: tile << 8 | slice per
+       slot), and the resident workgroups the cut is sized against (0: never cut) */
+    size_t off_split, off_split_meta, off_slot_owner;
+    uint32_t split_slots;
 } asf_info;
 
 /*

@@ -55,7 +55,9 @@ class Info(ctypes.Structure):
                 ("off_phase", ctypes.c_size_t), ("off_perm", ctypes.c_size_t),
                 ("off_fine", ctypes.c_size_t), ("off_mid", ctypes.c_size_t),
                 ("ws_bytes", ctypes.c_size_t), ("off_cursor", ctypes.c_size_t),
-                ("off_slab", ctypes.c_size_t)]
+                ("off_slab", ctypes.c_size_t), ("off_split", ctypes.c_size_t),
+                ("off_split_meta", ctypes.c_size_t), ("off_slot_owner", ctypes.c_size_t),
+                ("split_slots", ctypes.c_uint32)]
 
 
 class LineParams(ctypes.Structure):

@@ -33,6 +33,7 @@ int hip_fail(hipError_t e, const char *what) {
     return fail(ASF_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+static_assert(asf::kSplitSlots == kSplitSlotsHost, "partial-tile slots");
 static_assert(sizeof(Cf) == sizeof(float2), "host complex values are laid out like float2");
 
 }  // namespace
@@ -51,6 +52,7 @@ struct asf_plan_s {
     bool sized_slabs;   // the slabs were sized from a crowded binning's counts
     int copy;           // which copy of status and cursor the last binning used
     bool clear_both;    // clear both copies first (new plan, or a failed binning launch)
+    uint32_t slots;     // workgroups resident at once (crowded tiles are cut against it); 0: never cut
     bool events;
     hipEvent_t ev[2 * asf::NSTAGES];
     bool recorded[asf::NSTAGES];
@@ -116,7 +118,7 @@ int geometry_launches(asf_plan_s *p, const double *x, const double *y, const dou
     // compact layout: both kernels return at once when the slabs held
     {
         StageMark m(p, asf::STAGE_SCAN, s);
-        e = asf::launch_bin_scan(p->bin, p->lay.ntiles, s);
+        e = asf::launch_bin_scan(p->bin, p->lay.ntiles, p->slots, s);
         if (e != hipSuccess) return hip_fail(e, "bin_scan launch");
     }
     {
@@ -247,6 +249,11 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
     pl->bin.rec = reinterpret_cast<float4 *>(w + L.off_frac);
     pl->bin.slab = reinterpret_cast<uint2 *>(w + L.off_slab);
     pl->bin.slot_cap = (uint32_t)L.slot_cap;
+    pl->bin.split = reinterpret_cast<uint32_t *>(w + L.off_split);
+    pl->bin.split_meta = reinterpret_cast<uint32_t *>(w + L.off_split_meta);
+    pl->bin.slot_owner = reinterpret_cast<uint32_t *>(w + L.off_slot_owner);
+    pl->bin.combine = reinterpret_cast<uint32_t *>(w + L.off_combine);
+    pl->bin.partial = reinterpret_cast<unsigned long long *>(w + L.off_partial);
     pl->fine = reinterpret_cast<float2 *>(w + L.off_fine);
     pl->mid = reinterpret_cast<float2 *>(w + L.off_mid);
     pl->dx = reinterpret_cast<float2 *>(w + L.off_dx);
@@ -298,6 +305,15 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
     pl->sp.nty = L.nty;
     pl->sp.log_panel = log2i(panel);
     pl->sp.beta_log2e = (float)(L.beta * 1.4426950408889634);
+    pl->sp.split = L.split ? 1 : 0;
+    // three spreading workgroups fit a compute unit at once
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+        (void)hipGetLastError();
+        cus = 256;
+    }
+    pl->slots = L.split ? 3u * (uint32_t)cus : 0u;
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = upload_tables(pl, s);
@@ -438,6 +454,10 @@ int asf_plan_info(asf_plan_t plan, asf_info *info) {
     info->ws_bytes = L.total;
     info->off_cursor = plan->copy ? L.off_cursor2 : L.off_cursor;
     info->off_slab = L.off_slab;
+    info->off_split = L.off_split;
+    info->off_split_meta = L.off_split_meta;
+    info->off_slot_owner = L.off_slot_owner;
+    info->split_slots = plan->slots;
     return ASF_OK;
 }
 

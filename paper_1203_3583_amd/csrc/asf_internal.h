@@ -31,7 +31,28 @@ struct Binned {
     // binning pass clears it, so that a binning needs no clearing launch of its own
     uint32_t *next_status;
     uint32_t *next_cursor;
+    // Slices of crowded tiles (written by every binning's scan, read by spreading and
+    // interpolation).  A tile whose record count exceeds split_meta[0] is cut into
+    // split[t] & 255 slices of consecutive records if split[t] != 0 (slots
+    // split[t] >> 8 onward of the partial tiles); slot_owner[q] = t << 8 | slice
+    // for the split_meta[1] slots in use.
+    uint32_t *split;       // [ntiles]
+    uint32_t *split_meta;  // [2] record threshold, slots in use
+    uint32_t *slot_owner;  // [kSplitSlots]
+    uint32_t *combine;     // [kSplitSlots] slices finished per split tile (zero between launches)
+    unsigned long long *partial;   // [kSplitSlots][2][tile cells] integer sums of the slices (Re, Im),
+                                   // in write-out order
 };
+
+// Crowded tiles.  A tile holding more than max(kSplitMinRecords, 2 R / slots)
+// records (R: all records, slots: workgroups resident on the device at once) is
+// cut into up to kSplitMaxSlices slices of at least kSliceMinRecords records, so
+// a few tiles holding most of the points no longer run serially.
+constexpr int kSplitSlots = 512;
+constexpr int kSplitMaxSlices = 32;
+constexpr uint32_t kSplitMinRecords = 2048;
+constexpr uint32_t kSliceMinRecords = 256;
+constexpr uint32_t kNoSplit = 0xffffffffu;   // split_meta[0] when no tile is cut
 
 constexpr uint32_t kStatusDomain = 1u;    // some point has r0 <= 0 or a non-finite coordinate
 constexpr uint32_t kStatusOverflow = 2u;  // compact layout ran out of slots (internal error)
@@ -48,6 +69,39 @@ __device__ inline void tile_slots(const Binned &b, int t, uint32_t &s0, uint32_t
         s0 = sl.x;
         s1 = s0 + min(b.cursor[t], sl.y);
     }
+}
+
+// Workgroup blockIdx.x of a spreading or interpolation launch of ntiles + kSplitSlots
+// workgroups: the tile it takes and its records [s0, s1); slice and slices (1 if
+// the tile is not cut) and the first partial slot of the tile.  False if the
+// workgroup has nothing to do (uniform over the workgroup).
+__device__ inline bool tile_work(const Binned &b, int ntiles, int &t, uint32_t &slice, uint32_t &nsl,
+                                 uint32_t &slot, uint32_t &s0, uint32_t &s1) {
+    t = blockIdx.x;
+    slice = 0;
+    nsl = 1;
+    slot = 0;
+    if (t >= ntiles) {
+        const uint32_t q = (uint32_t)(t - ntiles);
+        if (q >= b.split_meta[1]) return false;
+        const uint32_t own = b.slot_owner[q];
+        slice = own & 255u;
+        if (slice == 0) return false;   // slice 0 is the tile's own workgroup
+        t = (int)(own >> 8);
+    }
+    tile_slots(b, t, s0, s1);
+    if (s1 - s0 > b.split_meta[0]) {
+        const uint32_t sp = b.split[t];
+        if (sp) {
+            nsl = sp & 255u;
+            slot = sp >> 8;
+            const uint32_t len = (s1 - s0 + nsl - 1) / nsl;
+            const uint32_t a = s0 + min(s1 - s0, slice * len);
+            s1 = a + min(s1 - a, len);
+            s0 = a;
+        }
+    }
+    return true;
 }
 
 // Scalars the geometry kernels need (all FP64 where the paper's phases live).
@@ -70,6 +124,7 @@ struct SpreadParams {
     int log_tile_x, log_tile_y, log_ntx;   // tile edges and tiles per row, as powers of two
     int log_panel;     // fine-grid panel width (columns stored contiguously per row), log2
     float beta_log2e;  // ES shape beta times log2(e), for exp2
+    int split;         // 1: crowded tiles may be cut (launches take kSplitSlots more workgroups)
 };
 
 // One batch of same-length FFTs.  In the first pass (along y) a workgroup
@@ -125,7 +180,8 @@ hipError_t launch_bin_count(const GeoParams &g, const Binned &b, int64_t n, cons
 // crowded: slabs sized from a compact binning's counts (fewer workgroups at a time)
 hipError_t launch_bin_fill(const GeoParams &g, const Binned &b, int64_t n, const double *x,
                            const double *y, const double *d, bool crowded, hipStream_t s);
-hipError_t launch_bin_scan(const Binned &b, int ntiles, hipStream_t s);
+// (and the slices of crowded tiles: slots = workgroups resident at once, 0 = never cut)
+hipError_t launch_bin_scan(const Binned &b, int ntiles, uint32_t slots, hipStream_t s);
 // (and, in every launch, clears next_status and next_cursor)
 hipError_t launch_bin_scatter(const GeoParams &g, const Binned &b, int64_t n, int ntiles, const double *x,
                               const double *y, const double *d, hipStream_t s);

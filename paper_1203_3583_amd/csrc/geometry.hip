@@ -30,7 +30,10 @@
 // grid), the compact layout is built instead: an exclusive scan of the per-tile
 // counts, then a second pass that packs the records in tile order.  The scan
 // and that pass are always launched and return at once when the slabs held, so
-// the host never waits for the decision.  The scan also sizes new slabs from
+// the host never waits for the decision (the scan first cuts crowded tiles into
+// slices of records for the spreading kernel, from the counts of either layout:
+// a tile far above the mean load of a resident workgroup would otherwise run
+// alone long after the rest of the grid).  The scan also sizes new slabs from
 // the counts (a quarter and 16 slots of headroom each) for the next binning; a
 // plan whose last synchronised binning needed the compact layout bins into
 // those if they fit, and otherwise counts first (a lighter pass than a slab
@@ -125,11 +128,17 @@ __device__ inline WaveGroup wave_group(int key, bool active) {
     return g;
 }
 
-// Both copies of the counters (at plan creation, and after a failed launch)
+// Both copies of the counters (at plan creation, and after a failed launch), and
+// the slice counters of cut tiles
 __global__ void __launch_bounds__(256) bin_reset_kernel(Binned b, int ntiles) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < ntiles) b.cursor[i] = b.next_cursor[i] = 0u;
-    if (i == 0) b.status[0] = b.next_status[0] = 0u;
+    if (i < kSplitSlots) b.combine[i] = 0u;
+    if (i == 0) {
+        b.status[0] = b.next_status[0] = 0u;
+        b.split_meta[0] = kNoSplit;
+        b.split_meta[1] = 0u;
+    }
 }
 
 constexpr int kGeoThreads = 256;
@@ -302,9 +311,9 @@ __device__ inline uint32_t slab_want(uint32_t count) {
     return w < 0xfffffff0ull ? (uint32_t)w : 0xfffffff0u;
 }
 
-// Exclusive scan of f(cursor[t]) over the tiles in 64-bit sums; calls put(t,
-// start, value) for each tile and returns the total.  Every thread of the block
-// must call it.
+// Exclusive scan of f(t) over the tiles in 64-bit sums; calls put(t, start,
+// value) for each tile and returns the total.  Every thread of the block must
+// call it.
 template <class F, class P>
 __device__ inline uint64_t block_scan(const Binned &b, int ntiles, uint64_t *wsum, F f, P put) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -315,7 +324,7 @@ __device__ inline uint64_t block_scan(const Binned &b, int ntiles, uint64_t *wsu
         uint64_t s = 0;
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
-            v[k] = lo + k < ntiles ? f(b.cursor[lo + k]) : 0u;
+            v[k] = lo + k < ntiles ? f(lo + k) : 0u;
             s += v[k];
         }
         uint64_t inc = s;   // inclusive scan within the wave
@@ -348,20 +357,120 @@ __device__ inline uint64_t block_scan(const Binned &b, int ntiles, uint64_t *wsu
     return carry;
 }
 
-__global__ void __launch_bounds__(kScanThreads) bin_scan_kernel(Binned b, int ntiles) {
+// Slices of crowded tiles, from the binning's record counts.  The spreading and
+// interpolation launches have ntiles + kSplitSlots workgroups; a tile is cut when
+// its count exceeds max(kSplitMinRecords, 2 R / slots) -- R records over the
+// slots workgroups resident at once -- into ceil(count / len) slices (at most
+// kSplitMaxSlices) of len = max(kSliceMinRecords, R / slots) records.  Cut tiles
+// take partial-tile slots in tile order; if they would need more than kSplitSlots,
+// len doubles until they do not.
+template <class C>
+__device__ inline void split_plan(const Binned &b, int ntiles, uint32_t slots, uint64_t *wsum,
+                                  uint32_t *wmax, C count) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    if (slots == 0) {   // grids whose tiles are never cut
+        if (t == 0) {
+            b.split_meta[0] = kNoSplit;
+            b.split_meta[1] = 0u;
+        }
+        return;
+    }
+    uint64_t r = 0;
+    uint32_t most = 0;
+    const bool compact = (b.status[0] & kStatusCompact) != 0u;
+    for (int base = 0; base < ntiles; base += kScanThreads * kScanPer) {
+        // kScanPer tiles' counts and slab sizes in flight (indices clamped so that
+        // no load waits on a branch)
+        uint32_t cur[kScanPer], cap[kScanPer];
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            const int i = min(base + k * kScanThreads + t, ntiles - 1);
+            cur[k] = b.cursor[i];
+            cap[k] = b.slab[i].y;
+        }
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            const uint32_t c = base + k * kScanThreads + t < ntiles ? (compact ? cur[k] : min(cur[k], cap[k])) : 0u;
+            r += c;
+            most = max(most, c);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        r += __shfl_xor(r, off);
+        most = max(most, (uint32_t)__shfl_xor((int)most, off));
+    }
+    if (lane == 0) {
+        wsum[wave] = r;
+        wmax[wave] = most;
+    }
+    __syncthreads();
+    r = 0;
+    most = 0;
+    for (int k = 0; k < kScanThreads / 64; ++k) {
+        r += wsum[k];
+        most = max(most, wmax[k]);
+    }
+    __syncthreads();   // wsum is reused by the scans
+    const uint64_t load = (r + slots - 1) / slots;
+    const uint64_t thr64 = max((uint64_t)kSplitMinRecords, 2 * load);
+    if (most <= thr64) {
+        if (t == 0) {
+            b.split_meta[0] = kNoSplit;
+            b.split_meta[1] = 0u;
+        }
+        return;
+    }
+    const uint32_t thr = (uint32_t)thr64;   // < most
+    uint64_t len = max((uint64_t)kSliceMinRecords, load);
+    for (;;) {
+        const auto slices = [&](int i) -> uint32_t {
+            const uint32_t c = count(i);
+            if (c <= thr) return 0u;
+            const uint64_t ns = min((uint64_t)kSplitMaxSlices, (c + len - 1) / len);
+            return ns >= 2 ? (uint32_t)ns : 0u;
+        };
+        const uint64_t used = block_scan(b, ntiles, wsum, slices, [&](int i, uint64_t at, uint32_t ns) {
+            if (ns == 0) {
+                if (count(i) > thr) b.split[i] = 0u;   // crowded, but one slice
+                return;
+            }
+            if (at + ns > (uint64_t)kSplitSlots) return;   // redone with longer slices
+            b.split[i] = (uint32_t)at << 8 | ns;
+            for (uint32_t q = 0; q < ns; ++q) b.slot_owner[at + q] = (uint32_t)i << 8 | q;
+        });
+        if (used <= (uint64_t)kSplitSlots) {
+            if (t == 0) {
+                b.split_meta[0] = thr;
+                b.split_meta[1] = (uint32_t)used;
+            }
+            return;
+        }
+        len *= 2;
+    }
+}
+
+__global__ void __launch_bounds__(kScanThreads) bin_scan_kernel(Binned b, int ntiles, uint32_t slots) {
     __shared__ uint64_t wsum[kScanThreads / 64];
-    if (!(b.status[0] & kStatusCompact)) return;   // every slab held its tile
+    __shared__ uint32_t wmax[kScanThreads / 64];
+    const bool compact = (b.status[0] & kStatusCompact) != 0u;
+    // record counts: the compact layout's counting pass, or the slabs' cursors
+    // (past a full slab a cursor keeps counting records that were not written)
+    split_plan(b, ntiles, slots, wsum, wmax, [&](int i) -> uint32_t {
+        return compact ? b.cursor[i] : min(b.cursor[i], b.slab[i].y);
+    });
+    if (!compact) return;   // every slab held its tile
     // slabs for the next binning, written only if they fit (the total is uniform
     // over the block), then the compact layout itself (slot counts never exceed
     // 4 n < 2^32), which rewrites the counts as insertion cursors
-    const auto want = [](uint32_t c) { return slab_want(c); };
+    const auto want = [&](int i) { return slab_want(b.cursor[i]); };
     const uint64_t need = block_scan(b, ntiles, wsum, want, [](int, uint64_t, uint32_t) {});
     const bool fits = need <= (uint64_t)b.slot_cap;
     if (fits)
         block_scan(b, ntiles, wsum, want,
                    [&](int t, uint64_t start, uint32_t v) { b.slab[t] = make_uint2((uint32_t)start, v); });
     const uint64_t total = block_scan(
-        b, ntiles, wsum, [](uint32_t c) { return c; },
+        b, ntiles, wsum, [&](int i) { return b.cursor[i]; },
         [&](int t, uint64_t start, uint32_t) {
             b.tile_start[t] = (uint32_t)start;
             b.cursor[t] = (uint32_t)start;
@@ -391,7 +500,7 @@ __global__ void __launch_bounds__(kGeoThreads) bin_scatter_kernel(GeoParams g, B
 }  // namespace
 
 hipError_t launch_bin_reset(const Binned &b, int ntiles, hipStream_t s) {
-    const int blocks = (ntiles + 255) / 256;
+    const int blocks = ((ntiles > kSplitSlots ? ntiles : kSplitSlots) + 255) / 256;
     hipLaunchKernelGGL(bin_reset_kernel, dim3(blocks), dim3(256), 0, s, b, ntiles);
     return hipGetLastError();
 }
@@ -417,8 +526,8 @@ hipError_t launch_bin_count(const GeoParams &g, const Binned &b, int64_t n, cons
     return hipGetLastError();
 }
 
-hipError_t launch_bin_scan(const Binned &b, int ntiles, hipStream_t s) {
-    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, b, ntiles);
+hipError_t launch_bin_scan(const Binned &b, int ntiles, uint32_t slots, hipStream_t s) {
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, b, ntiles, slots);
     return hipGetLastError();
 }
 

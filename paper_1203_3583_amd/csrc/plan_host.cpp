@@ -113,6 +113,15 @@ int make_layout(int64_t n, const asf_params *p, Layout &L) {
     L.off_twx = take(kC64 * fft_twiddle_entries(L.nfx));
     L.off_twy = take(kC64 * fft_twiddle_entries(L.nfy));
     L.off_w16 = take(kC64 * 16);
+    // the spreading kernel folds the halo of a tile back in on grids narrower than
+    // a tile plus w - 1 cells each side; only wider grids cut crowded tiles
+    L.split = L.nfx >= L.tile_x + 2 * (L.w - 1) && L.nfy >= L.tile_y + 2 * (L.w - 1);
+    L.off_split = take(sizeof(uint32_t) * L.ntiles);
+    L.off_split_meta = take(kAlign);
+    L.off_slot_owner = take(sizeof(uint32_t) * kSplitSlotsHost);
+    L.off_combine = take(sizeof(uint32_t) * kSplitSlotsHost);
+    // two 64-bit integer sums (Re, Im) per cell and slice
+    L.off_partial = take(L.split ? 16 * (size_t)kSplitSlotsHost * L.tile_x * L.tile_y : 0);
     L.total = o;
     return ASF_OK;
 }

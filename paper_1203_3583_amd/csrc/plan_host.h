@@ -19,6 +19,7 @@ constexpr size_t kAlign = 256;
 constexpr int kTileXMax = 64;      // spreading tile: 64 x 32 fine cells
 constexpr int kTileYMax = 32;
 constexpr int kLineMaxPoints = 16384;
+constexpr int kSplitSlotsHost = 512;   // partial tiles of cut crowded tiles
 
 // A complex value as two FP32 numbers, laid out like HIP's float2.
 struct Cf {
@@ -41,7 +42,11 @@ struct Layout {
     int64_t slot_cap;
     size_t off_status, off_tile_start, off_cursor, off_slab, off_cell, off_frac, off_phase, off_perm;
     size_t off_status2, off_cursor2;   // the counters' second copy
-    size_t off_fine, off_mid, off_dx, off_dy, off_twx, off_twy, off_w16, total;
+    size_t off_fine, off_mid, off_dx, off_dy, off_twx, off_twy, off_w16;
+    // crowded tiles cut into slices (only grids wider than a tile plus its halo)
+    bool split;
+    size_t off_split, off_split_meta, off_slot_owner, off_combine, off_partial;
+    size_t total;
 };
 
 int check_params(int64_t n, const asf_params *p);

@@ -38,11 +38,20 @@
 //            itself, keep separate 64-bit sums of Re and Im, accumulated in two
 //            sweeps over the same LDS array, with 42-bit terms (term42: the
 //            rounding remainder of each term kept as a second 20-bit piece).
-// One rounding step for every term of a tile costs a tile whose energy sits in a
+// One rounding step for every term of a tile costs a tile whose weight sits in a
 // few records (a bright point among weak ones) more than the others: their
 // rounding error is set by the bright record's amplitude, not by their own.
-// Such tiles (sum |c|^2 below nrec M^2 / 16) take the split sums as well.
-// Integer addition is associative, so the spread is bitwise deterministic.
+// Such tiles (nonzero parts averaging 4 or more octaves below the largest) take
+// the split sums as well.  Every decision of a tile comes from maxima and integer
+// counts, and integer addition is associative, so the spread is bitwise
+// deterministic and independent of the order the binning left the records in.
+//
+// Crowded tiles.  A tile far above the mean load of a resident workgroup (the
+// binning's scan decides, from the record counts) is cut into slices of
+// consecutive records, each taken by its own workgroup.  The slices share one
+// scale -- the largest |u1| among all the tile's records -- and the split sums,
+// write their integer sums to a partial buffer, and the last slice to finish
+// adds them (exactly) and writes the tile.
 //
 // Bank conflicts.  A wave's 64 lanes add the same footprint offset to 64
 // different points, so lane l touches base_l + const; LDS serves a quarter wave
@@ -163,26 +172,40 @@ struct Batch {
 
 // binned record fields (the u1 gather is separate so that it can be issued later,
 // once the indices have arrived)
+// Every load is issued unconditionally (slots past s1 are clamped to s1 - 1, a
+// record of the same tile, and then discarded), so that all of a thread's loads
+// are in flight together instead of each waiting behind a branch.  s0 < s1.
 __device__ inline void load_records(Batch &r, const Binned &b, uint32_t base, uint32_t s1, int nt) {
+    uint2 kv[kBatch];
+    float2 fr[kBatch], ph[kBatch];
 #pragma unroll
     for (int k = 0; k < kBatch; ++k) {
-        const uint32_t s = base + k * nt;
-        const bool in = s < s1;
-        const uint2 kv = in ? b.key[s] : make_uint2(0u, 0xffffffffu);
+        const uint32_t s = min(base + k * nt, s1 - 1u);
         const float2 *rv = reinterpret_cast<const float2 *>(b.rec + s);
-        r.j[k] = kv.y;
-        r.cell[k] = kv.x;
-        r.fr[k] = in ? rv[0] : make_float2(0.f, 0.f);
-        r.pc[k] = in ? rv[1] : make_float2(0.f, 0.f);
+        kv[k] = b.key[s];
+        fr[k] = rv[0];
+        ph[k] = rv[1];
+    }
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+        const bool in = base + k * nt < s1;
+        r.j[k] = in ? kv[k].y : 0xffffffffu;
+        r.cell[k] = kv[k].x;
+        r.fr[k] = in ? fr[k] : make_float2(0.f, 0.f);
+        r.pc[k] = in ? ph[k] : make_float2(0.f, 0.f);
     }
 }
 
+// (indices past the point count, which only discarded slots carry, are clamped)
 __device__ inline void gather_u(Batch &r, const float2 *__restrict__ u1, int64_t n) {
+    float2 u[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) u[k] = u1[min((int64_t)r.j[k], n - 1)];
 #pragma unroll
     for (int k = 0; k < kBatch; ++k) {
-        const float2 u = r.j[k] < n ? u1[r.j[k]] : make_float2(0.f, 0.f);
+        if (r.j[k] >= n) u[k] = make_float2(0.f, 0.f);
         const float2 ph = r.pc[k];
-        r.pc[k] = make_float2(u.x * ph.x - u.y * ph.y, u.x * ph.y + u.y * ph.x);
+        r.pc[k] = make_float2(u[k].x * ph.x - u[k].y * ph.y, u[k].x * ph.y + u[k].y * ph.x);
     }
 }
 
@@ -215,28 +238,41 @@ constexpr uint32_t kDealRecords = 64;
 // cells with terms below 2^21: no cell sum can leave int32.
 constexpr uint32_t kFewRecords = 1023;
 
-// Read back the tile's own cells in the order they are written out and convert
-// them to FP32.  Thread tid handles cells tid + k nt of the tile in panel order;
-// with nt a multiple of panel * tile_y each thread keeps its column offset and
-// row, and successive k step 16 columns: +16 cells in LDS, +16 nfy in the grid.
-template <int W, int PITCH>
-__device__ inline void write_tile(const unsigned long long *acc, float2 *__restrict__ fine,
-                                  const SpreadParams &p, int x0, int y0, int ncell, int nt,
-                                  bool packed, int sweep, float unscale) {
-    constexpr int PAD = W - 1;
+// The tile's own cells are read back and written out in panel order: thread tid
+// handles cells tid + k nt; with nt a multiple of panel * tile_y it keeps its row
+// ly and column offset lx, and successive k step col_step = nt / tile_y columns
+// (col_step nfy elements in the fine grid's panel layout).
+struct TileCells {
+    int lx, ly, col_step;
+    size_t grid, grid_step;
+};
+
+__device__ inline TileCells tile_cells(const SpreadParams &p, int x0, int y0, int nt) {
     const int tid = threadIdx.x;
     const int C = 1 << p.log_panel;
     const int c = tid & (C - 1);
     const int rest = tid >> p.log_panel;
-    const int ly = rest & ((1 << p.log_tile_y) - 1);
-    const int lx = ((rest >> p.log_tile_y) << p.log_panel) + c;
-    const unsigned long long *src = acc + (ly + PAD) * PITCH + lx + PAD;
-    const int step = nt >> p.log_tile_y;   // columns per k
-    float2 *dst = fine + ((((size_t)((x0 + lx) >> p.log_panel) * p.nfy + y0 + ly) << p.log_panel) + c);
-    const size_t dstep = (size_t)step * p.nfy;
+    TileCells m;
+    m.ly = rest & ((1 << p.log_tile_y) - 1);
+    m.lx = ((rest >> p.log_tile_y) << p.log_panel) + c;
+    m.col_step = nt >> p.log_tile_y;
+    m.grid = (((size_t)((x0 + m.lx) >> p.log_panel) * p.nfy + y0 + m.ly) << p.log_panel) + c;
+    m.grid_step = (size_t)m.col_step * p.nfy;
+    return m;
+}
+
+// The tile's own cells as FP32 into the fine grid.
+template <int W, int PITCH>
+__device__ inline void write_tile(const unsigned long long *acc, float2 *__restrict__ fine,
+                                  const SpreadParams &p, int x0, int y0, int ncell, int nt, bool packed,
+                                  int sweep, float unscale) {
+    constexpr int PAD = W - 1;
+    const TileCells m = tile_cells(p, x0, y0, nt);
+    const unsigned long long *src = acc + (m.ly + PAD) * PITCH + m.lx + PAD;
+    float2 *dst = fine + m.grid;
     for (int k = 0; k < ncell / nt; ++k) {
-        const unsigned long long v = src[k * step];
-        float2 *d = dst + k * dstep;
+        const unsigned long long v = src[k * m.col_step];
+        float2 *d = dst + k * m.grid_step;
         if (packed) {
             int sr, si;
             unpack2(v, sr, si);
@@ -248,14 +284,89 @@ __device__ inline void write_tile(const unsigned long long *acc, float2 *__restr
     }
 }
 
-// A tile whose records' energy sits in a few of them: sum |c|^2 < nrec M^2 / 16, with
-// M the largest |Re c|, |Im c|.  The packed sums round every term to 2^-21 M (or
-// 2^-22 M), which costs the tile a relative error of about 9e-7 sqrt(nrec M^2 / sum
-// |c|^2) of its own energy: about 1.5e-6 for a tile of random phases and amplitudes,
-// but 2e-5 for one bright point among 500 points 1e4 times weaker.  Above the
-// threshold (at most 3.6e-6) the tile uses the split sums with 42-bit terms.
-__device__ inline bool high_dynamic_range(uint32_t nrec, float big, float ssum) {
-    return big > 0.f && (double)nrec * (double)big * (double)big > 16.0 * (double)ssum;
+// A slice of a cut tile: its integer sums (one sweep's part) in write-out order.
+template <int W, int PITCH>
+__device__ inline void write_partial(const unsigned long long *acc, unsigned long long *__restrict__ part,
+                                     const SpreadParams &p, int ncell, int nt) {
+    constexpr int PAD = W - 1;
+    const TileCells m = tile_cells(p, 0, 0, nt);
+    const unsigned long long *src = acc + (m.ly + PAD) * PITCH + m.lx + PAD;
+    for (int k = 0; k < ncell / nt; ++k) part[k * nt + threadIdx.x] = src[k * m.col_step];
+}
+
+// The last slice of a cut tile to finish adds the slices' integer sums (exact: the
+// result does not depend on how the records were dealt to slices, nor on which
+// slice ends last) and writes the tile.  part: [slices][2][ncell], Re then Im.
+__device__ inline void combine_tile(const unsigned long long *part, uint32_t nsl, float2 *__restrict__ fine,
+                                    const SpreadParams &p, int x0, int y0, int ncell, int nt, float unscale) {
+    const TileCells m = tile_cells(p, x0, y0, nt);
+    for (int k = 0; k < ncell / nt; ++k) {
+        const unsigned long long *src = part + (size_t)k * nt + threadIdx.x;
+        unsigned long long re = 0ull, im = 0ull;
+        for (uint32_t q = 0; q < nsl; ++q) {
+            re += src[(size_t)(2 * q) * ncell];
+            im += src[(size_t)(2 * q + 1) * ncell];
+        }
+        fine[m.grid + k * m.grid_step] = make_float2((float)(long long)re * unscale, (float)(long long)im * unscale);
+    }
+}
+
+// Wave-wide reductions by lane permutations on the vector ALU (DPP): within each
+// row of 16 lanes, exchanges with lane ^ 1 and lane ^ 2, then the half-row and row
+// mirrors leave every lane with its row's result; four lane reads combine the
+// rows.  A few cycles per step, where shuffles routed through the LDS crossbar
+// take a round trip each.
+__device__ inline unsigned dpp_row_max(unsigned v) {
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad [1,0,3,2]
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad [2,3,0,1]
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // row half mirror
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));  // row mirror
+    return v;
+}
+
+__device__ inline unsigned dpp_row_sum(unsigned v) {
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);
+    return v;
+}
+
+// inclusive prefix sum within each row of 16 lanes (row shifts by 1, 2, 4, 8;
+// lanes shifted in from outside the row read 0)
+__device__ inline unsigned dpp_row_prefix(unsigned v) {
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);   // row_shr:1
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    return v;
+}
+
+// (the whole wave must be active; the result is uniform)
+__device__ inline unsigned wave_max(unsigned v) {
+    v = dpp_row_max(v);
+    return max(max((unsigned)__builtin_amdgcn_readlane((int)v, 0), (unsigned)__builtin_amdgcn_readlane((int)v, 16)),
+               max((unsigned)__builtin_amdgcn_readlane((int)v, 32), (unsigned)__builtin_amdgcn_readlane((int)v, 48)));
+}
+
+__device__ inline unsigned wave_sum(unsigned v) {
+    v = dpp_row_sum(v);
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 0) + (unsigned)__builtin_amdgcn_readlane((int)v, 16) +
+           (unsigned)__builtin_amdgcn_readlane((int)v, 32) + (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+}
+
+// A tile whose weight sits in a few of its records: the exponents of its nonzero
+// parts (max(|Re c|, |Im c|) per record) average 4 or more below the largest one,
+// E.  The packed sums round every term to 2^-21 M (or 2^-22 M), M the largest part,
+// which costs the other records a relative error set by M rather than by their own
+// size: about 1.5e-6 for a tile of random phases and amplitudes, 2e-5 for one
+// bright point among 500 points 1e4 times weaker.  Such tiles take the split sums
+// with 42-bit terms.  (Zero records add exact zeros and do not count.)  The
+// statistic is a sum of integer exponents, so this decision, like the tile's
+// others (maxima and counts), does not depend on the order the binning left the
+// records in.
+__device__ inline bool high_dynamic_range(unsigned ebig, unsigned long long nnz, unsigned long long esum) {
+    return nnz > 0ull && ebig * nnz - esum >= 4ull * nnz;
 }
 
 // Exponent bound of the terms of a split tile: each record adds at most one term
@@ -281,10 +392,13 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
     __shared__ int sbase[kChunk + 16];                   // their padded start cell
     __shared__ unsigned rcount[16];                      // records per start residue
     __shared__ unsigned sbig, smost;                     // block maxima
-    __shared__ float ssum;                               // sum of |c|^2 over the tile's records
+    __shared__ unsigned long long snnz, sesum;           // nonzero records, sum of their exponents
     int *starts = reinterpret_cast<int *>(sdat);         // footprint-start histogram (phase A)
 
-    const int t = blockIdx.x;
+    // this workgroup's tile, and its slice of the records if the tile is cut
+    int t;
+    uint32_t slice, nsl, slot, s0, s1;
+    if (!tile_work(b, p.ntx * p.nty, t, slice, nsl, slot, s0, s1)) return;
     const int tsx = 1 << p.log_tile_x, tsy = 1 << p.log_tile_y;
     const int ext_x = tsx + 2 * PAD, ext_y = tsy + 2 * PAD;   // padded tile extent
     const int swx = tsx + PAD, swy = tsy + PAD;               // start positions per axis
@@ -295,23 +409,27 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
     const uint32_t per_batch = (uint32_t)(kBatch * nt);
     const int ty = t >> p.log_ntx, tx = t & ((1 << p.log_ntx) - 1);
     const int x0 = tx << p.log_tile_x, y0 = ty << p.log_tile_y;
-    uint32_t s0, s1;
-    tile_slots(b, t, s0, s1);
     const uint32_t nrec = s1 - s0;
     const bool reload = nrec > per_batch;
     const bool deal = nrec > kDealRecords;
+    // The slices of a cut tile all take the split sums with 42-bit terms at one
+    // scale, set by the largest |u1| among all the tile's records (|exp(i phi)| = 1
+    // bounds |Re c| and |Im c| by it): every term is then the same integer whichever
+    // slice adds it, and the slices' sums add up exactly to the whole tile's.
+    const bool cut = nsl > 1;
     // a tile of few records needs no start histogram: no cell receives more than
     // nrec terms (unless the grid folds the padded tile onto itself: split sums)
-    const bool few = nrec <= kFewRecords && !fold_x && !fold_y;
+    const bool few = nrec <= kFewRecords && !fold_x && !fold_y && !cut;
+    const bool count_starts = !few && !cut;
     {
         uint4 *a4 = reinterpret_cast<uint4 *>(acc);
         for (int i = tid; i < G::CELLS / 2; i += nt) a4[i] = make_uint4(0u, 0u, 0u, 0u);
-        if (!few)
+        if (count_starts)
             for (int i = tid; i < swx * swy; i += nt) starts[i] = 0;
         if (tid < 16) rcount[tid] = 0u;
         if (tid == 0) {
             sbig = smost = 0u;
-            ssum = 0.f;
+            snnz = sesum = 0ull;
         }
     }
     Batch r;
@@ -322,7 +440,7 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
     // footprint starts per position).  A tile of at most kBatch * nt records
     // keeps them in registers for phase B; larger tiles reload them there.
     float big = 0.f;
-    float en = 0.f;
+    unsigned nnz = 0u, esum = 0u;   // this thread's nonzero parts and the sum of their exponents
     for (uint32_t base = s0; base < s1; base += per_batch) {
         load_records(r, b, base + tid, s1, nt);
         gather_u(r, u1, p.n);
@@ -332,44 +450,74 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
             rb[k] = -1;
             if (r.j[k] < p.n && local_start(r.cell[k], x0, y0, PAD, hix, hiy, p.nfx, p.nfy, px, py)) {
                 rb[k] = py * PITCH + px;
-                big = fmaxf(big, fmaxf(fabsf(r.pc[k].x), fabsf(r.pc[k].y)));
-                en = __builtin_fmaf(r.pc[k].x, r.pc[k].x, __builtin_fmaf(r.pc[k].y, r.pc[k].y, en));
-                if (!few) atomicAdd(&starts[py * swx + px], 1);
+                const float part = fmaxf(fabsf(r.pc[k].x), fabsf(r.pc[k].y));
+                big = fmaxf(big, part);
+                // branch-free: a zero part adds exponent 0 and no count
+                nnz += part > 0.f ? 1u : 0u;
+                esum += __float_as_uint(part) >> 23;
+                if (count_starts) atomicAdd(&starts[py * swx + px], 1);
             }
         }
     }
-    // block maximum (non-negative floats order like their bit patterns) and energy
+    uint32_t tile_records = nrec;
+    if (cut) {
+        // the scale of all the tile's slices: the largest |u1| over all its records,
+        // two records per thread in flight
+        uint32_t a0, a1;
+        tile_slots(b, t, a0, a1);
+        tile_records = a1 - a0;
+        big = 0.f;
+        for (uint32_t i = a0 + tid; i < a1; i += 2 * nt) {
+            uint32_t j[2];
+            float2 u[2];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        big = fmaxf(big, __shfl_xor(big, off));
-        en += __shfl_xor(en, off);
+            for (int q = 0; q < 2; ++q) j[q] = b.key[min(i + q * nt, a1 - 1u)].y;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) u[q] = u1[min((int64_t)j[q], p.n - 1)];
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                if (i + q * nt < a1 && j[q] < p.n) big = fmaxf(big, sqrtf(u[q].x * u[q].x + u[q].y * u[q].y));
+        }
     }
+    // block maximum (non-negative floats order like their bit patterns) and the
+    // exponent statistics: wave sums in 32 bits (a wave holds an eighth of the
+    // tile's records; tiles of 2^24 or more records skip the statistic), 64-bit
+    // sums across the block
+    const unsigned wbig = wave_max(__float_as_uint(big));
+    const unsigned wnnz = wave_sum(nnz), wesum = wave_sum(esum);
     if (lane == 0) {
-        atomicMax(&sbig, __float_as_uint(big));
-        atomicAdd(&ssum, en);
+        atomicMax(&sbig, wbig);
+        if (!cut && wnnz) {
+            atomicAdd(&snnz, (unsigned long long)wnnz);
+            atomicAdd(&sesum, (unsigned long long)wesum);
+        }
     }
-    __syncthreads();               // sbig and starts[] complete
+    __syncthreads();               // sbig, snnz, sesum and starts[] complete
     big = __uint_as_float(sbig);
     bool packed;
     int emax;                      // terms are bounded by 2^emax
-    if (few) {
+    if (cut) {
+        packed = false;
+        emax = split_emax(tile_records);
+    } else if (few) {
         packed = true;             // kFewRecords (2^21 + 1/2) < 2^31
         emax = 21;
     } else {
         unsigned most = 0u;        // most footprint starts in one cell
         for (int i = tid; i < swx * swy; i += nt) most = max(most, (unsigned)starts[i]);
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) most = max(most, (unsigned)__shfl_xor((int)most, off));
+        most = wave_max(most);
         if (lane == 0) atomicMax(&smost, most);
         __syncthreads();
         // 511 (2^22 + 1/2) < 2^31; grids folding the tile onto itself sum several cells
         packed = smost * (unsigned)(W * W) <= 511u && !fold_x && !fold_y;
         emax = 22;
     }
-    // a few records dominating the tile's energy: the others would be rounded on the
-    // dominant ones' grid, so the tile takes the split sums with 42-bit terms
-    if (high_dynamic_range(nrec, __uint_as_float(sbig), ssum)) packed = false;
-    if (!packed) emax = split_emax(nrec);
+    // a few records dominating the tile: the others would be rounded on the dominant
+    // ones' grid, so the tile takes the split sums with 42-bit terms
+    if (!cut) {
+        if (nrec >= (1u << 24) || high_dynamic_range(sbig >> 23, snnz, sesum)) packed = false;
+        if (!packed) emax = split_emax(nrec);
+    }
     int e = 0;
     if (big > 0.f) {
         int em;
@@ -425,13 +573,8 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
                 __syncthreads();   // residue counts complete
                 // exclusive prefix of the 16 counts, held by lanes 0..15 of every wave
                 const unsigned cnt = lane < 16 ? rcount[lane] : 0u;
-                unsigned inc = cnt;
-#pragma unroll
-                for (int off = 1; off < 16; off <<= 1) {
-                    const unsigned v = __shfl_up(inc, off);
-                    if (lane >= off) inc += v;
-                }
-                const unsigned total = __shfl(inc, 15);
+                const unsigned inc = dpp_row_prefix(cnt);
+                const unsigned total = (unsigned)__builtin_amdgcn_readlane((int)inc, 15);
                 const unsigned excl = inc - cnt;
                 const unsigned n16 = (total + 15u) >> 4;
                 const float inv16 = n16 ? 1.f / (float)n16 : 0.f;
@@ -461,7 +604,10 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
         }
         __syncthreads();
 
-        if (!fold_x && !fold_y) {
+        if (cut) {
+            // slices are only made on grids that do not fold
+            write_partial<W, PITCH>(acc, b.partial + (size_t)(2 * (slot + slice) + sweep) * ncell, p, ncell, nt);
+        } else if (!fold_x && !fold_y) {
             write_tile<W, PITCH>(acc, fine, p, x0, y0, ncell, nt, packed, sweep, unscale);
         } else {
             // grids narrower than the padded tile: fold the wrapped halo back in
@@ -496,13 +642,27 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
             __syncthreads();
         }
     }
+    if (cut) {
+        // partial sums stored: make them visible device-wide, then count the slice in;
+        // the last of the tile's slices (whichever it is) reads all partials back
+        __shared__ unsigned slast;
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) slast = atomicAdd(&b.combine[slot], 1u) == nsl - 1;
+        __syncthreads();
+        if (slast) {
+            __threadfence();
+            combine_tile(b.partial + (size_t)2 * slot * ncell, nsl, fine, p, x0, y0, ncell, nt, unscale);
+            if (tid == 0) b.combine[slot] = 0u;   // ready for the next launch
+        }
+    }
 }
 
 template <int W>
 hipError_t launch_w(const SpreadParams &p, const Binned &b, const float2 *u1, float2 *fine,
                     hipStream_t s) {
-    const int ntiles = p.ntx * p.nty;
-    hipLaunchKernelGGL(spread_kernel<W>, dim3(ntiles), dim3(kThreads), 0, s, p, b, u1, fine);
+    const int groups = p.ntx * p.nty + (p.split ? kSplitSlots : 0);
+    hipLaunchKernelGGL(spread_kernel<W>, dim3(groups), dim3(kThreads), 0, s, p, b, u1, fine);
     return hipGetLastError();
 }
 
@@ -523,7 +683,11 @@ __global__ void __launch_bounds__(kInterpThreads) interp_kernel(SpreadParams p, 
                                                                 float2 *__restrict__ g1) {
     constexpr int RP = kTileXMax + W - 1;   // LDS row pitch (cells)
     __shared__ float2 reg[(kTileYMax + W - 1) * RP];
-    const int t = blockIdx.x;
+    // this workgroup's tile, and its slice of the records if the tile is cut (no
+    // combining: every point is written by the one workgroup that holds its record)
+    int t;
+    uint32_t slice, nsl, slot, s0, s1;
+    if (!tile_work(b, p.ntx * p.nty, t, slice, nsl, slot, s0, s1)) return;
     const int tsx = 1 << p.log_tile_x, tsy = 1 << p.log_tile_y;
     const int rx = tsx + W - 1, ry = tsy + W - 1;
     const int ty = t >> p.log_ntx, tx = t & ((1 << p.log_ntx) - 1);
@@ -559,13 +723,17 @@ __global__ void __launch_bounds__(kInterpThreads) interp_kernel(SpreadParams p, 
             if (at[q] >= 0) reg[at[q]] = v[q];
     }
     __syncthreads();
-    uint32_t s0, s1;
-    tile_slots(b, t, s0, s1);
-    // two records per thread and iteration: their loads go out together
+    // two records per thread and iteration: their key and record loads all go out
+    // together (slots past s1 clamped to s1 - 1 and discarded)
     for (uint32_t sb = s0 + tid; sb < s1; sb += 2 * nt) {
         uint2 kv[2];   // (cell, point index)
+        float4 rv[2];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) kv[q] = sb + q * nt < s1 ? b.key[sb + q * nt] : make_uint2(0xffffffffu, 0u);
+        for (int q = 0; q < 2; ++q) {
+            const uint32_t s = min(sb + q * nt, s1 - 1u);
+            kv[q] = b.key[s];
+            rv[q] = b.rec[s];
+        }
         bool home[2];
         int px[2], py[2];
         uint32_t j[2];
@@ -576,11 +744,9 @@ __global__ void __launch_bounds__(kInterpThreads) interp_kernel(SpreadParams p, 
             py[q] = (int)(kv[q].x >> 16) - y0;
             // a point is handled in its home tile only (and past s1 nowhere)
             home[q] = sb + q * nt < s1 && px[q] >= 0 && px[q] < tsx && py[q] >= 0 && py[q] < tsy;
-            const uint32_t s = sb + q * nt;
-            const float4 rv = home[q] ? b.rec[s] : make_float4(0.f, 0.f, 0.f, 0.f);
             j[q] = home[q] ? kv[q].y : 0u;
-            fr[q] = make_float2(rv.x, rv.y);
-            ph[q] = make_float2(rv.z, rv.w);
+            fr[q] = make_float2(rv[q].x, rv[q].y);
+            ph[q] = make_float2(rv[q].z, rv[q].w);
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -611,7 +777,8 @@ __global__ void __launch_bounds__(kInterpThreads) interp_kernel(SpreadParams p, 
 template <int W>
 hipError_t launch_interp_w(const SpreadParams &p, const Binned &b, const float2 *fine, float2 *g1,
                            hipStream_t s) {
-    hipLaunchKernelGGL(interp_kernel<W>, dim3(p.ntx * p.nty), dim3(kInterpThreads), 0, s, p, b, fine, g1);
+    const int groups = p.ntx * p.nty + (p.split ? kSplitSlots : 0);
+    hipLaunchKernelGGL(interp_kernel<W>, dim3(groups), dim3(kInterpThreads), 0, s, p, b, fine, g1);
     return hipGetLastError();
 }
 

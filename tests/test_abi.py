@@ -51,8 +51,10 @@ def test_workspace_bytes_layout(asf):
     n = 2048 * 2048
     b = asf.workspace_bytes(n, p)
     nf = 4096
-    # binned records (24 B per slot, 4 slots per point) + fine grid + mid array dominate
-    lower = 24 * 4 * n + 8 * nf * nf + 8 * 2048 * nf
+    # binned records (24 B per slot, 4 slots per point) + fine grid + mid array dominate,
+    # then 512 partial tiles of 64 x 32 cells (two 64-bit sums each) for crowded tiles cut
+    # in slices
+    lower = 24 * 4 * n + 8 * nf * nf + 8 * 2048 * nf + 512 * 64 * 32 * 16
     assert lower <= b <= lower + (1 << 20)
     assert b % 256 == 0
     # more points need more space; the grid size alone sets the FFT buffers

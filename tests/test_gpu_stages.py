@@ -180,6 +180,80 @@ def test_binning_matches_host(which):
     assert np.max(np.abs(dev - ph[j])) <= 4e-7             # FP32 phase (<= 2e-7 rad) and sincos
 
 
+def _host_split(counts, slots):
+    """The cut of crowded tiles, by its rule: with R records and `slots` workgroups
+    resident at once, a tile of more than max(2048, 2 ceil(R / slots)) records takes
+    min(32, ceil(count / len)) slices (cut only if that is 2 or more), len =
+    max(256, ceil(R / slots)) doubled until all cut tiles need at most 512 slots."""
+    r = int(counts.sum())
+    load = -(-r // slots)
+    thr = max(2048, 2 * load)
+    if counts.max() <= thr:
+        return None, np.zeros_like(counts)
+    ln = max(256, load)
+    while True:
+        ns = np.where(counts > thr, np.minimum(32, -(-counts // ln)), 0)
+        ns[ns < 2] = 0
+        if ns.sum() <= 512:
+            return thr, ns
+        ln *= 2
+
+
+@pytest.mark.parametrize("which", ["even", "crowded", "hot", "sparse"])
+def test_split_plan_matches_rule(which):
+    """The binning's scan cuts exactly the tiles its rule names, into that many
+    slices, with partial-tile slots handed out in tile order and every slot's
+    owner recorded."""
+    torch = torch_gpu()
+    w = {"even": _even, "crowded": _crowded, "hot": _hot, "sparse": _sparse}[which]()
+    plan, _ = _plan(torch, w)
+    plan.status()
+    info = plan.info()
+    T = info["ntiles"]
+    _, ranges = _device_bins(torch, plan, info)
+    meta = _view(torch, plan, info["off_split_meta"], 2, torch.int32).view(np.uint32)
+    split = _view(torch, plan, info["off_split"], T, torch.int32).view(np.uint32)
+    owner = _view(torch, plan, info["off_slot_owner"], 512, torch.int32).view(np.uint32)
+    plan.close()
+    counts = np.array([b - a for a, b in ranges], dtype=np.int64)
+    slots = info["split_slots"]
+    assert slots > 0
+    thr, ns = _host_split(counts, slots)
+    print(f"split {which}: slots {slots}, largest tile {counts.max()}, threshold {thr}, "
+          f"cut tiles {int((ns > 0).sum())}, partial slots {int(ns.sum())}")
+    if thr is None:
+        assert meta[1] == 0 and meta[0] == 0xFFFFFFFF
+        return
+    assert meta[0] == thr and meta[1] == ns.sum()
+    at = 0
+    for t in np.flatnonzero(counts > thr):
+        if ns[t] == 0:
+            assert split[t] == 0
+            continue
+        assert split[t] == (at << 8 | ns[t])
+        for q in range(ns[t]):
+            assert owner[at + q] == (t << 8 | q)
+        at += ns[t]
+    if which in ("crowded", "hot"):
+        assert (ns > 0).any()   # these geometries are cut
+
+
+def test_cut_tiles_are_deterministic():
+    """Spreading a cut geometry twice gives bitwise the same fine grid (the partial
+    tiles are summed in slice order whichever slice finishes last)."""
+    torch = torch_gpu()
+    w = _hot()
+    plan, u = _plan(torch, w)
+    info = plan.info()
+    grids = []
+    for _ in range(3):
+        plan.forward(u)
+        torch.cuda.synchronize()
+        grids.append(_view(torch, plan, info["off_fine"], 2 * info["nfx"] * info["nfy"], torch.int32))
+    plan.close()
+    assert np.array_equal(grids[0], grids[1]) and np.array_equal(grids[0], grids[2])
+
+
 def _psi(z, wid, beta):
     a = 1.0 - (2.0 * z / wid) ** 2
     return np.where(a >= 0.0, np.exp(beta * (np.sqrt(np.maximum(a, 0.0)) - 1.0)), 0.0)
