@@ -176,6 +176,11 @@ def surface(model, x, y, d, u, lam, z0, p2x, p2y, mx, my, ix=None, iy=None, inci
 def line(model, x, d, u, lam, z0, p2, m, ix=None, incident="plane", nthreads=0, lib=None, x0=0.0):
     """One-dimensional u2 at pixels ix (default: all m) by Eq. (7), (5) or (2) read in 1D.
 
+    Eq. (7) and (5) in 1D are the exact (Fresnel chirp) integrals over y of the 2D forms,
+    with the amplitude's r0 read as z0 as the 2D forms read it; Eq. (2) in 1D is
+    an approximation the oracle makes itself: the y-integral of exp(i k R) / R^2 is
+    taken by its stationary-phase leading term, relative error about 1 / (k rho)
+    (1e-7 at rho = 1 m for visible light), far below the errors the study compares.
     x, d: float64 [n] (m); u: complex [n]; pixel ix at X = x0 + p2 (ix - m // 2).
     Returns complex128 [len(ix)].
     """
