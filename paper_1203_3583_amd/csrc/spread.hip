@@ -297,18 +297,42 @@ __device__ inline void write_partial(const unsigned long long *acc, unsigned lon
 // The last slice of a cut tile to finish adds the slices' integer sums (exact: the
 // result does not depend on how the records were dealt to slices, nor on which
 // slice ends last) and writes the tile.  part: [slices][2][ncell], Re then Im.
+// The tile's cells are kCombineCells per thread (ncell = 2048 = 4 nt on the grids
+// that cut tiles); each step loads kCombineSlices slices' sums of all of them, 32
+// loads in flight.
+constexpr int kCombineCells = 4;
+constexpr int kCombineSlices = 4;
+static_assert(kTileXMax * kTileYMax == kCombineCells * kThreads, "cut tiles are full 64 x 32 tiles");
+
 __device__ inline void combine_tile(const unsigned long long *part, uint32_t nsl, float2 *__restrict__ fine,
                                     const SpreadParams &p, int x0, int y0, int ncell, int nt, float unscale) {
     const TileCells m = tile_cells(p, x0, y0, nt);
-    for (int k = 0; k < ncell / nt; ++k) {
-        const unsigned long long *src = part + (size_t)k * nt + threadIdx.x;
-        unsigned long long re = 0ull, im = 0ull;
-        for (uint32_t q = 0; q < nsl; ++q) {
-            re += src[(size_t)(2 * q) * ncell];
-            im += src[(size_t)(2 * q + 1) * ncell];
+    unsigned long long re[kCombineCells] = {}, im[kCombineCells] = {};
+    const unsigned long long *src = part + threadIdx.x;
+    for (uint32_t q = 0; q < nsl; q += kCombineSlices) {
+        unsigned long long v[kCombineSlices][2][kCombineCells];
+#pragma unroll
+        for (int h = 0; h < kCombineSlices; ++h) {
+            const uint32_t qh = min(q + h, nsl - 1u);   // past the last slice: reloaded, added as zero
+#pragma unroll
+            for (int k = 0; k < kCombineCells; ++k) {
+                v[h][0][k] = src[(size_t)(2 * qh) * ncell + k * nt];
+                v[h][1][k] = src[(size_t)(2 * qh + 1) * ncell + k * nt];
+            }
         }
-        fine[m.grid + k * m.grid_step] = make_float2((float)(long long)re * unscale, (float)(long long)im * unscale);
+#pragma unroll
+        for (int h = 0; h < kCombineSlices; ++h) {
+            const unsigned long long keep = q + h < nsl ? ~0ull : 0ull;
+#pragma unroll
+            for (int k = 0; k < kCombineCells; ++k) {
+                re[k] += v[h][0][k] & keep;
+                im[k] += v[h][1][k] & keep;
+            }
+        }
     }
+#pragma unroll
+    for (int k = 0; k < kCombineCells; ++k)
+        fine[m.grid + k * m.grid_step] = make_float2((float)(long long)re[k] * unscale, (float)(long long)im[k] * unscale);
 }
 
 // Wave-wide reductions by lane permutations on the vector ALU (DPP): within each
@@ -462,20 +486,21 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
     uint32_t tile_records = nrec;
     if (cut) {
         // the scale of all the tile's slices: the largest |u1| over all its records,
-        // two records per thread in flight
+        // eight records per thread in flight
         uint32_t a0, a1;
         tile_slots(b, t, a0, a1);
         tile_records = a1 - a0;
         big = 0.f;
-        for (uint32_t i = a0 + tid; i < a1; i += 2 * nt) {
-            uint32_t j[2];
-            float2 u[2];
+        constexpr int kScan = 8;
+        for (uint32_t i = a0 + tid; i < a1; i += kScan * nt) {
+            uint32_t j[kScan];
+            float2 u[kScan];
 #pragma unroll
-            for (int q = 0; q < 2; ++q) j[q] = b.key[min(i + q * nt, a1 - 1u)].y;
+            for (int q = 0; q < kScan; ++q) j[q] = b.key[min(i + q * nt, a1 - 1u)].y;
 #pragma unroll
-            for (int q = 0; q < 2; ++q) u[q] = u1[min((int64_t)j[q], p.n - 1)];
+            for (int q = 0; q < kScan; ++q) u[q] = u1[min((int64_t)j[q], p.n - 1)];
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
+            for (int q = 0; q < kScan; ++q)
                 if (i + q * nt < a1 && j[q] < p.n) big = fmaxf(big, sqrtf(u[q].x * u[q].x + u[q].y * u[q].y));
         }
     }

@@ -184,13 +184,13 @@ def _host_split(counts, slots):
     """The cut of crowded tiles, by its rule: with R records and `slots` workgroups
     resident at once, a tile of more than max(2048, 2 ceil(R / slots)) records takes
     min(32, ceil(count / len)) slices (cut only if that is 2 or more), len =
-    max(256, ceil(R / slots)) doubled until all cut tiles need at most 512 slots."""
+    max(1024, ceil(R / slots)) doubled until all cut tiles need at most 512 slots."""
     r = int(counts.sum())
     load = -(-r // slots)
     thr = max(2048, 2 * load)
     if counts.max() <= thr:
         return None, np.zeros_like(counts)
-    ln = max(256, load)
+    ln = max(1024, load)
     while True:
         ns = np.where(counts > thr, np.minimum(32, -(-counts // ln)), 0)
         ns[ns < 2] = 0
