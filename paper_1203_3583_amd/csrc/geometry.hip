@@ -183,11 +183,20 @@ __device__ inline void bin_block(const GeoParams &g, const Binned &b, int64_t n,
     PointTiles p[kBinPoints];
     WaveGroup grp[kBinPoints][4];
     uint32_t base[kBinPoints][4];
+    // per replica: its tile's slab (slab layout) or end of its scanned range
+    // (compact layout), loaded unconditionally (tile 0 for absent replicas) so that
+    // the loads are in flight while the lanes are grouped
+    uint2 lim[kBinPoints][4];
 #pragma unroll
     for (int k = 0; k < kBinPoints; ++k) {
         p[k].n = 0;
         const bool in = geo_index(blk, k) < n;
         if (in) p[k] = point_tiles(g, xv[k], yv[k], dv[k]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int key = r < p[k].n ? p[k].key[r] : 0;
+            lim[k][r] = SLAB ? b.slab[key] : make_uint2(0u, b.tile_start[key + 1]);
+        }
         // one flag per wave holding invalid points
         if (SLAB && __ballot(in && p[k].n == 0) != 0ull && __lane_id() == 0) atomicOr(b.status, kStatusDomain);
         // group the replica keys, then let the leaders reserve their groups'
@@ -199,6 +208,13 @@ __device__ inline void bin_block(const GeoParams &g, const Binned &b, int64_t n,
             base[k][r] = (r < p[k].n && grp[k][r].leader == __lane_id())
                              ? atomicAdd(&b.cursor[p[k].key[r]], grp[k][r].size) : 0u;
     }
+    // every replica's slot within its tile: the group leader's reservation plus the
+    // lane's rank (all shuffles issued together)
+    uint32_t pos[kBinPoints][4];
+#pragma unroll
+    for (int k = 0; k < kBinPoints; ++k)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pos[k][r] = __shfl(base[k][r], grp[k][r].leader) + grp[k][r].rank;
 #pragma unroll
     for (int k = 0; k < kBinPoints; ++k) {
         float2 ph = make_float2(0.f, 0.f);
@@ -217,14 +233,11 @@ __device__ inline void bin_block(const GeoParams &g, const Binned &b, int64_t n,
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const bool act = r < p[k].n;
-            const int key = act ? p[k].key[r] : 0;
-            const uint32_t pos = __shfl(base[k][r], grp[k][r].leader) + grp[k][r].rank;
             uint32_t slot;
             bool ok;
             if (SLAB) {
-                const uint2 sl = act ? b.slab[key] : make_uint2(0u, 0u);
-                slot = sl.x + pos;
-                ok = pos < sl.y;
+                slot = lim[k][r].x + pos[k][r];
+                ok = pos[k][r] < lim[k][r].y;
                 // at most one flag per wave, none once the bit is seen set: a crowded
                 // tile can overflow by millions of records
                 if (!compact_known && __ballot(act && !ok) != 0ull) {
@@ -234,8 +247,8 @@ __device__ inline void bin_block(const GeoParams &g, const Binned &b, int64_t n,
                         atomicOr(b.status, kStatusCompact);
                 }
             } else {
-                slot = pos;
-                ok = act && slot < b.tile_start[key + 1];
+                slot = pos[k][r];
+                ok = act && slot < lim[k][r].y;
                 if (act && !ok) atomicOr(b.status, kStatusOverflow);
             }
             if (act && ok) {
