@@ -51,6 +51,20 @@ def _sparse():
     return synth.Workload("sparse", x, y, d, u, 532e-9, 0.1, 80e-6, 80e-6, 2048, 2048)
 
 
+def _many_hot():
+    """48 clusters of 12,000 points, each within a cell or two of a 2048^2 fine grid: some
+    hundred crowded tiles whose 1024-record slices would need more than the 512 partial
+    slots, so the cut lengthens its slices."""
+    rng = np.random.default_rng(41)
+    centres = rng.uniform(-5e-3, 5e-3, size=(48, 2))
+    x = (centres[:, 0, None] + rng.uniform(-0.1e-6, 0.1e-6, size=(48, 12000))).reshape(-1)
+    y = (centres[:, 1, None] + rng.uniform(-0.1e-6, 0.1e-6, size=(48, 12000))).reshape(-1)
+    d = synth.sinusoidal_relief(x, y, 20e-6, 0.8e-3)
+    n = x.size
+    u = (rng.uniform(0, 1, n) * np.exp(2j * np.pi * rng.uniform(0, 1, n))).astype(np.complex64)
+    return synth.Workload("many_hot", x, y, d, u, 532e-9, 0.1, 80e-6, 80e-6, 1024, 1024)
+
+
 def _bright():
     """One bright point over 256^2 points 1e4 times weaker (the tiles holding it take
     the split sums with 42-bit terms)."""
@@ -189,23 +203,23 @@ def _host_split(counts, slots):
     load = -(-r // slots)
     thr = max(2048, 2 * load)
     if counts.max() <= thr:
-        return None, np.zeros_like(counts)
+        return None, np.zeros_like(counts), None
     ln = max(1024, load)
     while True:
         ns = np.where(counts > thr, np.minimum(32, -(-counts // ln)), 0)
         ns[ns < 2] = 0
         if ns.sum() <= 512:
-            return thr, ns
+            return thr, ns, ln
         ln *= 2
 
 
-@pytest.mark.parametrize("which", ["even", "crowded", "hot", "sparse"])
+@pytest.mark.parametrize("which", ["even", "crowded", "hot", "sparse", "many_hot"])
 def test_split_plan_matches_rule(which):
     """The binning's scan cuts exactly the tiles its rule names, into that many
     slices, with partial-tile slots handed out in tile order and every slot's
     owner recorded."""
     torch = torch_gpu()
-    w = {"even": _even, "crowded": _crowded, "hot": _hot, "sparse": _sparse}[which]()
+    w = {"even": _even, "crowded": _crowded, "hot": _hot, "sparse": _sparse, "many_hot": _many_hot}[which]()
     plan, _ = _plan(torch, w)
     plan.status()
     info = plan.info()
@@ -218,7 +232,7 @@ def test_split_plan_matches_rule(which):
     counts = np.array([b - a for a, b in ranges], dtype=np.int64)
     slots = info["split_slots"]
     assert slots > 0
-    thr, ns = _host_split(counts, slots)
+    thr, ns, ln = _host_split(counts, slots)
     print(f"split {which}: slots {slots}, largest tile {counts.max()}, threshold {thr}, "
           f"cut tiles {int((ns > 0).sum())}, partial slots {int(ns.sum())}")
     if thr is None:
@@ -234,8 +248,10 @@ def test_split_plan_matches_rule(which):
         for q in range(ns[t]):
             assert owner[at + q] == (t << 8 | q)
         at += ns[t]
-    if which in ("crowded", "hot"):
+    if which in ("crowded", "hot", "many_hot"):
         assert (ns > 0).any()   # these geometries are cut
+    if which == "many_hot":
+        assert ln > 1024         # and this one needed longer slices
 
 
 def test_cut_tiles_are_deterministic():
@@ -267,7 +283,7 @@ def _fine_natural(torch, plan, info):
     return v.reshape(nfx // C, nfy, C).transpose(1, 0, 2).reshape(nfy, nfx)
 
 
-@pytest.mark.parametrize("which", ["even", "crowded", "hot", "sparse", "bright"])
+@pytest.mark.parametrize("which", ["even", "crowded", "hot", "sparse", "bright", "many_hot"])
 def test_spread_matches_host_sum(which):
     """Even points (slab layout), the crowded relief (compact layout), a small grid
     whose tiles hold thousands of records (start histogram, record reloads), a large
@@ -276,7 +292,8 @@ def test_spread_matches_host_sum(which):
     whole grid; for the bright point the weak field's own part of the grid (the cells
     the bright point does not reach) is also checked against its own norm."""
     torch = torch_gpu()
-    w = {"even": _even, "crowded": _crowded, "hot": _hot, "sparse": _sparse, "bright": _bright}[which]()
+    w = {"even": _even, "crowded": _crowded, "hot": _hot, "sparse": _sparse, "bright": _bright,
+         "many_hot": _many_hot}[which]()
     plan, u = _plan(torch, w)
     plan.forward(u)
     torch.cuda.synchronize()
