@@ -26,6 +26,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -76,15 +77,21 @@ def _summary_fields(path):
     return fields
 
 
-def _sha(path):
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+def _code_sha(path):
+    """SHA-256 of a C++/HIP source's code: comments removed and whitespace collapsed,
+    so that a stored counter summary stays tied to the code it was measured on and
+    not to the wording of its comments."""
+    text = open(path, encoding="utf-8").read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()
 
 
 def stored_traffic():
     """HBM bytes per spread launch from the committed counter summary, if it was
-    taken on the current spread source (else None)."""
+    taken on the current spread code (else None)."""
     fields = _summary_fields(PROFILE_TRAFFIC)
-    if fields.get("spread_source_sha256") != _sha(SPREAD_SOURCE):
+    if fields.get("spread_code_sha256") != _code_sha(SPREAD_SOURCE):
         return None
     try:
         return float(fields["hbm_bytes_per_launch"])
@@ -96,9 +103,9 @@ def stored_fft_busy():
     """Busy fraction of the unit each FFT pass computes on, from the committed counter
     summary (FP32 passes: vector ALU, SQ_ACTIVE_INST_VALU; split-FP16 passes: matrix
     cores, SQ_VALU_MFMA_BUSY_CYCLES; each over GRBM_GUI_ACTIVE and the SIMD count),
-    if it was taken on the current FFT source (else None)."""
+    if it was taken on the current FFT code (else None)."""
     fields = _summary_fields(PROFILE_FFT)
-    if fields.get("fft_source_sha256") != _sha(FFT_SOURCE):
+    if fields.get("fft_code_sha256") != _code_sha(FFT_SOURCE):
         return None
     out = {}
     for k, v in fields.items():
