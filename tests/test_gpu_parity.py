@@ -225,6 +225,36 @@ def test_binning_layout_switches_with_crowding():
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
 
 
+_ORACLE_CACHE = {}
+
+
+@pytest.mark.parametrize("fft", ["fp32", "split_fp16"])
+@pytest.mark.parametrize("mx,my", [(16, 2048), (2048, 16), (32, 1024), (1024, 32), (64, 512), (512, 64),
+                                   (16, 4096), (4096, 16)])
+def test_every_transform_length(mx, my, fft):
+    """Fine-grid lengths 32 .. 8192 along each axis (every length the two FFT passes
+    are built for below the 16384 of the largest grid; lengths that are not powers of
+    16 take a radix-2/4/8 first stage, 4096 the direct-I/O kernels), skinny grids whose
+    32-cell side folds a padded tile onto itself, and 2999 scattered points whose
+    frequencies wrap about one and a half periods: the whole output against the oracle."""
+    key = (mx, my)
+    if key not in _ORACLE_CACHE:
+        rng = np.random.default_rng(mx * 7 + my)
+        n = 2999
+        x = rng.uniform(-5e-4, 5e-4, n)
+        y = rng.uniform(-5e-4, 5e-4, n)
+        d = synth.sinusoidal_relief(x, y, 20e-6, 0.8e-3)
+        u = (rng.uniform(0, 1, n) * np.exp(2j * np.pi * rng.uniform(0, 1, n))).astype(np.complex64)
+        w = synth.Workload("lengths", x, y, d, u, 532e-9, 0.1, 80e-6, 80e-6, mx, my, 1e-5, "plane")
+        _ORACLE_CACHE[key] = (w, _full_grid(w))
+    w, want = _ORACLE_CACHE[key]
+    got, info = gpu_forward(w, fft)
+    assert (info["nfx"], info["nfy"]) == (2 * mx, 2 * my)
+    err = rel_l2(got, want)
+    print(f"{mx} x {my} {fft}: rel-L2 {err:.3e}")
+    assert err <= TOL[fft]
+
+
 @pytest.mark.parametrize("fft", ["fp32", "split_fp16"])
 def test_largest_destination_grid(fft):
     """The largest destination grid (8192 x 8192: a 16384^2 fine grid, 131072 tiles,
