@@ -65,6 +65,26 @@ def test_adjoint_ragged_nonsquare_no_incident(fft):
     assert err <= TOL[fft]
 
 
+@pytest.mark.parametrize("fft", ["fp32", "split_fp16"])
+@pytest.mark.parametrize("mx,my", [(16, 2048), (2048, 16), (32, 1024), (1024, 32), (64, 512), (512, 64),
+                                   (16, 4096), (4096, 16)])
+def test_adjoint_every_transform_length(mx, my, fft):
+    """The adjoint's passes and interpolation at fine-grid lengths 32 .. 8192 along each
+    axis (32-cell sides wrap a tile's region onto itself), 2999 scattered points whose
+    frequencies wrap: every point against the oracle."""
+    rng = np.random.default_rng(mx * 5 + my)
+    n = 2999
+    x = rng.uniform(-5e-4, 5e-4, n)
+    y = rng.uniform(-5e-4, 5e-4, n)
+    d = synth.sinusoidal_relief(x, y, 20e-6, 0.8e-3)
+    u = np.zeros(n, dtype=np.complex64)
+    w = synth.Workload("lengths", x, y, d, u, 532e-9, 0.1, 80e-6, 80e-6, mx, my, 1e-5, "plane")
+    g2 = _g2(w, seed=mx + my)
+    err = rel_l2(_gpu_adjoint(w, g2, fft), _oracle_adjoint(w, g2))
+    print(f"adjoint {mx} x {my} {fft}: rel-L2 {err:.3e}")
+    assert err <= TOL[fft]
+
+
 def test_adjoint_wrapping_frequencies():
     # destination pitch large enough that p2 xi spans more than one period
     rng = np.random.default_rng(9)
