@@ -85,6 +85,21 @@ def test_adjoint_every_transform_length(mx, my, fft):
     assert err <= TOL[fft]
 
 
+@pytest.mark.parametrize("tol", [1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7])
+def test_adjoint_every_width(tol):
+    """Interpolation at every spreading width the tolerances select (3 .. 9): the
+    requested accuracy, or the FP32 bar of 1e-5 below it."""
+    rng = np.random.default_rng(12)
+    x, y = synth.jittered_grid(rng, 64, 64, 8e-6, 2e-6)
+    d = synth.sinusoidal_relief(x, y, 20e-6, 0.8e-3)
+    u = synth.random_field(rng, 64, 64)
+    w = synth.Workload("width", x, y, d, u, 532e-9, 0.1, 8e-6, 8e-6, 64, 64, tol, "plane")
+    g2 = _g2(w, seed=6)
+    err = rel_l2(_gpu_adjoint(w, g2), _oracle_adjoint(w, g2))
+    print(f"adjoint tol {tol}: rel-L2 {err:.3e}")
+    assert err <= max(tol, 1e-5)
+
+
 def test_adjoint_wrapping_frequencies():
     # destination pitch large enough that p2 xi spans more than one period
     rng = np.random.default_rng(9)

@@ -71,13 +71,16 @@ def test_wrapping_frequencies(fft):
     assert err <= TOL[fft]
 
 
-@pytest.mark.parametrize("tol,bar", [(1e-3, 1e-3), (1e-6, 1e-5)])
-def test_tolerance_sets_width(tol, bar):
+@pytest.mark.parametrize("tol", [1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7])
+def test_tolerance_sets_width(tol):
+    """Every spreading width the tolerances select (w = ceil(log10(1/tol)) + 2, 3 .. 9):
+    the requested accuracy, or the FP32 FFT's 1e-5 bar below it."""
     w = _custom(64, 64, 8e-6, 2e-6, 64, 64, 8e-6, 8e-6, tol=tol)
     got, info = gpu_forward(w, "fp32", tol=tol)
+    assert info["w"] == round(-np.log10(tol)) + 2
     err = rel_l2(got, _full_grid(w))
     print(f"tol {tol}: w={info['w']} err {err:.3e}")
-    assert err <= bar
+    assert err <= max(tol, 1e-5)
 
 
 @pytest.mark.parametrize("fft,d0,incident", [("fp32", 0.0, "plane"), ("split_fp16", 0.0, "plane"),
