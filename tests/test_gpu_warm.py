@@ -29,11 +29,14 @@ def _weights(torch, ws, rng, cout, cin, scale=0.2):
     return wt, ws.bf16_bits(torch, wt), w.reshape(cout, 3, 3, cin)
 
 
-# both kernels: direct with 16-pixel wave tiles (the three small cases), LDS-tiled (the
-# three large ones: ragged tiles on both axes, several images)
+# every kernel: direct with 16-pixel wave tiles (the three small cases), LDS-tiled with
+# 16-channel slices (the next three: ragged tiles on both axes, several images) and with
+# 32-channel slices in 8-, 4- and 2-row tiles (the last three, ragged as well)
 @pytest.mark.parametrize("B,H,W,cin,cout,relu", [(2, 8, 12, 16, 32, True), (1, 5, 7, 48, 64, False),
                                                  (1, 16, 16, 32, 96, True), (1, 300, 250, 16, 32, False),
-                                                 (2, 255, 259, 16, 64, True), (3, 203, 100, 48, 64, False)])
+                                                 (2, 255, 259, 16, 64, True), (3, 203, 100, 48, 64, False),
+                                                 (1, 517, 500, 32, 64, True), (2, 203, 257, 64, 64, False),
+                                                 (1, 299, 250, 96, 32, True)])
 def test_conv3x3_forward(B, H, W, cin, cout, relu):
     torch, ws, wo = _setup()
     rng = np.random.default_rng(B * 100 + cin)
