@@ -57,8 +57,10 @@ def test_conv3x3_forward(B, H, W, cin, cout, relu):
     assert L.asf_warm_conv3x3(ws._ptr(xt), ws._ptr(wb), None, ws._ptr(out), B, H, W, cin + 1, cout, 0, s) == -1
 
 
+# direct kernel (16 and 48 input channels), LDS-staged kernel (multiples of 32: one tile per
+# workgroup, then runs of tiles crossing image boundaries with one and two input-channel blocks)
 @pytest.mark.parametrize("B,H,W,cin,cout", [(2, 8, 12, 16, 32), (1, 5, 7, 48, 64), (3, 32, 32, 32, 32),
-                                            (2, 255, 259, 32, 64)])
+                                            (2, 255, 259, 32, 64), (2, 300, 260, 32, 64), (2, 300, 260, 64, 32)])
 def test_conv3x3_gradients(B, H, W, cin, cout):
     torch, ws, wo = _setup()
     rng = np.random.default_rng(7 + cin)
