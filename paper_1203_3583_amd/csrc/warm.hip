@@ -651,6 +651,70 @@ __global__ void up2_kernel(const float *__restrict__ in, float *__restrict__ out
     }
 }
 
+// Four channels per thread (float4) and 32-bit index arithmetic: the fast forms of
+// pool2 / up2 / copy_channels for channel counts (and offsets) in multiples of 4
+// and fewer than 2^31 work items, which the host checks.  A flat index split by
+// 64-bit division costs dozens of instructions per element, more than the copy.
+__global__ void pool2_v4_kernel(const float4 *__restrict__ in, float4 *__restrict__ out, int B, int H, int W, int q4,
+                                int backward) {
+    const unsigned Ho = (unsigned)H / 2, Wo = (unsigned)W / 2, q = (unsigned)q4;
+    const unsigned n = (unsigned)B * Ho * Wo * q;
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const unsigned c = i % q, t = i / q;
+        const unsigned xo = t % Wo, t2 = t / Wo;
+        const unsigned yo = t2 % Ho, b = t2 / Ho;
+        const size_t base = (((size_t)b * H + 2 * yo) * W + 2 * xo) * q + c;
+        const size_t rowc = (size_t)W * q;
+        if (!backward) {
+            const float4 a = in[base], bb = in[base + q], cc = in[base + rowc], d = in[base + rowc + q];
+            out[i] = make_float4(0.25f * (a.x + bb.x + cc.x + d.x), 0.25f * (a.y + bb.y + cc.y + d.y),
+                                 0.25f * (a.z + bb.z + cc.z + d.z), 0.25f * (a.w + bb.w + cc.w + d.w));
+        } else {
+            const float4 g = in[i];
+            const float4 gq = make_float4(0.25f * g.x, 0.25f * g.y, 0.25f * g.z, 0.25f * g.w);
+            out[base] = gq;
+            out[base + q] = gq;
+            out[base + rowc] = gq;
+            out[base + rowc + q] = gq;
+        }
+    }
+}
+
+__global__ void up2_v4_kernel(const float4 *__restrict__ in, float4 *__restrict__ out, int B, int H, int W, int q4,
+                              int backward) {
+    // H, W: the small side
+    const unsigned q = (unsigned)q4;
+    const unsigned n = (unsigned)B * (unsigned)H * (unsigned)W * q;
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const unsigned c = i % q, t = i / q;
+        const unsigned x = t % (unsigned)W, t2 = t / (unsigned)W;
+        const unsigned y = t2 % (unsigned)H, b = t2 / (unsigned)H;
+        const size_t W2 = 2 * (size_t)W;
+        const size_t base = (((size_t)b * 2 * H + 2 * y) * W2 + 2 * x) * q + c;
+        const size_t rowc = W2 * q;
+        if (!backward) {
+            const float4 v = in[i];
+            out[base] = v;
+            out[base + q] = v;
+            out[base + rowc] = v;
+            out[base + rowc + q] = v;
+        } else {
+            const float4 a = in[base], bb = in[base + q], cc = in[base + rowc], d = in[base + rowc + q];
+            out[i] = make_float4(a.x + bb.x + cc.x + d.x, a.y + bb.y + cc.y + d.y, a.z + bb.z + cc.z + d.z,
+                                 a.w + bb.w + cc.w + d.w);
+        }
+    }
+}
+
+__global__ void copy_channels_v4_kernel(const float4 *__restrict__ src, int src_q, int src_off_q,
+                                        float4 *__restrict__ dst, int dst_q, int dst_off_q, int count_q,
+                                        unsigned n) {
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const unsigned p = i / (unsigned)count_q, c = i - p * (unsigned)count_q;
+        dst[(size_t)p * dst_q + dst_off_q + c] = src[(size_t)p * src_q + src_off_q + c];
+    }
+}
+
 __global__ void copy_channels_kernel(const float *__restrict__ src, int src_c, int src_off, float *__restrict__ dst,
                                      int dst_c, int dst_off, int count, int64_t npix) {
     const int64_t n = npix * count;
@@ -687,6 +751,13 @@ inline int grid_for(int64_t n) {
 }
 
 inline int done(hipError_t e) { return e == hipSuccess ? 0 : -1; }
+
+// the float4 kernels: channels in multiples of 4, 16-byte aligned tensors and work
+// items that index in 31 bits
+inline bool aligned16(const void *a, const void *b) {
+    return (((uintptr_t)a | (uintptr_t)b) & 15) == 0;
+}
+inline bool fits_v4(int c, int64_t items) { return (c & 3) == 0 && items > 0 && items < ((int64_t)1 << 31); }
 
 }  // namespace
 
@@ -776,6 +847,12 @@ int asf_warm_relu_backward(const float *y, const float *dy, float *dx, int64_t n
 
 int asf_warm_pool2(const float *in, float *out, int32_t B, int32_t H, int32_t W, int32_t C, void *stream) {
     if (!in || !out || B <= 0 || H <= 1 || W <= 1 || C <= 0 || (H & 1) || (W & 1)) return -1;
+    if (fits_v4(C, (int64_t)B * (H / 2) * (W / 2) * (C / 4)) && aligned16(in, out)) {
+        hipLaunchKernelGGL(pool2_v4_kernel, dim3(grid_for((int64_t)B * (H / 2) * (W / 2) * (C / 4))), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), reinterpret_cast<const float4 *>(in),
+                           reinterpret_cast<float4 *>(out), B, H, W, C / 4, 0);
+        return done(hipGetLastError());
+    }
     hipLaunchKernelGGL(pool2_kernel, dim3(grid_for((int64_t)B * H * W * C / 4)), dim3(256), 0,
                        static_cast<hipStream_t>(stream), in, out, B, H, W, C, 0);
     return done(hipGetLastError());
@@ -784,6 +861,12 @@ int asf_warm_pool2(const float *in, float *out, int32_t B, int32_t H, int32_t W,
 int asf_warm_pool2_backward(const float *dout, float *din, int32_t B, int32_t H, int32_t W, int32_t C,
                             void *stream) {
     if (!dout || !din || B <= 0 || H <= 1 || W <= 1 || C <= 0 || (H & 1) || (W & 1)) return -1;
+    if (fits_v4(C, (int64_t)B * (H / 2) * (W / 2) * (C / 4)) && aligned16(dout, din)) {
+        hipLaunchKernelGGL(pool2_v4_kernel, dim3(grid_for((int64_t)B * (H / 2) * (W / 2) * (C / 4))), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), reinterpret_cast<const float4 *>(dout),
+                           reinterpret_cast<float4 *>(din), B, H, W, C / 4, 1);
+        return done(hipGetLastError());
+    }
     hipLaunchKernelGGL(pool2_kernel, dim3(grid_for((int64_t)B * H * W * C / 4)), dim3(256), 0,
                        static_cast<hipStream_t>(stream), dout, din, B, H, W, C, 1);
     return done(hipGetLastError());
@@ -791,6 +874,12 @@ int asf_warm_pool2_backward(const float *dout, float *din, int32_t B, int32_t H,
 
 int asf_warm_up2(const float *in, float *out, int32_t B, int32_t H, int32_t W, int32_t C, void *stream) {
     if (!in || !out || B <= 0 || H <= 0 || W <= 0 || C <= 0) return -1;
+    if (fits_v4(C, (int64_t)B * H * W * (C / 4)) && aligned16(in, out)) {
+        hipLaunchKernelGGL(up2_v4_kernel, dim3(grid_for((int64_t)B * H * W * (C / 4))), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), reinterpret_cast<const float4 *>(in),
+                           reinterpret_cast<float4 *>(out), B, H, W, C / 4, 0);
+        return done(hipGetLastError());
+    }
     hipLaunchKernelGGL(up2_kernel, dim3(grid_for((int64_t)B * H * W * C)), dim3(256), 0,
                        static_cast<hipStream_t>(stream), in, out, B, H, W, C, 0);
     return done(hipGetLastError());
@@ -799,6 +888,12 @@ int asf_warm_up2(const float *in, float *out, int32_t B, int32_t H, int32_t W, i
 int asf_warm_up2_backward(const float *dout, float *din, int32_t B, int32_t H, int32_t W, int32_t C,
                           void *stream) {
     if (!dout || !din || B <= 0 || H <= 0 || W <= 0 || C <= 0) return -1;
+    if (fits_v4(C, (int64_t)B * H * W * (C / 4)) && aligned16(dout, din)) {
+        hipLaunchKernelGGL(up2_v4_kernel, dim3(grid_for((int64_t)B * H * W * (C / 4))), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), reinterpret_cast<const float4 *>(dout),
+                           reinterpret_cast<float4 *>(din), B, H, W, C / 4, 1);
+        return done(hipGetLastError());
+    }
     hipLaunchKernelGGL(up2_kernel, dim3(grid_for((int64_t)B * H * W * C)), dim3(256), 0,
                        static_cast<hipStream_t>(stream), dout, din, B, H, W, C, 1);
     return done(hipGetLastError());
@@ -809,6 +904,13 @@ int asf_warm_copy_channels(const float *src, int32_t src_c, int32_t src_off, flo
     if (!src || !dst || count <= 0 || npix <= 0 || src_off < 0 || dst_off < 0 || src_off + count > src_c ||
         dst_off + count > dst_c)
         return -1;
+    if (((src_c | src_off | dst_c | dst_off | count) & 3) == 0 && fits_v4(4, npix * (count / 4)) && aligned16(src, dst)) {
+        const int64_t n = npix * (count / 4);
+        hipLaunchKernelGGL(copy_channels_v4_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                           reinterpret_cast<const float4 *>(src), src_c / 4, src_off / 4,
+                           reinterpret_cast<float4 *>(dst), dst_c / 4, dst_off / 4, count / 4, (unsigned)n);
+        return done(hipGetLastError());
+    }
     hipLaunchKernelGGL(copy_channels_kernel, dim3(grid_for(npix * count)), dim3(256), 0,
                        static_cast<hipStream_t>(stream), src, src_c, src_off, dst, dst_c, dst_off, count, npix);
     return done(hipGetLastError());

@@ -92,29 +92,31 @@ def test_conv3x3_gradients(B, H, W, cin, cout):
     assert e_w < 1e-5 and e_b < 1e-5 and e_x < 1e-5
 
 
-def test_pool_up_copy_relu_axpy():
+# C = 5: the one-channel kernels; C = 8: four channels per thread (float4)
+@pytest.mark.parametrize("C,src_off,dst_c,dst_off,count", [(5, 1, 9, 4, 3), (8, 4, 12, 8, 4)])
+def test_pool_up_copy_relu_axpy(C, src_off, dst_c, dst_off, count):
     torch, ws, wo = _setup()
     rng = np.random.default_rng(3)
     L = ws._lib()
     s = ws._stream(torch)
-    x = rng.standard_normal((2, 6, 10, 5)).astype(np.float32)
+    x = rng.standard_normal((2, 6, 10, C)).astype(np.float32)
     xt = torch.from_numpy(x).cuda()
-    p = torch.empty((2, 3, 5, 5), dtype=torch.float32, device="cuda")
-    assert L.asf_warm_pool2(ws._ptr(xt), ws._ptr(p), 2, 6, 10, 5, s) == 0
+    p = torch.empty((2, 3, 5, C), dtype=torch.float32, device="cuda")
+    assert L.asf_warm_pool2(ws._ptr(xt), ws._ptr(p), 2, 6, 10, C, s) == 0
     assert _rel(p.cpu().numpy(), wo.pool2(x)) < 1e-7
     pb = torch.empty_like(xt)
-    assert L.asf_warm_pool2_backward(ws._ptr(p), ws._ptr(pb), 2, 6, 10, 5, s) == 0
+    assert L.asf_warm_pool2_backward(ws._ptr(p), ws._ptr(pb), 2, 6, 10, C, s) == 0
     assert _rel(pb.cpu().numpy(), wo.pool2_backward(p.cpu().numpy())) < 1e-7
-    u = torch.empty((2, 12, 20, 5), dtype=torch.float32, device="cuda")
-    assert L.asf_warm_up2(ws._ptr(xt), ws._ptr(u), 2, 6, 10, 5, s) == 0
+    u = torch.empty((2, 12, 20, C), dtype=torch.float32, device="cuda")
+    assert L.asf_warm_up2(ws._ptr(xt), ws._ptr(u), 2, 6, 10, C, s) == 0
     assert np.array_equal(u.cpu().numpy(), wo.up2(x))
     ub = torch.empty_like(xt)
-    assert L.asf_warm_up2_backward(ws._ptr(u), ws._ptr(ub), 2, 6, 10, 5, s) == 0
+    assert L.asf_warm_up2_backward(ws._ptr(u), ws._ptr(ub), 2, 6, 10, C, s) == 0
     assert _rel(ub.cpu().numpy(), wo.up2_backward(u.cpu().numpy())) < 1e-7
-    dst = torch.zeros((2, 6, 10, 9), dtype=torch.float32, device="cuda")
-    assert L.asf_warm_copy_channels(ws._ptr(xt), 5, 1, ws._ptr(dst), 9, 4, 3, 120, s) == 0
-    want = np.zeros((2, 6, 10, 9), dtype=np.float32)
-    want[..., 4:7] = x[..., 1:4]
+    dst = torch.zeros((2, 6, 10, dst_c), dtype=torch.float32, device="cuda")
+    assert L.asf_warm_copy_channels(ws._ptr(xt), C, src_off, ws._ptr(dst), dst_c, dst_off, count, 120, s) == 0
+    want = np.zeros((2, 6, 10, dst_c), dtype=np.float32)
+    want[..., dst_off:dst_off + count] = x[..., src_off:src_off + count]
     assert np.array_equal(dst.cpu().numpy(), want)
     dy = torch.from_numpy(rng.standard_normal(x.shape).astype(np.float32)).cuda()
     dx = torch.empty_like(dy)
