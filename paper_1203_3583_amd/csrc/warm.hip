@@ -471,7 +471,7 @@ constexpr int64_t kWgradMaxRun = 64;
 __global__ __launch_bounds__(256) void conv3x3_wgrad_lds_kernel(
     const float *__restrict__ in, const float *__restrict__ dout, float *__restrict__ dw,
     float *__restrict__ dbias, int H, int W, int cin, int cout, int tiles_x, int tiles_y, int64_t ntiles,
-    int chunk) {
+    int run) {
     __shared__ __align__(16) uint16_t dT[32 * kWgDPitch];
     __shared__ __align__(16) uint16_t xT[32 * kWgXPitch];
     __shared__ float bred[4][8][4];
@@ -486,8 +486,8 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_lds_kernel(
 #pragma unroll
     for (int q = 0; q < 9; ++q) acc[q] = (v4f){0.f, 0.f, 0.f, 0.f};
     float bs[4] = {0.f, 0.f, 0.f, 0.f};
-    const int64_t t0 = (int64_t)blockIdx.x * chunk;
-    const int64_t t1 = t0 + chunk < ntiles ? t0 + chunk : ntiles;
+    const int64_t t0 = (int64_t)blockIdx.x * run;   // this workgroup's run of tiles
+    const int64_t t1 = t0 + run < ntiles ? t0 + run : ntiles;
     for (int64_t t = t0; t < t1; ++t) {
         const int tx = (int)(t % tiles_x);
         const int64_t rest = t / tiles_x;
