@@ -215,7 +215,7 @@ def warm_bench(torch, steps=3):
     total = start.elapsed_time(stop) / steps
     start.record()
     for _ in range(steps):
-        net.forward(pr.net_input(d, inten))
+        net.infer(pr.net_input(d, inten))
     stop.record()
     torch.cuda.synchronize()
     fwd = start.elapsed_time(stop) / steps

@@ -34,6 +34,19 @@ int asf_warm_conv3x3(const float *in, const uint16_t *w, const float *bias, floa
                      int32_t H, int32_t W, int32_t cin, int32_t cout, int32_t relu, void *stream);
 
 /*
+ * asf_warm_conv3x3 of the decoder's concatenated input, read in place: channels
+ * 0 .. c_low-1 are the 2x nearest-neighbour upsampling of low [B][H/2][W/2][c_low],
+ * channels c_low .. c_low+c_skip-1 are skip [B][H][W][c_skip]; w [cout][3][3][c_low+c_skip].
+ * The result equals (bit for bit) asf_warm_up2 and two asf_warm_copy_channels into
+ * one tensor followed by asf_warm_conv3x3.  H, W even; c_low, c_skip multiples of 32,
+ * cout a multiple of 32; layers with fewer than 64 (8 x 32-pixel tiles x cout/32)
+ * are refused (-1): the caller concatenates those.
+ */
+int asf_warm_conv3x3_upcat(const float *low, int32_t c_low, const float *skip, int32_t c_skip,
+                           const uint16_t *w, const float *bias, float *out, int32_t B, int32_t H,
+                           int32_t W, int32_t cout, int32_t relu, void *stream);
+
+/*
  * Weight gradient of asf_warm_conv3x3 (before the activation):
  *   dw[co, ky, kx, ci] += sum_{b,y,x} dout[b,y,x,co] in[b, y+ky-1, x+kx-1, ci]
  *   dbias[co] += sum_{b,y,x} dout[b,y,x,co]      (dbias may be NULL)

@@ -235,9 +235,28 @@ __global__ __launch_bounds__(256) void conv3x3_tiled_kernel(
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 constexpr int64_t kConvWorkgroupsWanted = 1024;   // four per CU
 
+// The input of a 32-channel-slice convolution, channels-last: one tensor, or the
+// decoder's concatenation read in place -- the 2x nearest-neighbour upsampling of a
+// half-size tensor's c_low channels, then a full-size tensor's cin - c_low channels
+// (c_low a multiple of 32, so every slice lies in one of the two).
+struct ConvInput {
+    const float *in;     // [B][H][W][cin], or NULL for the concatenation
+    const float *low;    // [B][H/2][W/2][c_low]
+    const float *skip;   // [B][H][W][cin - c_low]
+    int c_low;
+    // channels c0 .. c0 + 3 of pixel (b, y, x)
+    __device__ __forceinline__ const float4 *at(size_t b, int y, int x, int H, int W, int cin, int c0) const {
+        const float *p;
+        if (in) p = in + ((b * H + y) * W + x) * cin + c0;
+        else if (c0 < c_low) p = low + ((b * (H >> 1) + (y >> 1)) * (W >> 1) + (x >> 1)) * c_low + c0;
+        else p = skip + ((b * H + y) * W + x) * (cin - c_low) + (c0 - c_low);
+        return reinterpret_cast<const float4 *>(p);
+    }
+};
+
 template <int TH>
 __global__ __launch_bounds__(256) void conv3x3_tiled32_kernel(
-    const float *__restrict__ in, const uint16_t *__restrict__ w, const float *__restrict__ bias,
+    ConvInput src, const uint16_t *__restrict__ w, const float *__restrict__ bias,
     float *__restrict__ out, int H, int W, int cin, int cout, int relu, int tiles_x, int tiles_y) {
     constexpr int HH = TH + 2;
     constexpr int BPW = TH / 2;            // 16-pixel blocks per wave (two per tile row)
@@ -263,8 +282,7 @@ __global__ __launch_bounds__(256) void conv3x3_tiled32_kernel(
             const int hy = pix / kHWd, hx = pix - hy * kHWd;
             const int yy = y0 + hy - 1, xx = x0 + hx - 1;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                v = *reinterpret_cast<const float4 *>(in + (img + (size_t)yy * W + xx) * cin + c0 + 4 * q);
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = *src.at(b, yy, xx, H, W, cin, c0 + 4 * q);
             *reinterpret_cast<v4s *>(halo + pix * 32 + 4 * q) = bf16x4(v);
         }
         for (int i = tid; i < 32 * 9 * 4; i += 256) {
@@ -759,7 +777,26 @@ inline bool aligned16(const void *a, const void *b) {
 }
 inline bool fits_v4(int c, int64_t items) { return (c & 3) == 0 && items > 0 && items < ((int64_t)1 << 31); }
 
+// 32-channel-slice convolution in 8-, 4- or 2-row tiles (the most rows that still
+// give kConvWorkgroupsWanted workgroups, else 2)
+void launch_tiled32(const ConvInput &src, const uint16_t *w, const float *bias, float *out, int B, int H, int W,
+                    int cin, int cout, int relu, hipStream_t st) {
+    const int tiles_x = (W + kTW - 1) / kTW, cb = cout / 32;
+    const int64_t t8 = (int64_t)B * tiles_x * ((H + 7) / 8), t4 = (int64_t)B * tiles_x * ((H + 3) / 4),
+                  t2 = (int64_t)B * tiles_x * ((H + 1) / 2);
+    if (t8 * cb >= kConvWorkgroupsWanted)
+        hipLaunchKernelGGL(conv3x3_tiled32_kernel<8>, dim3((unsigned)t8, cb), dim3(256), 0, st, src, w, bias, out, H,
+                           W, cin, cout, relu, tiles_x, (H + 7) / 8);
+    else if (t4 * cb >= kConvWorkgroupsWanted)
+        hipLaunchKernelGGL(conv3x3_tiled32_kernel<4>, dim3((unsigned)t4, cb), dim3(256), 0, st, src, w, bias, out, H,
+                           W, cin, cout, relu, tiles_x, (H + 3) / 4);
+    else
+        hipLaunchKernelGGL(conv3x3_tiled32_kernel<2>, dim3((unsigned)t2, cb), dim3(256), 0, st, src, w, bias, out, H,
+                           W, cin, cout, relu, tiles_x, (H + 1) / 2);
+}
+
 }  // namespace
+
 
 extern "C" {
 
@@ -777,17 +814,8 @@ int asf_warm_conv3x3(const float *in, const uint16_t *w, const float *bias, floa
     if (tiles * (cout / 32) >= 64 && tiles < (int64_t)1 << 31) {
         const int cb = cout / 32;
         if (cin % 32 == 0) {
-            const int64_t t4 = (int64_t)B * tiles_x * ((H + 3) / 4), t2 = (int64_t)B * tiles_x * ((H + 1) / 2);
             hipStream_t st = static_cast<hipStream_t>(stream);
-            if (tiles * cb >= kConvWorkgroupsWanted)
-                hipLaunchKernelGGL(conv3x3_tiled32_kernel<8>, dim3((unsigned)tiles, cb), dim3(256), 0, st, in, w,
-                                   bias, out, H, W, cin, cout, relu, tiles_x, tiles_y);
-            else if (t4 * cb >= kConvWorkgroupsWanted)
-                hipLaunchKernelGGL(conv3x3_tiled32_kernel<4>, dim3((unsigned)t4, cb), dim3(256), 0, st, in, w,
-                                   bias, out, H, W, cin, cout, relu, tiles_x, (H + 3) / 4);
-            else
-                hipLaunchKernelGGL(conv3x3_tiled32_kernel<2>, dim3((unsigned)t2, cb), dim3(256), 0, st, in, w,
-                                   bias, out, H, W, cin, cout, relu, tiles_x, (H + 1) / 2);
+            launch_tiled32(ConvInput{in, nullptr, nullptr, 0}, w, bias, out, B, H, W, cin, cout, relu, st);
         } else {
             hipLaunchKernelGGL(conv3x3_tiled_kernel, dim3((unsigned)tiles, cb), dim3(256), 0,
                                static_cast<hipStream_t>(stream), in, w, bias, out, H, W, cin, cout, relu, tiles_x,
@@ -799,6 +827,19 @@ int asf_warm_conv3x3(const float *in, const uint16_t *w, const float *bias, floa
         hipLaunchKernelGGL(conv3x3_kernel<1>, grid, dim3(64 * kConvWaves), 0, static_cast<hipStream_t>(stream), in,
                            w, bias, out, B, H, W, cin, cout, relu);
     }
+    return done(hipGetLastError());
+}
+
+int asf_warm_conv3x3_upcat(const float *low, int32_t c_low, const float *skip, int32_t c_skip, const uint16_t *w,
+                           const float *bias, float *out, int32_t B, int32_t H, int32_t W, int32_t cout,
+                           int32_t relu, void *stream) {
+    if (!low || !skip || !w || !out || B <= 0 || H <= 1 || W <= 1 || (H & 1) || (W & 1) || c_low <= 0 ||
+        c_skip <= 0 || c_low % 32 || c_skip % 32 || cout <= 0 || cout % 32)
+        return -1;
+    const int64_t tiles = (int64_t)B * ((W + kTW - 1) / kTW) * ((H + kTH - 1) / kTH);
+    if (tiles * (cout / 32) < 64 || tiles >= ((int64_t)1 << 30)) return -1;   // the tiled layers only
+    launch_tiled32(ConvInput{nullptr, low, skip, c_low}, w, bias, out, B, H, W, c_low + c_skip, cout, relu,
+                   static_cast<hipStream_t>(stream));
     return done(hipGetLastError());
 }
 

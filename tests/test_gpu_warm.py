@@ -57,6 +57,40 @@ def test_conv3x3_forward(B, H, W, cin, cout, relu):
     assert L.asf_warm_conv3x3(ws._ptr(xt), ws._ptr(wb), None, ws._ptr(out), B, H, W, cin + 1, cout, 0, s) == -1
 
 
+# the decoder's concatenation read in place, in 8-, 4- and 2-row tiles (the last ragged and two
+# images): bit for bit what upsampling, two channel copies and the convolution give
+@pytest.mark.parametrize("B,H,W,c_low,c_skip,cout", [(1, 512, 512, 64, 32, 32), (1, 256, 256, 32, 64, 64),
+                                                     (2, 130, 70, 32, 32, 64)])
+def test_conv3x3_upcat_matches_concatenation(B, H, W, c_low, c_skip, cout):
+    torch, ws, wo = _setup()
+    rng = np.random.default_rng(H + c_low)
+    low = torch.from_numpy(rng.standard_normal((B, H // 2, W // 2, c_low)).astype(np.float32)).cuda()
+    skip = torch.from_numpy(rng.standard_normal((B, H, W, c_skip)).astype(np.float32)).cuda()
+    cin = c_low + c_skip
+    _, wb, _ = _weights(torch, ws, rng, cout, cin)
+    bt = torch.from_numpy(rng.standard_normal(cout).astype(np.float32)).cuda()
+    L = ws._lib()
+    s = ws._stream(torch)
+    fused = torch.empty((B, H, W, cout), dtype=torch.float32, device="cuda")
+    assert L.asf_warm_conv3x3_upcat(ws._ptr(low), c_low, ws._ptr(skip), c_skip, ws._ptr(wb), ws._ptr(bt),
+                                    ws._ptr(fused), B, H, W, cout, 1, s) == 0
+    up = torch.empty((B, H, W, c_low), dtype=torch.float32, device="cuda")
+    assert L.asf_warm_up2(ws._ptr(low), ws._ptr(up), B, H // 2, W // 2, c_low, s) == 0
+    cat = torch.empty((B, H, W, cin), dtype=torch.float32, device="cuda")
+    assert L.asf_warm_copy_channels(ws._ptr(up), c_low, 0, ws._ptr(cat), cin, 0, c_low, B * H * W, s) == 0
+    assert L.asf_warm_copy_channels(ws._ptr(skip), c_skip, 0, ws._ptr(cat), cin, c_low, c_skip, B * H * W, s) == 0
+    want = torch.empty_like(fused)
+    assert L.asf_warm_conv3x3(ws._ptr(cat), ws._ptr(wb), ws._ptr(bt), ws._ptr(want), B, H, W, cin, cout, 1, s) == 0
+    assert np.array_equal(fused.cpu().numpy(), want.cpu().numpy())
+    # refused: odd size, channel counts off 32, a layer too small for the tiled kernel
+    assert L.asf_warm_conv3x3_upcat(ws._ptr(low), c_low, ws._ptr(skip), c_skip, ws._ptr(wb), None,
+                                    ws._ptr(fused), B, H - 1, W, cout, 0, s) == -1
+    assert L.asf_warm_conv3x3_upcat(ws._ptr(low), c_low - 16, ws._ptr(skip), c_skip + 16, ws._ptr(wb), None,
+                                    ws._ptr(fused), B, H, W, cout, 0, s) == -1
+    assert L.asf_warm_conv3x3_upcat(ws._ptr(low), c_low, ws._ptr(skip), c_skip, ws._ptr(wb), None,
+                                    ws._ptr(fused), 1, 16, 16, cout, 0, s) == -1
+
+
 # direct kernel (16 and 48 input channels), LDS-staged kernel (multiples of 32: one tile per
 # workgroup, then runs of tiles crossing image boundaries with one and two input-channel blocks)
 @pytest.mark.parametrize("B,H,W,cin,cout", [(2, 8, 12, 16, 32), (1, 5, 7, 48, 64), (3, 32, 32, 32, 32),
@@ -154,6 +188,21 @@ def _oracle_params(net):
         w = (wv.astype(np.uint32) << 16).view(np.float32).astype(np.float64).reshape(co, 3, 3, ci)
         params.append((w, net.b[i].cpu().numpy().astype(np.float64)))
     return params
+
+
+@pytest.mark.parametrize("side", [16, 256])
+def test_infer_matches_forward(side):
+    """Inference without kept activations (at 256^2 the three decoder concatenations are
+    read in place by their convolutions, at 16^2 they are too small and concatenated):
+    bit for bit the output of the training forward."""
+    torch, ws, wo = _setup()
+    net = ws.WarmNet(base=32, seed=4, head_scale=1.0)
+    rng = np.random.default_rng(side)
+    x = np.zeros((1, side, side, 16), dtype=np.float32)
+    x[..., :2] = rng.standard_normal((1, side, side, 2))
+    xt = torch.from_numpy(x).cuda()
+    out, _ = net.forward(xt)
+    assert np.array_equal(net.infer(xt).cpu().numpy(), out.cpu().numpy())
 
 
 def test_network_forward_and_gradient():
