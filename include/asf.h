@@ -106,11 +106,17 @@ typedef struct {
        status bit 2 says the compact layout (tile_start) is in use */
     size_t off_cursor, off_slab;
     /* crowded tiles cut into slices of records (u32 [ntiles]: 0, or first partial slot
-       << 8 | slices, meaningful for tiles of more records than split_meta[0]; u32 [2]:
-       that threshold and the partial slots in use; u32 [512]: tile << 8 | slice per
-       slot), and the resident workgroups the cut is sized against (0: never cut) */
+       << 8 | slices, meaningful for tiles of more records than split_meta[0]; u32 [3]:
+       that threshold, the partial slots in use and the tiles no record reaches; u32
+       [512]: tile << 8 | slice per slot), and the resident workgroups the cut is sized
+       against (0: never cut) */
     size_t off_split, off_split_meta, off_slot_owner;
     uint32_t split_slots;
+    /* per-tile flags of the last binning (u8 [ntiles], in tile order ty * ntx + tx): 1
+       where some record reaches the tile, 0 where none does.  When many tiles are
+       empty the transforms leave those tiles' fine-grid cells as they were (the
+       forward's column pass reads them as zeros) */
+    size_t off_live;
 } asf_info;
 
 /*

@@ -57,7 +57,7 @@ class Info(ctypes.Structure):
                 ("ws_bytes", ctypes.c_size_t), ("off_cursor", ctypes.c_size_t),
                 ("off_slab", ctypes.c_size_t), ("off_split", ctypes.c_size_t),
                 ("off_split_meta", ctypes.c_size_t), ("off_slot_owner", ctypes.c_size_t),
-                ("split_slots", ctypes.c_uint32)]
+                ("split_slots", ctypes.c_uint32), ("off_live", ctypes.c_size_t)]
 
 
 class LineParams(ctypes.Structure):

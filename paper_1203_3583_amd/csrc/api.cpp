@@ -50,6 +50,7 @@ struct asf_plan_s {
     int timing;
     bool count_first;   // bin with the compact layout directly (crowded last time)
     bool sized_slabs;   // the slabs were sized from a crowded binning's counts
+    bool sparse;        // many tiles empty last time: leave them unwritten, the column pass reads zeros
     int copy;           // which copy of status and cursor the last binning used
     bool clear_both;    // clear both copies first (new plan, or a failed binning launch)
     uint32_t slots;     // workgroups resident at once (crowded tiles are cut against it); 0: never cut
@@ -194,11 +195,19 @@ int upload_tables(asf_plan_s *p, hipStream_t s) {
 }
 
 int read_status(asf_plan_s *p, hipStream_t s) {
-    uint32_t st = 0;
+    uint32_t st = 0, empty = 0;
     hipError_t e = hipMemcpyAsync(&st, p->bin.status, sizeof st, hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return hip_fail(e, "status read");
+    e = hipMemcpyAsync(&empty, p->bin.split_meta + 2, sizeof empty, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "empty-tile count read");
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    // a quarter of the tiles or more empty: the next transforms leave them unwritten
+    // (spreading, the adjoint's column pass) and the forward's column pass reads them
+    // as zeros (either form is exact for any geometry, the flags being rewritten by
+    // every binning; this one saves the empty tiles' writes and reads)
+    p->sparse = (uint64_t)empty * 4 >= (uint64_t)p->lay.ntiles;
+    p->sp.skip_dead = p->sparse ? 1 : 0;
     // kStatusCompact and kStatusFits only describe the binned layout: the next
     // binning counts first if this one needed the compact layout, unless its
     // scan sized new slabs from the counts that fit in the slot arrays
@@ -252,6 +261,7 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
     pl->bin.split = reinterpret_cast<uint32_t *>(w + L.off_split);
     pl->bin.split_meta = reinterpret_cast<uint32_t *>(w + L.off_split_meta);
     pl->bin.slot_owner = reinterpret_cast<uint32_t *>(w + L.off_slot_owner);
+    pl->bin.live = reinterpret_cast<uint8_t *>(w + L.off_live);
     pl->bin.combine = reinterpret_cast<uint32_t *>(w + L.off_combine);
     pl->bin.partial = reinterpret_cast<unsigned long long *>(w + L.off_partial);
     pl->fine = reinterpret_cast<float2 *>(w + L.off_fine);
@@ -306,6 +316,8 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
     pl->sp.log_panel = log2i(panel);
     pl->sp.beta_log2e = (float)(L.beta * 1.4426950408889634);
     pl->sp.split = L.split ? 1 : 0;
+    pl->sp.skip_dead = 0;
+    pl->sparse = false;
     // three spreading workgroups fit a compute unit at once
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -341,6 +353,13 @@ int asf_status(asf_plan_t plan, void *stream) {
 
 namespace {
 
+// The binning's per-tile flags for the column passes, when the plan leaves the tiles
+// no record reaches unwritten.
+asf::LiveTiles live_tiles(const asf_plan_s *p) {
+    return asf::LiveTiles{p->sp.skip_dead ? p->bin.live : nullptr, p->lay.ntx, p->lay.nty,
+                          log2i(p->lay.tile_x), log2i(p->lay.tile_y)};
+}
+
 // Spread, column pass and row pass into u2; fine and mid are the fine grid and the
 // column pass's output (the plan's workspace, or the static scratch).
 int forward_into(asf_plan_t plan, const void *u1, void *u2, void *stream, int accumulate, float2 *fine,
@@ -356,7 +375,8 @@ int forward_into(asf_plan_t plan, const void *u1, void *u2, void *stream, int ac
     }
     {
         StageMark m(p, asf::STAGE_FFT1, s);
-        e = asf::launch_fft_pass1(p->sh1, split, fine, mid, p->twy, p->w16, p->lay.nfx, p->lay.my, s);
+        e = asf::launch_fft_pass1(p->sh1, split, fine, mid, p->twy, p->w16, p->lay.nfx, p->lay.my,
+                                  live_tiles(p), s);
         if (e != hipSuccess) return hip_fail(e, "fft pass 1 launch");
     }
     {
@@ -415,7 +435,7 @@ int asf_adjoint(asf_plan_t plan, const void *g2, void *g1, void *stream) {
     {
         StageMark m(p, asf::STAGE_ADJ_FFT1, s);
         e = asf::launch_fft_adj_cols(p->lay.nfy, split, p->mid, p->fine, p->twy, p->w16, p->lay.nfx,
-                                     p->lay.my, s);
+                                     p->lay.my, live_tiles(p), s);
         if (e != hipSuccess) return hip_fail(e, "adjoint column pass launch");
     }
     {
@@ -458,6 +478,7 @@ int asf_plan_info(asf_plan_t plan, asf_info *info) {
     info->off_split_meta = L.off_split_meta;
     info->off_slot_owner = L.off_slot_owner;
     info->split_slots = plan->slots;
+    info->off_live = L.off_live;
     return ASF_OK;
 }
 

@@ -37,7 +37,12 @@ struct Binned {
     // split[t] >> 8 onward of the partial tiles); slot_owner[q] = t << 8 | slice
     // for the split_meta[1] slots in use.
     uint32_t *split;       // [ntiles]
-    uint32_t *split_meta;  // [2] record threshold, slots in use
+    uint32_t *split_meta;  // [3] record threshold, slots in use, tiles no record reaches
+    // Per tile, in tile order: 1 if some record reaches it, else 0 (written by every
+    // binning's scan, on grids whose tiles may be cut).  Tiles flagged 0 may be left
+    // unwritten by the spreading and the adjoint's column pass: the forward's column
+    // pass then reads them as zeros, and no interpolation footprint reaches them.
+    uint8_t *live;         // [ntiles]
     uint32_t *slot_owner;  // [kSplitSlots]
     uint32_t *combine;     // [kSplitSlots] slices finished per split tile (zero between launches)
     unsigned long long *partial;   // [kSplitSlots][2][tile cells] integer sums of the slices (Re, Im),
@@ -129,6 +134,15 @@ struct SpreadParams {
     int log_panel;     // fine-grid panel width (columns stored contiguously per row), log2
     float beta_log2e;  // ES shape beta times log2(e), for exp2
     int split;         // 1: crowded tiles may be cut (launches take kSplitSlots more workgroups)
+    int skip_dead;     // 1: tiles no record reaches are left unwritten
+};
+
+// The binning's per-tile flags (Binned::live) as the column passes take them.
+// Forward: tiles flagged 0 were not written and are read as zeros; adjoint: their
+// cells are not needed.  flag NULL: every tile is written and read.
+struct LiveTiles {
+    const uint8_t *flag;   // [ty][tx]
+    int ntx, nty, log_tile_x, log_tile_y;
 };
 
 // One batch of same-length FFTs.  In the first pass (along y) a workgroup
@@ -193,7 +207,8 @@ hipError_t launch_spread(const SpreadParams &p, const Binned &b, const float2 *u
                          hipStream_t s);
 // pass 1: columns of the fine grid (panel layout) -> mid (my x nfx, same panel layout)
 hipError_t launch_fft_pass1(const FftShape &sh, int split16, const float2 *fine, float2 *mid,
-                            const float2 *tw, const float2 *w16, int nfx, int my, hipStream_t s);
+                            const float2 *tw, const float2 *w16, int nfx, int my, const LiveTiles &lt,
+                            hipStream_t s);
 // pass 2: rows of mid (panels of 2^log_panel columns) -> u2[my][mx] with the
 // deconvolution and destination phase
 hipError_t launch_fft_pass2(const FftShape &sh, int log_panel, int split16, const float2 *mid,
@@ -205,7 +220,8 @@ hipError_t launch_fft_adj_rows(int len, int split16, const float2 *g2, float2 *m
                                hipStream_t s);
 // adjoint: columns of mid (zero-padded) -> fine grid (panel layout)
 hipError_t launch_fft_adj_cols(int len, int split16, const float2 *mid, float2 *fine,
-                               const float2 *tw, const float2 *w16, int nfx, int my, hipStream_t s);
+                               const float2 *tw, const float2 *w16, int nfx, int my, const LiveTiles &lt,
+                               hipStream_t s);
 // adjoint of spreading: fine grid -> g1[n] (caller's order)
 hipError_t launch_interp(const SpreadParams &p, const Binned &b, const float2 *fine, float2 *g1,
                          hipStream_t s);

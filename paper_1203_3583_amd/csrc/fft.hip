@@ -4,7 +4,10 @@
 //
 // A 2D forward DFT (exp(-i) sign) of the nfx x nfy fine grid is done in two
 // passes, each pruned to the modes the destination grid keeps:
-//   pass 1: every fine-grid column (length nfy), keep the my centred modes,
+//   pass 1: every fine-grid column (length nfy; where the plan leaves the tiles no
+//           record reaches unwritten, their cells read as zeros without a load, and
+//           a panel of columns with no such tile writes zeros without a transform),
+//           keep the my centred modes,
 //           write them to mid in the fine grid's panel layout (panels of C
 //           adjacent columns, element (lx, ky) at ((lx / C) my + ky) C + lx % C),
 //           so that each workgroup writes one contiguous block;
@@ -387,23 +390,61 @@ __device__ __forceinline__ int range_exponent(float max_abs) {
     return e;
 }
 
+// Tile rows of the fine grid: at most 16384 / 32.
+constexpr int kMaxTileRows = 512;
+
+// With flags (tiles no record reaches, left unwritten): the flags of the tile column
+// holding fine-grid column x0, one byte per tile row, into LDS.  Returns whether
+// flags are in use.
+__device__ __forceinline__ bool live_rows(const LiveTiles &lt, int x0, uint8_t *lrow) {
+    if (!lt.flag) return false;
+    const uint8_t *col = lt.flag + (x0 >> lt.log_tile_x);
+    for (int i = threadIdx.x; i < lt.nty; i += blockDim.x) lrow[i] = col[(size_t)i * lt.ntx];
+    __syncthreads();
+    return true;
+}
+
+// With flags: whether any tile of that tile column was written (the same answer in
+// every thread).  A panel with none transforms to zeros.
+__device__ __forceinline__ bool any_live(const LiveTiles &lt, const uint8_t *lrow) {
+    int any = 0;
+    for (int i = threadIdx.x; i < lt.nty; i += blockDim.x) any |= lrow[i];
+    return __syncthreads_or(any) != 0;
+}
+
+// A panel's block of mid (count float2, count even, 16-byte aligned) set to zeros.
+__device__ __forceinline__ void zero_block(float2 *dst, int count) {
+    float4 *d = reinterpret_cast<float4 *>(dst);
+    for (int i = threadIdx.x; i < count / 2; i += blockDim.x) d[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 // Pass 1: a workgroup transforms one panel of BATCH adjacent fine-grid columns.
 template <int LOGL, int BATCH, int NT, bool SPLIT>
 __global__ void __launch_bounds__(NT) fft_pass1_kernel(const float2 *__restrict__ fine,
                                                        float2 *__restrict__ mid,
                                                        const float2 *__restrict__ tw,
-                                                       const float2 *__restrict__ w16, int my) {
+                                                       const float2 *__restrict__ w16, int my,
+                                                       LiveTiles lt) {
     using S = Len<LOGL>;
     extern __shared__ float2 lds[];
     __shared__ float scratch[NT / 64];
+    __shared__ uint8_t lrow[kMaxTileRows];
     const int pc = blockIdx.x;
     const float2 *src = fine + (size_t)pc * S::L * BATCH;
+    const bool sparse = live_rows(lt, pc * BATCH, lrow);
+    if (sparse && !any_live(lt, lrow)) {
+        zero_block(mid + (size_t)pc * my * BATCH, my * BATCH);
+        return;
+    }
     float big = 0.f;
-    // every load in flight before the first LDS write
+    // every load in flight before the first LDS write (none for tiles left unwritten)
     constexpr int PER = S::L * BATCH / NT;
     float2 v[PER];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) v[k] = src[threadIdx.x + k * NT];
+    for (int k = 0; k < PER; ++k) {
+        const int t = threadIdx.x + k * NT;
+        v[k] = (!sparse || lrow[(t / BATCH) >> lt.log_tile_y]) ? src[t] : make_float2(0.f, 0.f);
+    }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int t = threadIdx.x + k * NT;
@@ -572,22 +613,30 @@ __global__ void __launch_bounds__(NT) fft_adj_rows_kernel(const float2 *__restri
 
 // Adjoint pass 1: a workgroup takes BATCH adjacent columns of mid (the my kept
 // rows), zero-pads to nfy and writes the transformed columns to the fine grid
-// in its panel layout (one contiguous block per workgroup).  The 16 / BATCH
+// in its panel layout (one contiguous block per workgroup; with the binning's
+// flags, only the cells of tiles some record reaches, which are all that the
+// interpolation uses).  The 16 / BATCH
 // panels that share 128-byte lines of mid rows run on one XCD.
 template <int LOGL, int BATCH, int NT, bool SPLIT>
 __global__ void __launch_bounds__(NT) fft_adj_cols_kernel(const float2 *__restrict__ mid,
                                                           float2 *__restrict__ fine,
                                                           const float2 *__restrict__ tw,
                                                           const float2 *__restrict__ w16,
-                                                          int nfx, int my, int xcd_group) {
+                                                          int nfx, int my, int xcd_group,
+                                                          LiveTiles lt) {
     using S = Len<LOGL>;
     extern __shared__ float2 lds[];
     __shared__ float scratch[NT / 64];
+    __shared__ uint8_t lrow[kMaxTileRows];
     int pc = blockIdx.x;
     if (xcd_group > 1) {
         const int xcd = pc & 7, slot = pc >> 3;
         pc = ((slot / xcd_group) * 8 + xcd) * xcd_group + slot % xcd_group;
     }
+    // with flags: a panel no record reaches is not needed at all, and in the others
+    // only the cells of tiles some record reaches are stored
+    const bool sparse = live_rows(lt, pc * BATCH, lrow);
+    if (sparse && !any_live(lt, lrow)) return;
     const int half = my >> 1;
     float big = 0.f;
     // every load in flight before the first LDS write
@@ -622,6 +671,7 @@ __global__ void __launch_bounds__(NT) fft_adj_cols_kernel(const float2 *__restri
     float2 *dst = fine + (size_t)pc * S::L * BATCH;
     for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
         const int l = t / BATCH, c = t % BATCH;
+        if (sparse && !lrow[l >> lt.log_tile_y]) continue;
         const float2 v = lds[c * S::STRIDE + lds_pos<S::PS>(l)];
         dst[t] = make_float2(v.x * unscale, -v.y * unscale);
     }
@@ -789,16 +839,26 @@ template <int LOGL, int BATCH, int NT, bool SPLIT>
 __global__ void __launch_bounds__(NT) fft_pass1_direct_kernel(const float2 *__restrict__ fine,
                                                               float2 *__restrict__ mid,
                                                               const float2 *__restrict__ tw,
-                                                              const float2 *__restrict__ w16, int my) {
+                                                              const float2 *__restrict__ w16, int my,
+                                                              LiveTiles lt) {
     using S = Len<LOGL>;
     extern __shared__ float2 lds[];
     __shared__ float scratch[NT / 64];
+    __shared__ uint8_t lrow[kMaxTileRows];
     const int pc = blockIdx.x;
     const float2 *src = fine + (size_t)pc * S::L * BATCH;
     float2 *dst = mid + (size_t)pc * my * BATCH;   // this panel's block of mid
     const int half = my >> 1;
+    const bool sparse = live_rows(lt, pc * BATCH, lrow);
+    if (sparse && !any_live(lt, lrow)) {
+        zero_block(dst, my * BATCH);
+        return;
+    }
     transform_direct<LOGL, BATCH, NT, SPLIT>(
-        lds, tw, w16, scratch, [&](int c, int e) { return src[e * BATCH + c]; },
+        lds, tw, w16, scratch,
+        [&](int c, int e) {
+            return (!sparse || lrow[e >> lt.log_tile_y]) ? src[e * BATCH + c] : make_float2(0.f, 0.f);
+        },
         [&](int c, int l, float2 val) {
             const int ky = (l + half) & (S::L - 1);
             if (ky < my) dst[ky * BATCH + c] = val;
@@ -864,7 +924,7 @@ constexpr int threads_for() {
 
 template <int LOGL, int BATCH, bool SPLIT>
 hipError_t launch1(const FftShape &sh, const float2 *fine, float2 *mid, const float2 *tw,
-                   const float2 *w16, int nfx, int my, hipStream_t s) {
+                   const float2 *w16, int nfx, int my, const LiveTiles &lt, hipStream_t s) {
     (void)sh;
     constexpr int NT = threads_for<LOGL, BATCH>();
     const size_t lds = (size_t)BATCH * Len<LOGL>::STRIDE * sizeof(float2);
@@ -873,12 +933,12 @@ hipError_t launch1(const FftShape &sh, const float2 *fine, float2 *mid, const fl
         auto k = fft_pass1_direct_kernel<LOGL, BATCH, NT, SPLIT>;
         hipError_t e = allow_lds((const void *)k, lds, enabled);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k, dim3(nfx / BATCH), dim3(NT), lds, s, fine, mid, tw, w16, my);
+        hipLaunchKernelGGL(k, dim3(nfx / BATCH), dim3(NT), lds, s, fine, mid, tw, w16, my, lt);
     } else {
         auto k = fft_pass1_kernel<LOGL, BATCH, NT, SPLIT>;
         hipError_t e = allow_lds((const void *)k, lds, enabled);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k, dim3(nfx / BATCH), dim3(NT), lds, s, fine, mid, tw, w16, my);
+        hipLaunchKernelGGL(k, dim3(nfx / BATCH), dim3(NT), lds, s, fine, mid, tw, w16, my, lt);
     }
     return hipGetLastError();
 }
@@ -927,7 +987,7 @@ hipError_t launch_adj2(const float2 *g2, float2 *mid, const float2 *tw, const fl
 
 template <int LOGL, int BATCH, bool SPLIT>
 hipError_t launch_adj1(const float2 *mid, float2 *fine, const float2 *tw, const float2 *w16,
-                       int nfx, int my, hipStream_t s) {
+                       int nfx, int my, const LiveTiles &lt, hipStream_t s) {
     constexpr int NT = threads_for<LOGL, BATCH>();
     const size_t lds = (size_t)BATCH * Len<LOGL>::STRIDE * sizeof(float2);
     static thread_local size_t enabled = 0;
@@ -937,7 +997,7 @@ hipError_t launch_adj1(const float2 *mid, float2 *fine, const float2 *tw, const 
     const int groups = nfx / BATCH;
     const int g = BATCH < 16 ? 16 / BATCH : 1;   // panels per 128-byte line of a mid row
     const int xcd_group = (g > 1 && groups % (8 * g) == 0) ? g : 1;
-    hipLaunchKernelGGL(k, dim3(groups), dim3(NT), lds, s, mid, fine, tw, w16, nfx, my, xcd_group);
+    hipLaunchKernelGGL(k, dim3(groups), dim3(NT), lds, s, mid, fine, tw, w16, nfx, my, xcd_group, lt);
     return hipGetLastError();
 }
 
@@ -961,18 +1021,18 @@ hipError_t dispatch_adj2(int len, const float2 *g2, float2 *mid, const float2 *t
 
 template <bool SPLIT>
 hipError_t dispatch_adj1(int len, const float2 *mid, float2 *fine, const float2 *tw,
-                         const float2 *w16, int nfx, int my, hipStream_t s) {
+                         const float2 *w16, int nfx, int my, const LiveTiles &lt, hipStream_t s) {
     switch (__builtin_ctz(len)) {
-        case 5: return launch_adj1<5, 16, SPLIT>(mid, fine, tw, w16, nfx, my, s);
-        case 6: return launch_adj1<6, 16, SPLIT>(mid, fine, tw, w16, nfx, my, s);
-        case 7: return launch_adj1<7, 16, SPLIT>(mid, fine, tw, w16, nfx, my, s);
-        case 8: return launch_adj1<8, 16, SPLIT>(mid, fine, tw, w16, nfx, my, s);
-        case 9: return launch_adj1<9, 16, SPLIT>(mid, fine, tw, w16, nfx, my, s);
-        case 10: return launch_adj1<10, 8, SPLIT>(mid, fine, tw, w16, nfx, my, s);
-        case 11: return launch_adj1<11, 4, SPLIT>(mid, fine, tw, w16, nfx, my, s);
-        case 12: return launch_adj1<12, 2, SPLIT>(mid, fine, tw, w16, nfx, my, s);
-        case 13: return launch_adj1<13, 1, SPLIT>(mid, fine, tw, w16, nfx, my, s);
-        case 14: return launch_adj1<14, 1, SPLIT>(mid, fine, tw, w16, nfx, my, s);
+        case 5: return launch_adj1<5, 16, SPLIT>(mid, fine, tw, w16, nfx, my, lt, s);
+        case 6: return launch_adj1<6, 16, SPLIT>(mid, fine, tw, w16, nfx, my, lt, s);
+        case 7: return launch_adj1<7, 16, SPLIT>(mid, fine, tw, w16, nfx, my, lt, s);
+        case 8: return launch_adj1<8, 16, SPLIT>(mid, fine, tw, w16, nfx, my, lt, s);
+        case 9: return launch_adj1<9, 16, SPLIT>(mid, fine, tw, w16, nfx, my, lt, s);
+        case 10: return launch_adj1<10, 8, SPLIT>(mid, fine, tw, w16, nfx, my, lt, s);
+        case 11: return launch_adj1<11, 4, SPLIT>(mid, fine, tw, w16, nfx, my, lt, s);
+        case 12: return launch_adj1<12, 2, SPLIT>(mid, fine, tw, w16, nfx, my, lt, s);
+        case 13: return launch_adj1<13, 1, SPLIT>(mid, fine, tw, w16, nfx, my, lt, s);
+        case 14: return launch_adj1<14, 1, SPLIT>(mid, fine, tw, w16, nfx, my, lt, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -985,19 +1045,19 @@ hipError_t dispatch_adj1(int len, const float2 *mid, float2 *fine, const float2 
 // shorter than 256.
 template <bool SPLIT>
 hipError_t dispatch1(const FftShape &sh, const float2 *fine, float2 *mid, const float2 *tw,
-                     const float2 *w16, int nfx, int my, hipStream_t s) {
+                     const float2 *w16, int nfx, int my, const LiveTiles &lt, hipStream_t s) {
     const int log = __builtin_ctz(sh.L);
     switch (log) {
-        case 5: return launch1<5, 16, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
-        case 6: return launch1<6, 16, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
-        case 7: return launch1<7, 16, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
-        case 8: return launch1<8, 16, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
-        case 9: return launch1<9, 16, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
-        case 10: return launch1<10, 8, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
-        case 11: return launch1<11, 4, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
-        case 12: return launch1<12, 2, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
-        case 13: return launch1<13, 1, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
-        case 14: return launch1<14, 1, SPLIT>(sh, fine, mid, tw, w16, nfx, my, s);
+        case 5: return launch1<5, 16, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
+        case 6: return launch1<6, 16, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
+        case 7: return launch1<7, 16, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
+        case 8: return launch1<8, 16, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
+        case 9: return launch1<9, 16, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
+        case 10: return launch1<10, 8, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
+        case 11: return launch1<11, 4, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
+        case 12: return launch1<12, 2, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
+        case 13: return launch1<13, 1, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
+        case 14: return launch1<14, 1, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1049,9 +1109,11 @@ int fft_max_lds_bytes() {
 }
 
 hipError_t launch_fft_pass1(const FftShape &sh, int split16, const float2 *fine, float2 *mid,
-                            const float2 *tw, const float2 *w16, int nfx, int my, hipStream_t s) {
-    if (split16) return dispatch1<true>(sh, fine, mid, tw, w16, nfx, my, s);
-    return dispatch1<false>(sh, fine, mid, tw, w16, nfx, my, s);
+                            const float2 *tw, const float2 *w16, int nfx, int my, const LiveTiles &lt,
+                            hipStream_t s) {
+    if (lt.flag && (lt.nty > kMaxTileRows || lt.nty <= 0)) return hipErrorInvalidValue;
+    if (split16) return dispatch1<true>(sh, fine, mid, tw, w16, nfx, my, lt, s);
+    return dispatch1<false>(sh, fine, mid, tw, w16, nfx, my, lt, s);
 }
 
 hipError_t launch_fft_pass2(const FftShape &sh, int log_panel, int split16, const float2 *mid,
@@ -1069,9 +1131,11 @@ hipError_t launch_fft_adj_rows(int len, int split16, const float2 *g2, float2 *m
 }
 
 hipError_t launch_fft_adj_cols(int len, int split16, const float2 *mid, float2 *fine,
-                               const float2 *tw, const float2 *w16, int nfx, int my, hipStream_t s) {
-    if (split16) return dispatch_adj1<true>(len, mid, fine, tw, w16, nfx, my, s);
-    return dispatch_adj1<false>(len, mid, fine, tw, w16, nfx, my, s);
+                               const float2 *tw, const float2 *w16, int nfx, int my, const LiveTiles &lt,
+                               hipStream_t s) {
+    if (lt.flag && (lt.nty > kMaxTileRows || lt.nty <= 0)) return hipErrorInvalidValue;
+    if (split16) return dispatch_adj1<true>(len, mid, fine, tw, w16, nfx, my, lt, s);
+    return dispatch_adj1<false>(len, mid, fine, tw, w16, nfx, my, lt, s);
 }
 
 }  // namespace asf

@@ -379,17 +379,18 @@ __device__ inline uint64_t block_scan(const Binned &b, int ntiles, uint64_t *wsu
 // len doubles until they do not.
 template <class C>
 __device__ inline void split_plan(const Binned &b, int ntiles, uint32_t slots, uint64_t *wsum,
-                                  uint32_t *wmax, C count) {
+                                  uint32_t *wmax, uint32_t *wempty, C count) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    if (slots == 0) {   // grids whose tiles are never cut
+    if (slots == 0) {   // grids whose tiles are never cut (nor left unwritten: no flags)
         if (t == 0) {
             b.split_meta[0] = kNoSplit;
             b.split_meta[1] = 0u;
+            b.split_meta[2] = 0u;
         }
         return;
     }
     uint64_t r = 0;
-    uint32_t most = 0;
+    uint32_t most = 0, empty = 0;
     const bool compact = (b.status[0] & kStatusCompact) != 0u;
     for (int base = 0; base < ntiles; base += kScanThreads * kScanPer) {
         // kScanPer tiles' counts and slab sizes in flight (indices clamped so that
@@ -403,27 +404,38 @@ __device__ inline void split_plan(const Binned &b, int ntiles, uint32_t slots, u
         }
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
-            const uint32_t c = base + k * kScanThreads + t < ntiles ? (compact ? cur[k] : min(cur[k], cap[k])) : 0u;
+            const bool in = base + k * kScanThreads + t < ntiles;
+            const uint32_t c = in ? (compact ? cur[k] : min(cur[k], cap[k])) : 0u;
             r += c;
             most = max(most, c);
+            empty += (in && c == 0u) ? 1u : 0u;
+            if (in) b.live[base + k * kScanThreads + t] = c != 0u ? 1 : 0;
         }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         r += __shfl_xor(r, off);
         most = max(most, (uint32_t)__shfl_xor((int)most, off));
+        empty += (uint32_t)__shfl_xor((int)empty, off);
     }
     if (lane == 0) {
         wsum[wave] = r;
         wmax[wave] = most;
+        wempty[wave] = empty;
     }
     __syncthreads();
     r = 0;
     most = 0;
+    empty = 0;
     for (int k = 0; k < kScanThreads / 64; ++k) {
         r += wsum[k];
         most = max(most, wmax[k]);
+        empty += wempty[k];
     }
+    // tiles no record reaches, which the spreading and the adjoint's column pass may
+    // leave unwritten (read by the host with the status, to choose that form for the
+    // plan's next transforms)
+    if (t == 0) b.split_meta[2] = empty;
     __syncthreads();   // wsum is reused by the scans
     const uint64_t load = (r + slots - 1) / slots;
     const uint64_t thr64 = max((uint64_t)kSplitMinRecords, 2 * load);
@@ -465,11 +477,11 @@ __device__ inline void split_plan(const Binned &b, int ntiles, uint32_t slots, u
 
 __global__ void __launch_bounds__(kScanThreads) bin_scan_kernel(Binned b, int ntiles, uint32_t slots) {
     __shared__ uint64_t wsum[kScanThreads / 64];
-    __shared__ uint32_t wmax[kScanThreads / 64];
+    __shared__ uint32_t wmax[kScanThreads / 64], wempty[kScanThreads / 64];
     const bool compact = (b.status[0] & kStatusCompact) != 0u;
     // record counts: the compact layout's counting pass, or the slabs' cursors
     // (past a full slab a cursor keeps counting records that were not written)
-    split_plan(b, ntiles, slots, wsum, wmax, [&](int i) -> uint32_t {
+    split_plan(b, ntiles, slots, wsum, wmax, wempty, [&](int i) -> uint32_t {
         return compact ? b.cursor[i] : min(b.cursor[i], b.slab[i].y);
     });
     if (!compact) return;   // every slab held its tile

@@ -46,6 +46,7 @@ struct Layout {
     // crowded tiles cut into slices (only grids wider than a tile plus its halo)
     bool split;
     size_t off_split, off_split_meta, off_slot_owner, off_combine, off_partial;
+    size_t off_live;   // per-tile flags of the last spread (u8 [ntx][nty])
     size_t total;
 };
 

@@ -7,8 +7,11 @@
 // One workgroup owns one tile of the fine grid.  Its bin lists every point whose
 // footprint touches the tile, so the workgroup accumulates whole footprints
 // into an LDS tile padded by w-1 cells on each side (no clipping), then writes
-// only its own cells -- every fine cell is written exactly once with plain
-// stores, no global atomics and no separate clear of the fine grid.
+// only its own cells -- every fine cell of a tile some record reaches is written
+// exactly once with plain stores, no global atomics and no separate clear of the
+// fine grid.  Where the plan asks for it, a tile no record reaches is not written at
+// all: the binning flags it 0 and the column pass reads its cells as zeros
+// (geometries whose frequencies cover part of the fine grid leave most tiles so).
 //
 // Kernel values.  psi at the w cells of a footprint is a polynomial in the
 // point's cell offset f (es_poly.h, FP64 Chebyshev interpolants, within 1e-7 of
@@ -441,6 +444,9 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd) spread_kernel(SpreadP
     // bounds |Re c| and |Im c| by it): every term is then the same integer whichever
     // slice adds it, and the slices' sums add up exactly to the whole tile's.
     const bool cut = nsl > 1;
+    // a tile no record reaches (flagged 0 by the binning) may be left unwritten: the
+    // column pass then reads its cells as zeros
+    if (p.skip_dead && nrec == 0) return;
     // a tile of few records needs no start histogram: no cell receives more than
     // nrec terms (unless the grid folds the padded tile onto itself: split sums)
     const bool few = nrec <= kFewRecords && !fold_x && !fold_y && !cut;
@@ -699,7 +705,9 @@ hipError_t launch_w(const SpreadParams &p, const Binned &b, const float2 *u1, fl
 // points reach (the tile plus w-1 cells right and below, periodic).  A point is
 // handled in the tile that holds its first footprint cell and skipped in the
 // other bins that list it, so each point is written once, with a plain store:
-// no atomics, and FP32 sums in registers.
+// no atomics, and FP32 sums in registers.  Only footprint cells enter the sums:
+// every one lies in a tile whose bin lists the point, so cells of tiles no record
+// reaches (which the column pass may leave unwritten) are copied but never used.
 constexpr int kInterpThreads = 256;
 
 template <int W>
@@ -713,6 +721,7 @@ __global__ void __launch_bounds__(kInterpThreads) interp_kernel(SpreadParams p, 
     int t;
     uint32_t slice, nsl, slot, s0, s1;
     if (!tile_work(b, p.ntx * p.nty, t, slice, nsl, slot, s0, s1)) return;
+    if (s0 == s1) return;   // no point to gather for: the region is not needed
     const int tsx = 1 << p.log_tile_x, tsy = 1 << p.log_tile_y;
     const int rx = tsx + W - 1, ry = tsy + W - 1;
     const int ty = t >> p.log_ntx, tx = t & ((1 << p.log_ntx) - 1);

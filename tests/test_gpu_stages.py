@@ -275,12 +275,25 @@ def _psi(z, wid, beta):
     return np.where(a >= 0.0, np.exp(beta * (np.sqrt(np.maximum(a, 0.0)) - 1.0)), 0.0)
 
 
-def _fine_natural(torch, plan, info):
+def _live_cells(torch, plan, info):
+    """[gy, gx] True in the tiles the binning flags as reached by some record."""
+    tx_n, ty_n = info["nfx"] // info["tile_x"], info["nfy"] // info["tile_y"]
+    live = _view(torch, plan, info["off_live"], tx_n * ty_n, torch.uint8).reshape(ty_n, tx_n)
+    return np.repeat(np.repeat(live != 0, info["tile_y"], axis=0), info["tile_x"], axis=1)
+
+
+def _fine_natural(torch, plan, info, after_forward=True):
+    """The fine grid as [gy, gx].  After a forward, tiles no record reaches may have
+    been left unwritten (holding whatever was there); they are taken as zeros, as the
+    column pass reads them."""
     nfx, nfy, C = info["nfx"], info["nfy"], info["col_batch"]
     raw = _view(torch, plan, info["off_fine"], 2 * nfx * nfy, torch.float32)
     v = (raw[0::2] + 1j * raw[1::2]).astype(np.complex128)
     # element (gx, gy) at ((gx / C) nfy + gy) C + gx % C -> [gy, gx]
-    return v.reshape(nfx // C, nfy, C).transpose(1, 0, 2).reshape(nfy, nfx)
+    fine = v.reshape(nfx // C, nfy, C).transpose(1, 0, 2).reshape(nfy, nfx)
+    if after_forward:
+        fine = np.where(_live_cells(torch, plan, info), fine, 0.0)
+    return fine
 
 
 @pytest.mark.parametrize("which", ["even", "crowded", "hot", "sparse", "bright", "many_hot"])
@@ -299,6 +312,7 @@ def test_spread_matches_host_sum(which):
     torch.cuda.synchronize()
     info = plan.info()
     fine = _fine_natural(torch, plan, info)
+    live = _live_cells(torch, plan, info)
     plan.close()
     nfx, nfy, wid, beta = info["nfx"], info["nfy"], info["w"], info["beta"]
     cx, cy, ox, oy, ph = _host_points(w, nfx, nfy, wid)
@@ -315,6 +329,8 @@ def test_spread_matches_host_sum(which):
     err = rel_l2(fine, want)
     print(f"spread {which}: rel-L2 {err:.2e}")
     assert err <= 2e-6
+    # the tiles flagged as reached by no record receive nothing
+    assert not want[~live].any()
     if which == "bright":
         # the weak field alone, away from the bright point's footprint: 42-bit terms
         # keep its rounding far below the 2^-21 of the bright point's amplitude
@@ -331,6 +347,75 @@ def _psi_hat(m, nf, wid, beta):
     xq, wq = np.polynomial.legendre.leggauss(200)
     es = np.exp(beta * (np.sqrt(1.0 - xq * xq) - 1.0))
     return 0.5 * wid * np.sum(wq * es * np.cos(np.pi * np.outer(m, xq) * wid / nf), axis=1)
+
+
+def test_unwritten_tiles_follow_the_geometry():
+    """A plan re-binned between a geometry whose frequencies cover the whole fine grid
+    and one that leaves nearly every tile empty.  Every binning flags the tiles some
+    record reaches; the empty-tile count read with the status picks the form of the
+    next transforms: every tile written (empty ones as zeros), or only the flagged
+    ones, the forward's column pass reading the rest as zeros -- while the fine grid
+    there still holds the previous geometry's sums.  Both forms give the same forward
+    and adjoint bit for bit, whichever geometry they meet, and equal a fresh plan's."""
+    torch = torch_gpu()
+    import dataclasses
+    import paper_1203_3583_amd as asf
+
+    sp = _sparse()
+    rng = np.random.default_rng(51)
+    x, y = rng.uniform(-6e-4, 6e-4, sp.n), rng.uniform(-6e-4, 6e-4, sp.n)
+    dense = dataclasses.replace(sp, name="dense", x=x, y=y, d=synth.sinusoidal_relief(x, y, 20e-6, 0.8e-3))
+    geo_s, geo_d = to_dev(torch, sp)[:3], to_dev(torch, dense)[:3]
+    u = to_dev(torch, sp)[3]
+    g2 = torch.from_numpy(synth.random_field(rng, sp.mx, sp.my)).cuda()
+
+    def fresh(geo):
+        plan = asf.Plan(*geo, sp.lam, sp.z0, sp.p2x, sp.p2y, sp.mx, sp.my)
+        out = plan.forward(u).cpu().numpy(), plan.adjoint(g2).cpu().numpy()
+        plan.close()
+        return out
+
+    want_s, want_d = fresh(geo_s), fresh(geo_d)
+    plan = asf.Plan(*geo_s, sp.lam, sp.z0, sp.p2x, sp.p2y, sp.mx, sp.my)
+    info = plan.info()
+
+    def step():
+        out = plan.forward(u).cpu().numpy()
+        live = _live_cells(torch, plan, info)
+        fine = _fine_natural(torch, plan, info, after_forward=False)
+        # the flags name exactly the tiles some record reaches
+        _, ranges = _device_bins(torch, plan, plan.info())   # the binning's copy of the counters
+        tx_n, ty_n = info["nfx"] // info["tile_x"], info["nfy"] // info["tile_y"]
+        reached = np.array([b > a for a, b in ranges]).reshape(ty_n, tx_n)
+        flags = _view(torch, plan, info["off_live"], tx_n * ty_n, torch.uint8).reshape(ty_n, tx_n)
+        assert np.array_equal(flags, reached.astype(np.uint8))
+        adj = plan.adjoint(g2).cpu().numpy()
+        return out, adj, live, fine
+
+    def same(got, want):
+        return np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+
+    out, adj, live, fine = step()   # sparse geometry, flagged form (from the plan's own status read)
+    print(f"sparse: {int((~live).sum())} of {live.size} cells in empty tiles")
+    assert (~live).sum() * 4 >= live.size and same((out, adj), want_s)
+    plan.setpts(*geo_d)             # dense geometry, still the flagged form
+    out, adj, live, fine = step()
+    assert same((out, adj), want_d)
+    plan.status()                   # dense: every tile written
+    out, adj, live, fine = step()
+    assert (~live).sum() * 4 < live.size and same((out, adj), want_d)
+    plan.setpts(*geo_s)             # sparse geometry, every tile written: zeros in the empty ones
+    out, adj, live, fine = step()
+    assert same((out, adj), want_s)
+    plan.setpts(*geo_d)
+    plan.status()
+    plan.forward(u)                 # the whole fine grid holds the dense sums
+    plan.setpts(*geo_s)
+    plan.status()                   # sparse again: the empty tiles keep those sums
+    out, adj, live, fine = step()
+    plan.close()
+    assert np.abs(fine[~live]).max() > 0     # stale sums really are there
+    assert same((out, adj), want_s)
 
 
 @pytest.mark.parametrize("fft,bar", [("fp32", 2e-6), ("split_fp16", 1e-4)])
@@ -367,13 +452,16 @@ def test_fft_passes_match_numpy(fft, bar):
     assert e1 <= bar and e2 <= bar
 
 
+@pytest.mark.parametrize("which", ["even", "crowded"])
 @pytest.mark.parametrize("fft,bar", [("fp32", 2e-6), ("split_fp16", 1e-4)])
-def test_adjoint_stages_match_host(fft, bar):
+def test_adjoint_stages_match_host(fft, bar, which):
     """The adjoint's three stages, each from the device's own input to it: the row pass
     (g2 times conj(Dx Dy), zero-padded, exp(+i) DFT), the column pass (exp(+i) DFT of the
-    kept rows) and the interpolation (conj(exp(i phi)) times the footprint sum)."""
+    kept rows) and the interpolation (conj(exp(i phi)) times the footprint sum).  The
+    column pass is checked in the tiles some record reaches: in the crowded relief most
+    tiles are empty and left unwritten, and no footprint reaches them."""
     torch = torch_gpu()
-    w = _even()
+    w = {"even": _even, "crowded": _crowded}[which]()
     plan, u = _plan(torch, w, fft)
     info = plan.info()
     nfx, nfy, mx, my, C = info["nfx"], info["nfy"], w.mx, w.my, info["col_batch"]
@@ -384,7 +472,8 @@ def test_adjoint_stages_match_host(fft, bar):
     torch.cuda.synchronize()
     raw = _view(torch, plan, info["off_mid"], 2 * my * nfx, torch.float32)
     mid = (raw[0::2] + 1j * raw[1::2]).astype(np.complex128).reshape(my, nfx)   # row-major
-    fine = _fine_natural(torch, plan, info)
+    fine = _fine_natural(torch, plan, info, after_forward=False)
+    live = _live_cells(torch, plan, info)
     plan.close()
     k = 2.0 * np.pi / w.lam
     m = np.arange(mx) - mx // 2
@@ -401,7 +490,9 @@ def test_adjoint_stages_match_host(fft, bar):
     padc = np.zeros((nfy, nfx), dtype=np.complex128)
     padc[n % nfy, :] = mid
     want_fine = np.fft.ifft(padc, axis=0) * nfy
-    e2 = rel_l2(fine, want_fine)
+    e2 = rel_l2(fine[live], want_fine[live])
+    if which == "even":
+        assert live.all()
     # interpolation from the device's fine grid, exact kernel values
     cx, cy, ox, oy, ph = _host_points(w, nfx, nfy, wid)
     a = np.arange(wid)
