@@ -61,10 +61,20 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_spread_bytes(n_points, nfx, nfy):
+def algorithmic_spread_bytes(n_points, cells_written):
     """Per launch: 28 B per source point (u1 8 B and a 20 B record: point index 4,
     fine cell and offsets 8, pre-phase 8) plus 8 B per fine-grid cell written."""
-    return 28 * n_points + 8 * nfx * nfy
+    return 28 * n_points + 8 * cells_written
+
+
+def cells_written(torch, plan):
+    """Fine-grid cells the spreading writes: all of them, or, while the plan leaves the
+    tiles no record reaches unwritten, the cells of the tiles the binning flags."""
+    info = plan.info()
+    if not info["skip_empty"]:
+        return info["nfx"] * info["nfy"]
+    flags = plan.workspace_view(info["off_live"], info["ntiles"], torch.uint8)
+    return int(flags.sum().item()) * info["tile_x"] * info["tile_y"]
 
 
 def _summary_fields(path):
@@ -332,6 +342,7 @@ def main():
         sec, _ = time_steps(torch, plan, x, y, d, u, out, args.steps, args.warmup, False)
         med = median_step_ms(torch, plan, x, y, d, u, out, args.steps)
         _, stages = time_steps(torch, plan, x, y, d, u, out, args.steps, 0, True)
+        cells = cells_written(torch, plan)
         plan.forward(u, out=out)
         torch.cuda.synchronize()
         u2 = out.cpu().numpy().astype(np.complex128)
@@ -339,7 +350,7 @@ def main():
         fwd_sec, fwd_stages = time_calls(torch, plan, lambda: plan.forward(u, out=out), args.steps, 2)
         g1 = torch.empty(w.n, dtype=torch.complex64, device=dev)
         adj_sec, adj_stages = time_calls(torch, plan, lambda: plan.adjoint(out, out=g1), args.steps, 2)
-        results[fft] = {"sec": sec, "median_ms": med, "stages": stages, "info": info, "u2": u2,
+        results[fft] = {"sec": sec, "median_ms": med, "stages": stages, "info": info, "u2": u2, "cells": cells,
                         "fwd_sec": fwd_sec, "fwd_stages": fwd_stages,
                         "adj_sec": adj_sec, "adj_stages": adj_stages}
         plan.close()
@@ -361,7 +372,7 @@ def main():
     n = w.n
     info = r["info"]
     spread_ms = r["stages"].get("spread")
-    alg = algorithmic_spread_bytes(n, info["nfx"], info["nfy"])
+    alg = algorithmic_spread_bytes(n, r["cells"])
     achieved = alg / (spread_ms * 1e-3) / 1e9 if spread_ms else None
     line = {
         "metric": "NU points/s, 2D forward at rel-L2<=1e-5 vs FP64 oracle",
@@ -407,7 +418,8 @@ def main():
             # counter traffic was taken on the cap's spread only
             "traffic": stored_traffic() if args.workload == "cap_2048" else None,
             "algorithmic_bytes": alg,
-            "bytes_model": "28 B per point (u1 8 + record 20) + 8 B per fine cell",
+            "bytes_model": "28 B per point (u1 8 + record 20) + 8 B per fine cell written",
+            "fine_cells_written": r["cells"],
             "avg_launch_ms": spread_ms,
         },
         # busy fraction of the FFT passes' compute unit (vector ALU for FP32, matrix

@@ -113,10 +113,15 @@ typedef struct {
     size_t off_split, off_split_meta, off_slot_owner;
     uint32_t split_slots;
     /* per-tile flags of the last binning (u8 [ntiles], in tile order ty * ntx + tx): 1
-       where some record reaches the tile, 0 where none does.  When many tiles are
-       empty the transforms leave those tiles' fine-grid cells as they were (the
-       forward's column pass reads them as zeros) */
+       where some record reaches the tile, 0 where none does; then u8 [ntx], 1 for the
+       tile columns holding such a tile.  When many tiles are empty the transforms
+       leave those tiles' fine-grid cells as they were (the forward's column pass reads
+       them as zeros), and the fine-grid columns of the tile columns flagged 0, being
+       zeros, are neither transformed nor stored in the column-pass output */
     size_t off_live;
+    /* 1 while the plan's transforms leave those tiles unwritten (a quarter or more of
+       the tiles were empty at the last status read), else 0 */
+    uint32_t skip_empty;
 } asf_info;
 
 /*

@@ -57,7 +57,8 @@ class Info(ctypes.Structure):
                 ("ws_bytes", ctypes.c_size_t), ("off_cursor", ctypes.c_size_t),
                 ("off_slab", ctypes.c_size_t), ("off_split", ctypes.c_size_t),
                 ("off_split_meta", ctypes.c_size_t), ("off_slot_owner", ctypes.c_size_t),
-                ("split_slots", ctypes.c_uint32), ("off_live", ctypes.c_size_t)]
+                ("split_slots", ctypes.c_uint32), ("off_live", ctypes.c_size_t),
+                ("skip_empty", ctypes.c_uint32)]
 
 
 class LineParams(ctypes.Structure):

@@ -119,7 +119,7 @@ int geometry_launches(asf_plan_s *p, const double *x, const double *y, const dou
     // compact layout: both kernels return at once when the slabs held
     {
         StageMark m(p, asf::STAGE_SCAN, s);
-        e = asf::launch_bin_scan(p->bin, p->lay.ntiles, p->slots, s);
+        e = asf::launch_bin_scan(p->bin, p->lay.ntiles, p->lay.ntx, p->slots, s);
         if (e != hipSuccess) return hip_fail(e, "bin_scan launch");
     }
     {
@@ -262,6 +262,7 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
     pl->bin.split_meta = reinterpret_cast<uint32_t *>(w + L.off_split_meta);
     pl->bin.slot_owner = reinterpret_cast<uint32_t *>(w + L.off_slot_owner);
     pl->bin.live = reinterpret_cast<uint8_t *>(w + L.off_live);
+    pl->bin.live_col = pl->bin.live + L.ntiles;
     pl->bin.combine = reinterpret_cast<uint32_t *>(w + L.off_combine);
     pl->bin.partial = reinterpret_cast<unsigned long long *>(w + L.off_partial);
     pl->fine = reinterpret_cast<float2 *>(w + L.off_fine);
@@ -356,7 +357,7 @@ namespace {
 // The binning's per-tile flags for the column passes, when the plan leaves the tiles
 // no record reaches unwritten.
 asf::LiveTiles live_tiles(const asf_plan_s *p) {
-    return asf::LiveTiles{p->sp.skip_dead ? p->bin.live : nullptr, p->lay.ntx, p->lay.nty,
+    return asf::LiveTiles{p->sp.skip_dead ? p->bin.live : nullptr, p->bin.live_col, p->lay.ntx, p->lay.nty,
                           log2i(p->lay.tile_x), log2i(p->lay.tile_y)};
 }
 
@@ -382,7 +383,8 @@ int forward_into(asf_plan_t plan, const void *u1, void *u2, void *stream, int ac
     {
         StageMark m(p, asf::STAGE_FFT2, s);
         e = asf::launch_fft_pass2(p->sh2, log2i(p->sh1.batch), split, mid, static_cast<float2 *>(u2),
-                                  p->twx, p->w16, p->dx, p->dy, p->lay.mx, p->lay.my, accumulate, s);
+                                  p->twx, p->w16, p->dx, p->dy, p->lay.mx, p->lay.my, accumulate,
+                                  live_tiles(p), s);
         if (e != hipSuccess) return hip_fail(e, "fft pass 2 launch");
     }
     return ASF_OK;
@@ -429,7 +431,7 @@ int asf_adjoint(asf_plan_t plan, const void *g2, void *g1, void *stream) {
     {
         StageMark m(p, asf::STAGE_ADJ_FFT2, s);
         e = asf::launch_fft_adj_rows(p->lay.nfx, split, static_cast<const float2 *>(g2), p->mid, p->twx,
-                                     p->w16, p->dx, p->dy, p->lay.mx, p->lay.my, s);
+                                     p->w16, p->dx, p->dy, p->lay.mx, p->lay.my, live_tiles(p), s);
         if (e != hipSuccess) return hip_fail(e, "adjoint row pass launch");
     }
     {
@@ -479,6 +481,7 @@ int asf_plan_info(asf_plan_t plan, asf_info *info) {
     info->off_slot_owner = L.off_slot_owner;
     info->split_slots = plan->slots;
     info->off_live = L.off_live;
+    info->skip_empty = plan->sparse ? 1u : 0u;
     return ASF_OK;
 }
 

@@ -43,6 +43,7 @@ struct Binned {
     // unwritten by the spreading and the adjoint's column pass: the forward's column
     // pass then reads them as zeros, and no interpolation footprint reaches them.
     uint8_t *live;         // [ntiles]
+    uint8_t *live_col;     // [ntx] per tile column: 1 if some tile of it is flagged 1
     uint32_t *slot_owner;  // [kSplitSlots]
     uint32_t *combine;     // [kSplitSlots] slices finished per split tile (zero between launches)
     unsigned long long *partial;   // [kSplitSlots][2][tile cells] integer sums of the slices (Re, Im),
@@ -137,11 +138,18 @@ struct SpreadParams {
     int skip_dead;     // 1: tiles no record reaches are left unwritten
 };
 
-// The binning's per-tile flags (Binned::live) as the column passes take them.
-// Forward: tiles flagged 0 were not written and are read as zeros; adjoint: their
-// cells are not needed.  flag NULL: every tile is written and read.
+// Tile rows and columns of the largest fine grid (16384 cells a side, 64 x 32 tiles).
+constexpr int kMaxTileRows = 512;
+constexpr int kMaxTileCols = 256;
+
+// The binning's per-tile flags (Binned::live, live_col) as the FFT passes take them.
+// Forward: tiles flagged 0 were not written and are read as zeros, and the columns
+// of a tile column with no flagged tile are neither transformed by the column pass
+// nor read by the row pass (they are zeros); adjoint: the cells and columns are not
+// needed.  flag NULL: every tile is written and read.
 struct LiveTiles {
     const uint8_t *flag;   // [ty][tx]
+    const uint8_t *col;    // [tx]
     int ntx, nty, log_tile_x, log_tile_y;
 };
 
@@ -199,7 +207,7 @@ hipError_t launch_bin_count(const GeoParams &g, const Binned &b, int64_t n, cons
 hipError_t launch_bin_fill(const GeoParams &g, const Binned &b, int64_t n, const double *x,
                            const double *y, const double *d, bool crowded, hipStream_t s);
 // (and the slices of crowded tiles: slots = workgroups resident at once, 0 = never cut)
-hipError_t launch_bin_scan(const Binned &b, int ntiles, uint32_t slots, hipStream_t s);
+hipError_t launch_bin_scan(const Binned &b, int ntiles, int ntx, uint32_t slots, hipStream_t s);
 // (and, in every launch, clears next_status and next_cursor)
 hipError_t launch_bin_scatter(const GeoParams &g, const Binned &b, int64_t n, int ntiles, const double *x,
                               const double *y, const double *d, hipStream_t s);
@@ -213,11 +221,12 @@ hipError_t launch_fft_pass1(const FftShape &sh, int split16, const float2 *fine,
 // deconvolution and destination phase
 hipError_t launch_fft_pass2(const FftShape &sh, int log_panel, int split16, const float2 *mid,
                             float2 *u2, const float2 *tw, const float2 *w16, const float2 *dx,
-                            const float2 *dy, int mx, int my, int accumulate, hipStream_t s);
+                            const float2 *dy, int mx, int my, int accumulate, const LiveTiles &lt,
+                            hipStream_t s);
 // adjoint: rows of g2 (pre-corrected, zero-padded) -> mid (my x nfx, row-major)
 hipError_t launch_fft_adj_rows(int len, int split16, const float2 *g2, float2 *mid, const float2 *tw,
                                const float2 *w16, const float2 *dx, const float2 *dy, int mx, int my,
-                               hipStream_t s);
+                               const LiveTiles &lt, hipStream_t s);
 // adjoint: columns of mid (zero-padded) -> fine grid (panel layout)
 hipError_t launch_fft_adj_cols(int len, int split16, const float2 *mid, float2 *fine,
                                const float2 *tw, const float2 *w16, int nfx, int my, const LiveTiles &lt,

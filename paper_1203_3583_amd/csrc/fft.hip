@@ -390,9 +390,6 @@ __device__ __forceinline__ int range_exponent(float max_abs) {
     return e;
 }
 
-// Tile rows of the fine grid: at most 16384 / 32.
-constexpr int kMaxTileRows = 512;
-
 // With flags (tiles no record reaches, left unwritten): the flags of the tile column
 // holding fine-grid column x0, one byte per tile row, into LDS.  Returns whether
 // flags are in use.
@@ -404,18 +401,20 @@ __device__ __forceinline__ bool live_rows(const LiveTiles &lt, int x0, uint8_t *
     return true;
 }
 
-// With flags: whether any tile of that tile column was written (the same answer in
-// every thread).  A panel with none transforms to zeros.
-__device__ __forceinline__ bool any_live(const LiveTiles &lt, const uint8_t *lrow) {
-    int any = 0;
-    for (int i = threadIdx.x; i < lt.nty; i += blockDim.x) any |= lrow[i];
-    return __syncthreads_or(any) != 0;
+// With flags: whether the tile column holding fine-grid column x0 has a flagged tile
+// (the same answer in every thread).  The columns of one with none are zeros: the
+// column passes skip them, and the row passes neither read nor write them in mid.
+__device__ __forceinline__ bool column_needed(const LiveTiles &lt, int x0) {
+    return !lt.flag || lt.col[x0 >> lt.log_tile_x] != 0;
 }
 
-// A panel's block of mid (count float2, count even, 16-byte aligned) set to zeros.
-__device__ __forceinline__ void zero_block(float2 *dst, int count) {
-    float4 *d = reinterpret_cast<float4 *>(dst);
-    for (int i = threadIdx.x; i < count / 2; i += blockDim.x) d[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+// With flags: the tile columns' flags, one byte per tile column, into LDS.  Returns
+// whether flags are in use.
+__device__ __forceinline__ bool live_cols(const LiveTiles &lt, uint8_t *lcol) {
+    if (!lt.flag) return false;
+    for (int i = threadIdx.x; i < lt.ntx; i += blockDim.x) lcol[i] = lt.col[i];
+    __syncthreads();
+    return true;
 }
 
 // Pass 1: a workgroup transforms one panel of BATCH adjacent fine-grid columns.
@@ -431,11 +430,8 @@ __global__ void __launch_bounds__(NT) fft_pass1_kernel(const float2 *__restrict_
     __shared__ uint8_t lrow[kMaxTileRows];
     const int pc = blockIdx.x;
     const float2 *src = fine + (size_t)pc * S::L * BATCH;
+    if (!column_needed(lt, pc * BATCH)) return;
     const bool sparse = live_rows(lt, pc * BATCH, lrow);
-    if (sparse && !any_live(lt, lrow)) {
-        zero_block(mid + (size_t)pc * my * BATCH, my * BATCH);
-        return;
-    }
     float big = 0.f;
     // every load in flight before the first LDS write (none for tiles left unwritten)
     constexpr int PER = S::L * BATCH / NT;
@@ -481,10 +477,11 @@ __global__ void __launch_bounds__(NT) fft_pass2_kernel(const float2 *__restrict_
                                                        const float2 *__restrict__ dx,
                                                        const float2 *__restrict__ dy, int mx,
                                                        int my, int log_panel, int xcd_group,
-                                                       int accumulate) {
+                                                       int accumulate, LiveTiles lt) {
     using S = Len<LOGL>;
     extern __shared__ float2 lds[];
     __shared__ float scratch[NT / 64];
+    __shared__ uint8_t lcol[kMaxTileCols];
     // workgroups are dealt to the 8 XCDs round-robin: give the xcd_group
     // workgroups whose rows share lines of mid consecutive slots on one XCD
     int g = blockIdx.x;
@@ -494,16 +491,20 @@ __global__ void __launch_bounds__(NT) fft_pass2_kernel(const float2 *__restrict_
     }
     const int row0 = g * BATCH;
     const int cmask = (1 << log_panel) - 1;
+    const bool sparse = live_cols(lt, lcol);
     float big = 0.f;
     // every load in flight before the first LDS write (a row is gathered from
-    // the panels, one line per element: serial round trips would dominate)
+    // the panels, one line per element: serial round trips would dominate);
+    // columns the column pass skipped are zeros, not loaded
     constexpr int PER = S::L * BATCH / NT;
     float2 v[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int t = threadIdx.x + k * NT;
         const int c = t >> LOGL, lx = t & (S::L - 1);
-        v[k] = mid[((((size_t)(lx >> log_panel)) * my + row0 + c) << log_panel) + (lx & cmask)];
+        v[k] = (!sparse || lcol[lx >> lt.log_tile_x])
+                   ? mid[((((size_t)(lx >> log_panel)) * my + row0 + c) << log_panel) + (lx & cmask)]
+                   : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -564,11 +565,14 @@ __global__ void __launch_bounds__(NT) fft_adj_rows_kernel(const float2 *__restri
                                                           const float2 *__restrict__ tw,
                                                           const float2 *__restrict__ w16,
                                                           const float2 *__restrict__ dx,
-                                                          const float2 *__restrict__ dy, int mx) {
+                                                          const float2 *__restrict__ dy, int mx,
+                                                          LiveTiles lt) {
     using S = Len<LOGL>;
     extern __shared__ float2 lds[];
     __shared__ float scratch[NT / 64];
+    __shared__ uint8_t lcol[kMaxTileCols];
     const int row0 = blockIdx.x * BATCH;
+    const bool sparse = live_cols(lt, lcol);
     const int half = mx >> 1;
     float big = 0.f;
     // every load in flight before the first LDS write
@@ -606,6 +610,7 @@ __global__ void __launch_bounds__(NT) fft_adj_rows_kernel(const float2 *__restri
     float2 *dst = mid + (size_t)row0 * S::L;
     for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
         const int c = t >> LOGL, l = t & (S::L - 1);
+        if (sparse && !lcol[l >> lt.log_tile_x]) continue;   // a column the column pass skips
         const float2 v = lds[c * S::STRIDE + lds_pos<S::PS>(l)];
         dst[t] = make_float2(v.x * unscale, -v.y * unscale);
     }
@@ -635,8 +640,8 @@ __global__ void __launch_bounds__(NT) fft_adj_cols_kernel(const float2 *__restri
     }
     // with flags: a panel no record reaches is not needed at all, and in the others
     // only the cells of tiles some record reaches are stored
+    if (!column_needed(lt, pc * BATCH)) return;
     const bool sparse = live_rows(lt, pc * BATCH, lrow);
-    if (sparse && !any_live(lt, lrow)) return;
     const int half = my >> 1;
     float big = 0.f;
     // every load in flight before the first LDS write
@@ -849,11 +854,8 @@ __global__ void __launch_bounds__(NT) fft_pass1_direct_kernel(const float2 *__re
     const float2 *src = fine + (size_t)pc * S::L * BATCH;
     float2 *dst = mid + (size_t)pc * my * BATCH;   // this panel's block of mid
     const int half = my >> 1;
+    if (!column_needed(lt, pc * BATCH)) return;
     const bool sparse = live_rows(lt, pc * BATCH, lrow);
-    if (sparse && !any_live(lt, lrow)) {
-        zero_block(dst, my * BATCH);
-        return;
-    }
     transform_direct<LOGL, BATCH, NT, SPLIT>(
         lds, tw, w16, scratch,
         [&](int c, int e) {
@@ -874,10 +876,12 @@ __global__ void __launch_bounds__(NT) fft_pass2_direct_kernel(const float2 *__re
                                                               const float2 *__restrict__ w16,
                                                               const float2 *__restrict__ dx,
                                                               const float2 *__restrict__ dy, int my,
-                                                              int log_panel, int xcd_group, int accumulate) {
+                                                              int log_panel, int xcd_group, int accumulate,
+                                                              LiveTiles lt) {
     using S = Len<LOGL>;
     extern __shared__ float2 lds[];
     __shared__ float scratch[NT / 64];
+    __shared__ uint8_t lcol[kMaxTileCols];
     int g = blockIdx.x;
     if (xcd_group > 1) {
         const int xcd = g & 7, slot = g >> 3;
@@ -886,10 +890,13 @@ __global__ void __launch_bounds__(NT) fft_pass2_direct_kernel(const float2 *__re
     const int row0 = g * BATCH;
     const int cmask = (1 << log_panel) - 1;
     constexpr int MX = S::L / 2, HALF = MX / 2;
+    const bool sparse = live_cols(lt, lcol);
     transform_direct<LOGL, BATCH, NT, SPLIT>(
         lds, tw, w16, scratch,
         [&](int c, int e) {
-            return mid[((((size_t)(e >> log_panel)) * my + row0 + c) << log_panel) + (e & cmask)];
+            return (!sparse || lcol[e >> lt.log_tile_x])
+                       ? mid[((((size_t)(e >> log_panel)) * my + row0 + c) << log_panel) + (e & cmask)]
+                       : make_float2(0.f, 0.f);
         },
         [&](int c, int l, float2 val) {
             const int ix = (l + HALF) & (S::L - 1);
@@ -946,7 +953,7 @@ hipError_t launch1(const FftShape &sh, const float2 *fine, float2 *mid, const fl
 template <int LOGL, int BATCH, bool SPLIT>
 hipError_t launch2(const FftShape &sh, const float2 *mid, float2 *u2, const float2 *tw,
                    const float2 *w16, const float2 *dx, const float2 *dy, int mx, int my,
-                   int log_panel, int accumulate, hipStream_t s) {
+                   int log_panel, int accumulate, const LiveTiles &lt, hipStream_t s) {
     constexpr int NT = threads_for<LOGL, BATCH>();
     const size_t lds = (size_t)BATCH * Len<LOGL>::STRIDE * sizeof(float2);
     static thread_local size_t enabled = 0;
@@ -961,27 +968,28 @@ hipError_t launch2(const FftShape &sh, const float2 *mid, float2 *u2, const floa
         if (e != hipSuccess) return e;
         if (mx != Len<LOGL>::L / 2) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k, dim3(groups), dim3(NT), lds, s, mid, u2, tw, w16, dx, dy, my, log_panel,
-                           xcd_group, accumulate);
+                           xcd_group, accumulate, lt);
     } else {
         auto k = fft_pass2_kernel<LOGL, BATCH, NT, SPLIT>;
         hipError_t e = allow_lds((const void *)k, lds, enabled);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k, dim3(groups), dim3(NT), lds, s, mid, u2, tw, w16, dx, dy, mx, my, log_panel,
-                           xcd_group, accumulate);
+                           xcd_group, accumulate, lt);
     }
     return hipGetLastError();
 }
 
 template <int LOGL, int BATCH, bool SPLIT>
 hipError_t launch_adj2(const float2 *g2, float2 *mid, const float2 *tw, const float2 *w16,
-                       const float2 *dx, const float2 *dy, int mx, int my, hipStream_t s) {
+                       const float2 *dx, const float2 *dy, int mx, int my, const LiveTiles &lt,
+                       hipStream_t s) {
     constexpr int NT = threads_for<LOGL, BATCH>();
     const size_t lds = (size_t)BATCH * Len<LOGL>::STRIDE * sizeof(float2);
     static thread_local size_t enabled = 0;
     auto k = fft_adj_rows_kernel<LOGL, BATCH, NT, SPLIT>;
     hipError_t e = allow_lds((const void *)k, lds, enabled);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(my / BATCH), dim3(NT), lds, s, g2, mid, tw, w16, dx, dy, mx);
+    hipLaunchKernelGGL(k, dim3(my / BATCH), dim3(NT), lds, s, g2, mid, tw, w16, dx, dy, mx, lt);
     return hipGetLastError();
 }
 
@@ -1003,18 +1011,18 @@ hipError_t launch_adj1(const float2 *mid, float2 *fine, const float2 *tw, const 
 
 template <bool SPLIT>
 hipError_t dispatch_adj2(int len, const float2 *g2, float2 *mid, const float2 *tw, const float2 *w16,
-                         const float2 *dx, const float2 *dy, int mx, int my, hipStream_t s) {
+                         const float2 *dx, const float2 *dy, int mx, int my, const LiveTiles &lt, hipStream_t s) {
     switch (__builtin_ctz(len)) {
-        case 5: return launch_adj2<5, 8, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
-        case 6: return launch_adj2<6, 4, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
-        case 7: return launch_adj2<7, 2, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
-        case 8: return launch_adj2<8, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
-        case 9: return launch_adj2<9, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
-        case 10: return launch_adj2<10, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
-        case 11: return launch_adj2<11, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
-        case 12: return launch_adj2<12, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
-        case 13: return launch_adj2<13, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
-        case 14: return launch_adj2<14, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, s);
+        case 5: return launch_adj2<5, 8, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, lt, s);
+        case 6: return launch_adj2<6, 4, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, lt, s);
+        case 7: return launch_adj2<7, 2, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, lt, s);
+        case 8: return launch_adj2<8, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, lt, s);
+        case 9: return launch_adj2<9, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, lt, s);
+        case 10: return launch_adj2<10, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, lt, s);
+        case 11: return launch_adj2<11, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, lt, s);
+        case 12: return launch_adj2<12, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, lt, s);
+        case 13: return launch_adj2<13, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, lt, s);
+        case 14: return launch_adj2<14, 1, SPLIT>(g2, mid, tw, w16, dx, dy, mx, my, lt, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1065,19 +1073,19 @@ hipError_t dispatch1(const FftShape &sh, const float2 *fine, float2 *mid, const 
 template <bool SPLIT>
 hipError_t dispatch2(const FftShape &sh, int log_panel, const float2 *mid, float2 *u2, const float2 *tw,
                      const float2 *w16, const float2 *dx, const float2 *dy, int mx, int my,
-                     int accumulate, hipStream_t s) {
+                     int accumulate, const LiveTiles &lt, hipStream_t s) {
     const int log = __builtin_ctz(sh.L);
     switch (log) {
-        case 5: return launch2<5, 8, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
-        case 6: return launch2<6, 4, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
-        case 7: return launch2<7, 2, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
-        case 8: return launch2<8, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
-        case 9: return launch2<9, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
-        case 10: return launch2<10, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
-        case 11: return launch2<11, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
-        case 12: return launch2<12, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
-        case 13: return launch2<13, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
-        case 14: return launch2<14, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, s);
+        case 5: return launch2<5, 8, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, lt, s);
+        case 6: return launch2<6, 4, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, lt, s);
+        case 7: return launch2<7, 2, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, lt, s);
+        case 8: return launch2<8, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, lt, s);
+        case 9: return launch2<9, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, lt, s);
+        case 10: return launch2<10, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, lt, s);
+        case 11: return launch2<11, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, lt, s);
+        case 12: return launch2<12, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, lt, s);
+        case 13: return launch2<13, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, lt, s);
+        case 14: return launch2<14, 1, SPLIT>(sh, mid, u2, tw, w16, dx, dy, mx, my, log_panel, accumulate, lt, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1118,16 +1126,19 @@ hipError_t launch_fft_pass1(const FftShape &sh, int split16, const float2 *fine,
 
 hipError_t launch_fft_pass2(const FftShape &sh, int log_panel, int split16, const float2 *mid,
                             float2 *u2, const float2 *tw, const float2 *w16, const float2 *dx,
-                            const float2 *dy, int mx, int my, int accumulate, hipStream_t s) {
-    if (split16) return dispatch2<true>(sh, log_panel, mid, u2, tw, w16, dx, dy, mx, my, accumulate, s);
-    return dispatch2<false>(sh, log_panel, mid, u2, tw, w16, dx, dy, mx, my, accumulate, s);
+                            const float2 *dy, int mx, int my, int accumulate, const LiveTiles &lt,
+                            hipStream_t s) {
+    if (lt.flag && (lt.ntx > kMaxTileCols || lt.ntx <= 0)) return hipErrorInvalidValue;
+    if (split16) return dispatch2<true>(sh, log_panel, mid, u2, tw, w16, dx, dy, mx, my, accumulate, lt, s);
+    return dispatch2<false>(sh, log_panel, mid, u2, tw, w16, dx, dy, mx, my, accumulate, lt, s);
 }
 
 hipError_t launch_fft_adj_rows(int len, int split16, const float2 *g2, float2 *mid, const float2 *tw,
                                const float2 *w16, const float2 *dx, const float2 *dy, int mx, int my,
-                               hipStream_t s) {
-    if (split16) return dispatch_adj2<true>(len, g2, mid, tw, w16, dx, dy, mx, my, s);
-    return dispatch_adj2<false>(len, g2, mid, tw, w16, dx, dy, mx, my, s);
+                               const LiveTiles &lt, hipStream_t s) {
+    if (lt.flag && (lt.ntx > kMaxTileCols || lt.ntx <= 0)) return hipErrorInvalidValue;
+    if (split16) return dispatch_adj2<true>(len, g2, mid, tw, w16, dx, dy, mx, my, lt, s);
+    return dispatch_adj2<false>(len, g2, mid, tw, w16, dx, dy, mx, my, lt, s);
 }
 
 hipError_t launch_fft_adj_cols(int len, int split16, const float2 *mid, float2 *fine,

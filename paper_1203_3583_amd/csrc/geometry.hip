@@ -378,8 +378,8 @@ __device__ inline uint64_t block_scan(const Binned &b, int ntiles, uint64_t *wsu
 // take partial-tile slots in tile order; if they would need more than kSplitSlots,
 // len doubles until they do not.
 template <class C>
-__device__ inline void split_plan(const Binned &b, int ntiles, uint32_t slots, uint64_t *wsum,
-                                  uint32_t *wmax, uint32_t *wempty, C count) {
+__device__ inline void split_plan(const Binned &b, int ntiles, int ntx, uint32_t slots, uint64_t *wsum,
+                                  uint32_t *wmax, uint32_t *wempty, uint8_t *lcol, C count) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     if (slots == 0) {   // grids whose tiles are never cut (nor left unwritten: no flags)
         if (t == 0) {
@@ -389,9 +389,25 @@ __device__ inline void split_plan(const Binned &b, int ntiles, uint32_t slots, u
         }
         return;
     }
+    // per tile column: whether some tile of it holds a record (plain stores of 1)
+    for (int i = t; i < ntx; i += kScanThreads) lcol[i] = 0;
+    __syncthreads();
     uint64_t r = 0;
     uint32_t most = 0, empty = 0;
     const bool compact = (b.status[0] & kStatusCompact) != 0u;
+    // each tile's flag (some record reaches it) is stored one round late, after the
+    // next round's loads are issued, so that waiting for those loads does not also
+    // wait for these stores
+    uint32_t flags = 0;
+    int flag_base = -1;
+    auto store_flags = [&]() {
+        if (flag_base < 0) return;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            const int i = flag_base + k * kScanThreads + t;
+            if (i < ntiles) b.live[i] = (uint8_t)((flags >> k) & 1u);
+        }
+    };
     for (int base = 0; base < ntiles; base += kScanThreads * kScanPer) {
         // kScanPer tiles' counts and slab sizes in flight (indices clamped so that
         // no load waits on a branch)
@@ -402,6 +418,9 @@ __device__ inline void split_plan(const Binned &b, int ntiles, uint32_t slots, u
             cur[k] = b.cursor[i];
             cap[k] = b.slab[i].y;
         }
+        store_flags();
+        flags = 0;
+        flag_base = base;
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
             const bool in = base + k * kScanThreads + t < ntiles;
@@ -409,9 +428,11 @@ __device__ inline void split_plan(const Binned &b, int ntiles, uint32_t slots, u
             r += c;
             most = max(most, c);
             empty += (in && c == 0u) ? 1u : 0u;
-            if (in) b.live[base + k * kScanThreads + t] = c != 0u ? 1 : 0;
+            flags |= (c != 0u ? 1u : 0u) << k;
+            if (c != 0u) lcol[(base + k * kScanThreads + t) & (ntx - 1)] = 1;
         }
     }
+    store_flags();
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         r += __shfl_xor(r, off);
@@ -436,6 +457,7 @@ __device__ inline void split_plan(const Binned &b, int ntiles, uint32_t slots, u
     // leave unwritten (read by the host with the status, to choose that form for the
     // plan's next transforms)
     if (t == 0) b.split_meta[2] = empty;
+    for (int i = t; i < ntx; i += kScanThreads) b.live_col[i] = lcol[i];
     __syncthreads();   // wsum is reused by the scans
     const uint64_t load = (r + slots - 1) / slots;
     const uint64_t thr64 = max((uint64_t)kSplitMinRecords, 2 * load);
@@ -475,13 +497,14 @@ __device__ inline void split_plan(const Binned &b, int ntiles, uint32_t slots, u
     }
 }
 
-__global__ void __launch_bounds__(kScanThreads) bin_scan_kernel(Binned b, int ntiles, uint32_t slots) {
+__global__ void __launch_bounds__(kScanThreads) bin_scan_kernel(Binned b, int ntiles, int ntx, uint32_t slots) {
     __shared__ uint64_t wsum[kScanThreads / 64];
     __shared__ uint32_t wmax[kScanThreads / 64], wempty[kScanThreads / 64];
+    __shared__ uint8_t lcol[kMaxTileCols];
     const bool compact = (b.status[0] & kStatusCompact) != 0u;
     // record counts: the compact layout's counting pass, or the slabs' cursors
     // (past a full slab a cursor keeps counting records that were not written)
-    split_plan(b, ntiles, slots, wsum, wmax, wempty, [&](int i) -> uint32_t {
+    split_plan(b, ntiles, ntx, slots, wsum, wmax, wempty, lcol, [&](int i) -> uint32_t {
         return compact ? b.cursor[i] : min(b.cursor[i], b.slab[i].y);
     });
     if (!compact) return;   // every slab held its tile
@@ -551,8 +574,9 @@ hipError_t launch_bin_count(const GeoParams &g, const Binned &b, int64_t n, cons
     return hipGetLastError();
 }
 
-hipError_t launch_bin_scan(const Binned &b, int ntiles, uint32_t slots, hipStream_t s) {
-    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, b, ntiles, slots);
+hipError_t launch_bin_scan(const Binned &b, int ntiles, int ntx, uint32_t slots, hipStream_t s) {
+    if (ntx <= 0 || ntx > kMaxTileCols || (ntx & (ntx - 1)) || ntiles % ntx) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, b, ntiles, ntx, slots);
     return hipGetLastError();
 }
 

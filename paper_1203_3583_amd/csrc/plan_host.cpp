@@ -122,7 +122,7 @@ int make_layout(int64_t n, const asf_params *p, Layout &L) {
     L.off_combine = take(sizeof(uint32_t) * kSplitSlotsHost);
     // two 64-bit integer sums (Re, Im) per cell and slice
     L.off_partial = take(L.split ? 16 * (size_t)kSplitSlotsHost * L.tile_x * L.tile_y : 0);
-    L.off_live = take((size_t)L.ntiles);
+    L.off_live = take((size_t)L.ntiles + L.ntx);
     L.total = o;
     return ASF_OK;
 }

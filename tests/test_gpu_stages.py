@@ -282,6 +282,14 @@ def _live_cells(torch, plan, info):
     return np.repeat(np.repeat(live != 0, info["tile_y"], axis=0), info["tile_x"], axis=1)
 
 
+def _live_columns(torch, plan, info):
+    """[gx] True in the tile columns holding a tile some record reaches (the others are
+    zeros, which the column passes may skip and the row passes not touch in mid)."""
+    tx_n = info["nfx"] // info["tile_x"]
+    col = _view(torch, plan, info["off_live"] + info["ntiles"], tx_n, torch.uint8)
+    return np.repeat(col != 0, info["tile_x"])
+
+
 def _fine_natural(torch, plan, info, after_forward=True):
     """The fine grid as [gy, gx].  After a forward, tiles no record reaches may have
     been left unwritten (holding whatever was there); they are taken as zeros, as the
@@ -398,42 +406,57 @@ def test_unwritten_tiles_follow_the_geometry():
     out, adj, live, fine = step()   # sparse geometry, flagged form (from the plan's own status read)
     print(f"sparse: {int((~live).sum())} of {live.size} cells in empty tiles")
     assert (~live).sum() * 4 >= live.size and same((out, adj), want_s)
+    assert plan.info()["skip_empty"] == 1
     plan.setpts(*geo_d)             # dense geometry, still the flagged form
     out, adj, live, fine = step()
     assert same((out, adj), want_d)
     plan.status()                   # dense: every tile written
+    assert plan.info()["skip_empty"] == 0
     out, adj, live, fine = step()
     assert (~live).sum() * 4 < live.size and same((out, adj), want_d)
     plan.setpts(*geo_s)             # sparse geometry, every tile written: zeros in the empty ones
     out, adj, live, fine = step()
     assert same((out, adj), want_s)
+    assert not fine[~live].any()
     plan.setpts(*geo_d)
     plan.status()
     plan.forward(u)                 # the whole fine grid holds the dense sums
     plan.setpts(*geo_s)
     plan.status()                   # sparse again: the empty tiles keep those sums
+    assert plan.info()["skip_empty"] == 1
     out, adj, live, fine = step()
     plan.close()
     assert np.abs(fine[~live]).max() > 0     # stale sums really are there
     assert same((out, adj), want_s)
 
 
+@pytest.mark.parametrize("which", ["even", "crowded"])
 @pytest.mark.parametrize("fft,bar", [("fp32", 2e-6), ("split_fp16", 1e-4)])
-def test_fft_passes_match_numpy(fft, bar):
+def test_fft_passes_match_numpy(fft, bar, which):
+    """Both passes, each from the device's own input to it.  In the crowded relief most
+    tiles are empty: their cells are read as zeros, the columns of tile columns with no
+    reached tile are neither transformed nor read (zeros in the host's check)."""
     torch = torch_gpu()
-    w = _even()
+    w = {"even": _even, "crowded": _crowded}[which]()
     plan, u = _plan(torch, w, fft)
     u2 = plan.forward(u).cpu().numpy().astype(np.complex128)
     info = plan.info()
     fine = _fine_natural(torch, plan, info)
+    cols = _live_columns(torch, plan, info)
+    if which == "even":
+        assert cols.all()
+    else:
+        assert info["skip_empty"] == 1 and not cols.all()
     nfx, nfy, mx, my, C = info["nfx"], info["nfy"], w.mx, w.my, info["col_batch"]
     raw = _view(torch, plan, info["off_mid"], 2 * my * nfx, torch.float32)
     plan.close()
     mid = (raw[0::2] + 1j * raw[1::2]).astype(np.complex128)
     mid = mid.reshape(nfx // C, my, C).transpose(1, 0, 2).reshape(my, nfx)   # [ky, x]
+    mid = np.where(cols[None, :], mid, 0.0)
     # column pass: exp(-i) DFT along y of the device's fine grid, modes -my/2 .. my/2 - 1
     ky = (np.arange(my) - my // 2) % nfy
     want_mid = np.fft.fft(fine, axis=0)[ky, :]
+    assert not want_mid[:, ~cols].any()
     e1 = rel_l2(mid, want_mid)
     # row pass: DFT along x of the device's mid, times 1/psi-hat, the destination chirp
     # and exp(i k z0) / (i lambda z0) (Eq. (8))
@@ -474,7 +497,9 @@ def test_adjoint_stages_match_host(fft, bar, which):
     mid = (raw[0::2] + 1j * raw[1::2]).astype(np.complex128).reshape(my, nfx)   # row-major
     fine = _fine_natural(torch, plan, info, after_forward=False)
     live = _live_cells(torch, plan, info)
+    cols = _live_columns(torch, plan, info)
     plan.close()
+    mid = np.where(cols[None, :], mid, 0.0)   # columns the column pass does not need
     k = 2.0 * np.pi / w.lam
     m = np.arange(mx) - mx // 2
     n = np.arange(my) - my // 2
@@ -486,13 +511,13 @@ def test_adjoint_stages_match_host(fft, bar, which):
     pad = np.zeros((my, nfx), dtype=np.complex128)
     pad[:, m % nfx] = g
     want_mid = np.fft.ifft(pad, axis=1) * nfx                 # exp(+i), unnormalised
-    e1 = rel_l2(mid, want_mid)
+    e1 = rel_l2(mid[:, cols], want_mid[:, cols])
     padc = np.zeros((nfy, nfx), dtype=np.complex128)
     padc[n % nfy, :] = mid
     want_fine = np.fft.ifft(padc, axis=0) * nfy
     e2 = rel_l2(fine[live], want_fine[live])
     if which == "even":
-        assert live.all()
+        assert live.all() and cols.all()
     # interpolation from the device's fine grid, exact kernel values
     cx, cy, ox, oy, ph = _host_points(w, nfx, nfy, wid)
     a = np.arange(wid)
