@@ -49,7 +49,6 @@ struct asf_plan_s {
     float2 *fine, *mid, *dx, *dy, *twx, *twy, *w16;
     int timing;
     bool count_first;   // bin with the compact layout directly (crowded last time)
-    bool sized_slabs;   // the slabs were sized from a crowded binning's counts
     bool sparse;        // many tiles empty last time: leave them unwritten, the column pass reads zeros
     int copy;           // which copy of status and cursor the last binning used
     bool clear_both;    // clear both copies first (new plan, or a failed binning launch)
@@ -112,7 +111,7 @@ int geometry_launches(asf_plan_s *p, const double *x, const double *y, const dou
             e = asf::launch_bin_count(p->geo, p->bin, p->lay.n, x, y, d, s);
             if (e != hipSuccess) return hip_fail(e, "bin_count launch");
         } else {
-            e = asf::launch_bin_fill(p->geo, p->bin, p->lay.n, x, y, d, p->sized_slabs, s);
+            e = asf::launch_bin_fill(p->geo, p->bin, p->lay.n, x, y, d, s);
             if (e != hipSuccess) return hip_fail(e, "bin_fill launch");
         }
     }
@@ -212,7 +211,6 @@ int read_status(asf_plan_s *p, hipStream_t s) {
     // binning counts first if this one needed the compact layout, unless its
     // scan sized new slabs from the counts that fit in the slot arrays
     p->count_first = (st & asf::kStatusCompact) && !(st & asf::kStatusFits);
-    if ((st & asf::kStatusCompact) && (st & asf::kStatusFits)) p->sized_slabs = true;
     if (st & asf::kStatusDomain)
         return fail(ASF_EDOMAIN, "some point has r0 = z0 - d1 <= 0 or a non-finite coordinate");
     if (st & asf::kStatusOverflow) return fail(ASF_EHIP, "internal error: tile bin overflow");

@@ -203,9 +203,9 @@ hipError_t launch_bin_reset(const Binned &b, int ntiles, hipStream_t s);
 // once unless the status word says the compact layout is in use
 hipError_t launch_bin_count(const GeoParams &g, const Binned &b, int64_t n, const double *x,
                             const double *y, const double *d, hipStream_t s);
-// crowded: slabs sized from a compact binning's counts (fewer workgroups at a time)
+// the slab pass: one workgroup per point block, the blocks in a scattered order
 hipError_t launch_bin_fill(const GeoParams &g, const Binned &b, int64_t n, const double *x,
-                           const double *y, const double *d, bool crowded, hipStream_t s);
+                           const double *y, const double *d, hipStream_t s);
 // (and the slices of crowded tiles: slots = workgroups resident at once, 0 = never cut)
 hipError_t launch_bin_scan(const Binned &b, int ntiles, int ntx, uint32_t slots, hipStream_t s);
 // (and, in every launch, clears next_status and next_cursor)
