@@ -49,8 +49,8 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "make_eval_sets.py")
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="cap_2048", choices=sorted(WORKLOADS),
                     help="surface to time (the headline is cap_2048; the others are the small "
                          "and the large configuration)")
