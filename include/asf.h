@@ -92,8 +92,8 @@ typedef struct {
     int32_t tile_x, tile_y; /* spreading tile edges in fine cells */
     int32_t ntiles;       /* tiles in the fine grid */
     int64_t slot_cap;     /* capacity of the binned point list (4 n_src) */
-    int32_t col_batch;    /* panel width C of the fine grid and FFT intermediate (adjacent columns
-                             stored together; columns per workgroup in the first FFT pass) */
+    int32_t col_batch;    /* panel width C of the fine grid (adjacent columns stored together;
+                             columns per workgroup in the first FFT pass) */
     uint32_t flags;
     /* byte offsets into the workspace of buffers tests may inspect (off_status and
      * off_cursor: the copy of the counters the latest binning used; two binnings
@@ -122,6 +122,9 @@ typedef struct {
     /* 1 while the plan's transforms leave those tiles unwritten (a quarter or more of
        the tiles were empty at the last status read), else 0 */
     uint32_t skip_empty;
+    /* panel width of the first FFT pass's output (element (x, ky) at ((x / P) my + ky) P + x % P):
+       col_batch, or more where several first-pass workgroups fill one panel */
+    int32_t mid_panel;
 } asf_info;
 
 /*

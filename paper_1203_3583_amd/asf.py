@@ -58,7 +58,7 @@ class Info(ctypes.Structure):
                 ("off_slab", ctypes.c_size_t), ("off_split", ctypes.c_size_t),
                 ("off_split_meta", ctypes.c_size_t), ("off_slot_owner", ctypes.c_size_t),
                 ("split_slots", ctypes.c_uint32), ("off_live", ctypes.c_size_t),
-                ("skip_empty", ctypes.c_uint32)]
+                ("skip_empty", ctypes.c_uint32), ("mid_panel", ctypes.c_int32)]
 
 
 class LineParams(ctypes.Structure):

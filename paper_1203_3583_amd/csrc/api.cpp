@@ -46,6 +46,7 @@ struct asf_plan_s {
     asf::GeoParams geo;
     asf::SpreadParams sp;
     FftShape sh1, sh2;
+    int mid_panel;      // columns per panel of the column pass's output (sh1.batch or more)
     float2 *fine, *mid, *dx, *dy, *twx, *twy, *w16;
     int timing;
     bool count_first;   // bin with the compact layout directly (crowded last time)
@@ -294,6 +295,7 @@ int asf_plan(asf_plan_t *out, int64_t n_src, const double *x1, const double *y1,
     const int panel = asf::fft_batch_pass1(L.nfy);
     pl->sh1.L = L.nfy;
     pl->sh1.batch = panel;
+    pl->mid_panel = asf::fft_mid_panel(L.nfy);
     pl->sh2.L = L.nfx;
     pl->sh2.batch = asf::fft_batch_pass2(L.nfx);
     if (panel > L.tile_x || L.nfx % panel != 0 || L.my % pl->sh2.batch != 0 ||
@@ -380,7 +382,7 @@ int forward_into(asf_plan_t plan, const void *u1, void *u2, void *stream, int ac
     }
     {
         StageMark m(p, asf::STAGE_FFT2, s);
-        e = asf::launch_fft_pass2(p->sh2, log2i(p->sh1.batch), split, mid, static_cast<float2 *>(u2),
+        e = asf::launch_fft_pass2(p->sh2, log2i(p->mid_panel), split, mid, static_cast<float2 *>(u2),
                                   p->twx, p->w16, p->dx, p->dy, p->lay.mx, p->lay.my, accumulate,
                                   live_tiles(p), s);
         if (e != hipSuccess) return hip_fail(e, "fft pass 2 launch");
@@ -462,6 +464,7 @@ int asf_plan_info(asf_plan_t plan, asf_info *info) {
     info->ntiles = L.ntiles;
     info->slot_cap = L.slot_cap;
     info->col_batch = plan->sh1.batch;
+    info->mid_panel = plan->mid_panel;
     info->flags = plan->prm.flags;
     info->off_status = plan->copy ? L.off_status2 : L.off_status;
     info->off_tile_start = L.off_tile_start;

@@ -240,6 +240,7 @@ constexpr size_t kStaticScratchBytes = ASF_STATIC_SCRATCH_BYTES;
 hipError_t static_scratch(void **out);
 
 int fft_batch_pass1(int len);          // columns per workgroup in pass 1 (fine-grid panel width)
+int fft_mid_panel(int len);            // columns per panel of pass 1's output (mid)
 int fft_batch_pass2(int len);          // rows per workgroup in pass 2
 size_t fft_lds_bytes(int len, int batch);
 int fft_max_lds_bytes();

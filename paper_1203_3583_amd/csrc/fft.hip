@@ -622,7 +622,7 @@ __global__ void __launch_bounds__(NT) fft_adj_rows_kernel(const float2 *__restri
 // flags, only the cells of tiles some record reaches, which are all that the
 // interpolation uses).  The 16 / BATCH
 // panels that share 128-byte lines of mid rows run on one XCD.
-template <int LOGL, int BATCH, int NT, bool SPLIT>
+template <int LOGL, int BATCH, int NT, bool SPLIT, int FP>
 __global__ void __launch_bounds__(NT) fft_adj_cols_kernel(const float2 *__restrict__ mid,
                                                           float2 *__restrict__ fine,
                                                           const float2 *__restrict__ tw,
@@ -673,12 +673,24 @@ __global__ void __launch_bounds__(NT) fft_adj_cols_kernel(const float2 *__restri
         unscale = ldexpf(1.f, e);
     }
     transform_all<LOGL, BATCH, NT, SPLIT>(lds, tw, w16, inv);
-    float2 *dst = fine + (size_t)pc * S::L * BATCH;
-    for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
-        const int l = t / BATCH, c = t % BATCH;
-        if (sparse && !lrow[l >> lt.log_tile_y]) continue;
-        const float2 v = lds[c * S::STRIDE + lds_pos<S::PS>(l)];
-        dst[t] = make_float2(v.x * unscale, -v.y * unscale);
+    if constexpr (FP == BATCH) {
+        float2 *dst = fine + (size_t)pc * S::L * BATCH;
+        for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
+            const int l = t / BATCH, c = t % BATCH;
+            if (sparse && !lrow[l >> lt.log_tile_y]) continue;
+            const float2 v = lds[c * S::STRIDE + lds_pos<S::PS>(l)];
+            dst[t] = make_float2(v.x * unscale, -v.y * unscale);
+        }
+    } else {
+        // the fine grid in panels of FP < BATCH columns (FP = 1: column-major)
+        static_assert(FP == 1, "narrower fine-grid panels are single columns");
+        float2 *dst = fine + (size_t)pc * S::L * BATCH;   // this workgroup's BATCH whole columns
+        for (int t = threadIdx.x; t < S::L * BATCH; t += NT) {
+            const int c = t >> LOGL, l = t & (S::L - 1);
+            if (sparse && !lrow[l >> lt.log_tile_y]) continue;
+            const float2 v = lds[c * S::STRIDE + lds_pos<S::PS>(l)];
+            dst[t] = make_float2(v.x * unscale, -v.y * unscale);
+        }
     }
 }
 
@@ -840,19 +852,29 @@ __device__ __forceinline__ void transform_direct(float2 *lds, const float2 *tw, 
 }
 
 // Pass 1 for L = 16^a: a workgroup transforms one panel of BATCH adjacent columns.
-template <int LOGL, int BATCH, int NT, bool SPLIT>
+// mid's panels hold MP >= BATCH columns: the MP / BATCH workgroups that fill one
+// panel (each writing its columns' pieces of the panel's lines) run on one XCD when
+// xcd_pair is set, so that its L2 merges the pieces before they reach HBM.
+template <int LOGL, int BATCH, int NT, bool SPLIT, int MP>
 __global__ void __launch_bounds__(NT) fft_pass1_direct_kernel(const float2 *__restrict__ fine,
                                                               float2 *__restrict__ mid,
                                                               const float2 *__restrict__ tw,
                                                               const float2 *__restrict__ w16, int my,
-                                                              LiveTiles lt) {
+                                                              LiveTiles lt, int xcd_pair) {
     using S = Len<LOGL>;
+    static_assert(MP % BATCH == 0, "mid panels hold whole column batches");
     extern __shared__ float2 lds[];
     __shared__ float scratch[NT / 64];
     __shared__ uint8_t lrow[kMaxTileRows];
-    const int pc = blockIdx.x;
+    int pc = blockIdx.x;
+    if (MP > BATCH && xcd_pair) {
+        constexpr int G = MP / BATCH;
+        const int xcd = pc & 7, slot = pc >> 3;
+        pc = ((slot / G) * 8 + xcd) * G + slot % G;
+    }
     const float2 *src = fine + (size_t)pc * S::L * BATCH;
-    float2 *dst = mid + (size_t)pc * my * BATCH;   // this panel's block of mid
+    const int x0 = pc * BATCH;
+    float2 *dst = mid + (size_t)(x0 / MP) * my * MP + x0 % MP;   // this batch's columns of its mid panel
     const int half = my >> 1;
     if (!column_needed(lt, pc * BATCH)) return;
     const bool sparse = live_rows(lt, pc * BATCH, lrow);
@@ -863,7 +885,7 @@ __global__ void __launch_bounds__(NT) fft_pass1_direct_kernel(const float2 *__re
         },
         [&](int c, int l, float2 val) {
             const int ky = (l + half) & (S::L - 1);
-            if (ky < my) dst[ky * BATCH + c] = val;
+            if (ky < my) dst[ky * MP + c] = val;
         });
 }
 
@@ -929,7 +951,7 @@ constexpr int threads_for() {
     return nt;
 }
 
-template <int LOGL, int BATCH, bool SPLIT>
+template <int LOGL, int BATCH, bool SPLIT, int MP = BATCH>
 hipError_t launch1(const FftShape &sh, const float2 *fine, float2 *mid, const float2 *tw,
                    const float2 *w16, int nfx, int my, const LiveTiles &lt, hipStream_t s) {
     (void)sh;
@@ -937,11 +959,14 @@ hipError_t launch1(const FftShape &sh, const float2 *fine, float2 *mid, const fl
     const size_t lds = (size_t)BATCH * Len<LOGL>::STRIDE * sizeof(float2);
     static thread_local size_t enabled = 0;
     if constexpr (LOGL % 4 == 0 && LOGL >= 8) {
-        auto k = fft_pass1_direct_kernel<LOGL, BATCH, NT, SPLIT>;
+        auto k = fft_pass1_direct_kernel<LOGL, BATCH, NT, SPLIT, MP>;
         hipError_t e = allow_lds((const void *)k, lds, enabled);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k, dim3(nfx / BATCH), dim3(NT), lds, s, fine, mid, tw, w16, my, lt);
+        const int groups = nfx / BATCH;
+        const int xcd_pair = (MP > BATCH && groups % (8 * (MP / BATCH)) == 0) ? 1 : 0;
+        hipLaunchKernelGGL(k, dim3(groups), dim3(NT), lds, s, fine, mid, tw, w16, my, lt, xcd_pair);
     } else {
+        static_assert(MP == BATCH, "wider mid panels only with the direct-I/O kernel");
         auto k = fft_pass1_kernel<LOGL, BATCH, NT, SPLIT>;
         hipError_t e = allow_lds((const void *)k, lds, enabled);
         if (e != hipSuccess) return e;
@@ -993,13 +1018,13 @@ hipError_t launch_adj2(const float2 *g2, float2 *mid, const float2 *tw, const fl
     return hipGetLastError();
 }
 
-template <int LOGL, int BATCH, bool SPLIT>
+template <int LOGL, int BATCH, bool SPLIT, int FP = BATCH>
 hipError_t launch_adj1(const float2 *mid, float2 *fine, const float2 *tw, const float2 *w16,
                        int nfx, int my, const LiveTiles &lt, hipStream_t s) {
     constexpr int NT = threads_for<LOGL, BATCH>();
     const size_t lds = (size_t)BATCH * Len<LOGL>::STRIDE * sizeof(float2);
     static thread_local size_t enabled = 0;
-    auto k = fft_adj_cols_kernel<LOGL, BATCH, NT, SPLIT>;
+    auto k = fft_adj_cols_kernel<LOGL, BATCH, NT, SPLIT, FP>;
     hipError_t e = allow_lds((const void *)k, lds, enabled);
     if (e != hipSuccess) return e;
     const int groups = nfx / BATCH;
@@ -1038,7 +1063,7 @@ hipError_t dispatch_adj1(int len, const float2 *mid, float2 *fine, const float2 
         case 9: return launch_adj1<9, 16, SPLIT>(mid, fine, tw, w16, nfx, my, lt, s);
         case 10: return launch_adj1<10, 8, SPLIT>(mid, fine, tw, w16, nfx, my, lt, s);
         case 11: return launch_adj1<11, 4, SPLIT>(mid, fine, tw, w16, nfx, my, lt, s);
-        case 12: return launch_adj1<12, 2, SPLIT>(mid, fine, tw, w16, nfx, my, lt, s);
+        case 12: return launch_adj1<12, 2, SPLIT, 1>(mid, fine, tw, w16, nfx, my, lt, s);
         case 13: return launch_adj1<13, 1, SPLIT>(mid, fine, tw, w16, nfx, my, lt, s);
         case 14: return launch_adj1<14, 1, SPLIT>(mid, fine, tw, w16, nfx, my, lt, s);
         default: return hipErrorInvalidValue;
@@ -1063,7 +1088,7 @@ hipError_t dispatch1(const FftShape &sh, const float2 *fine, float2 *mid, const 
         case 9: return launch1<9, 16, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
         case 10: return launch1<10, 8, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
         case 11: return launch1<11, 4, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
-        case 12: return launch1<12, 2, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
+        case 12: return launch1<12, 1, SPLIT, 2>(sh, fine, mid, tw, w16, nfx, my, lt, s);
         case 13: return launch1<13, 1, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
         case 14: return launch1<14, 1, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
         default: return hipErrorInvalidValue;
@@ -1094,7 +1119,11 @@ hipError_t dispatch2(const FftShape &sh, int log_panel, const float2 *mid, float
 
 int fft_batch_pass1(int len) {
     const int log = __builtin_ctz(len);
-    return log <= 9 ? 16 : log == 10 ? 8 : log == 11 ? 4 : log == 12 ? 2 : 1;
+    return log <= 9 ? 16 : log == 10 ? 8 : log == 11 ? 4 : 1;
+}
+
+int fft_mid_panel(int len) {
+    return __builtin_ctz(len) == 12 ? 2 : fft_batch_pass1(len);
 }
 
 int fft_batch_pass2(int len) {

@@ -447,11 +447,11 @@ def test_fft_passes_match_numpy(fft, bar, which):
         assert cols.all()
     else:
         assert info["skip_empty"] == 1 and not cols.all()
-    nfx, nfy, mx, my, C = info["nfx"], info["nfy"], w.mx, w.my, info["col_batch"]
+    nfx, nfy, mx, my, P = info["nfx"], info["nfy"], w.mx, w.my, info["mid_panel"]
     raw = _view(torch, plan, info["off_mid"], 2 * my * nfx, torch.float32)
     plan.close()
     mid = (raw[0::2] + 1j * raw[1::2]).astype(np.complex128)
-    mid = mid.reshape(nfx // C, my, C).transpose(1, 0, 2).reshape(my, nfx)   # [ky, x]
+    mid = mid.reshape(nfx // P, my, P).transpose(1, 0, 2).reshape(my, nfx)   # [ky, x]
     mid = np.where(cols[None, :], mid, 0.0)
     # column pass: exp(-i) DFT along y of the device's fine grid, modes -my/2 .. my/2 - 1
     ky = (np.arange(my) - my // 2) % nfy
