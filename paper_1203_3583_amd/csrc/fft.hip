@@ -1071,11 +1071,12 @@ hipError_t dispatch_adj1(int len, const float2 *mid, float2 *fine, const float2 
 }
 
 // Batch sizes used per length (the same as fft_batch_pass1/2): pass 1 holds up to
-// 70 KB of LDS -- 16 columns up to 512 points, then 8, 4, and 2 at 4096 (two
-// workgroups per CU; against one column the pass costs 7 us more and the row pass,
-// gathering 16-byte pieces of mid's lines instead of 8, saves 15 us at the 4096^2
-// fine grid) -- and one column from 8192 up; pass 2 uses one row unless the row is
-// shorter than 256.
+// 70 KB of LDS -- 16 columns up to 512 points, then 8, 4, and one column from 4096
+// up.  At 4096 mid keeps panels of two columns (fft_mid_panel), filled by two
+// one-column workgroups on one XCD: the row pass gathers 16-byte pieces of mid's
+// lines instead of 8 (15 us less at the 4096^2 fine grid) while pass 1 keeps four
+// 35 KB workgroups per CU.  The adjoint's column pass takes two columns at 4096 and
+// stores them column-major.  Pass 2 uses one row unless the row is shorter than 256.
 template <bool SPLIT>
 hipError_t dispatch1(const FftShape &sh, const float2 *fine, float2 *mid, const float2 *tw,
                      const float2 *w16, int nfx, int my, const LiveTiles &lt, hipStream_t s) {
