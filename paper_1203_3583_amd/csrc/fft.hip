@@ -417,18 +417,25 @@ __device__ __forceinline__ bool live_cols(const LiveTiles &lt, uint8_t *lcol) {
     return true;
 }
 
-// Pass 1: a workgroup transforms one panel of BATCH adjacent fine-grid columns.
-template <int LOGL, int BATCH, int NT, bool SPLIT>
+// Pass 1: a workgroup transforms one panel of BATCH adjacent fine-grid columns
+// (mid's panels hold MP >= BATCH columns, as in the direct-I/O kernel below).
+template <int LOGL, int BATCH, int NT, bool SPLIT, int MP>
 __global__ void __launch_bounds__(NT) fft_pass1_kernel(const float2 *__restrict__ fine,
                                                        float2 *__restrict__ mid,
                                                        const float2 *__restrict__ tw,
                                                        const float2 *__restrict__ w16, int my,
-                                                       LiveTiles lt) {
+                                                       LiveTiles lt, int xcd_pair) {
     using S = Len<LOGL>;
+    static_assert(MP % BATCH == 0, "mid panels hold whole column batches");
     extern __shared__ float2 lds[];
     __shared__ float scratch[NT / 64];
     __shared__ uint8_t lrow[kMaxTileRows];
-    const int pc = blockIdx.x;
+    int pc = blockIdx.x;
+    if (MP > BATCH && xcd_pair) {
+        constexpr int G = MP / BATCH;
+        const int xcd = pc & 7, slot = pc >> 3;
+        pc = ((slot / G) * 8 + xcd) * G + slot % G;
+    }
     const float2 *src = fine + (size_t)pc * S::L * BATCH;
     if (!column_needed(lt, pc * BATCH)) return;
     const bool sparse = live_rows(lt, pc * BATCH, lrow);
@@ -459,12 +466,13 @@ __global__ void __launch_bounds__(NT) fft_pass1_kernel(const float2 *__restrict_
     }
     transform_all<LOGL, BATCH, NT, SPLIT>(lds, tw, w16, inv);
     const int half = my >> 1;
-    float2 *dst = mid + (size_t)pc * my * BATCH;   // this panel's block of mid
+    const int x0 = pc * BATCH;
+    float2 *dst = mid + (size_t)(x0 / MP) * my * MP + x0 % MP;   // this batch's columns of its mid panel
     for (int t = threadIdx.x; t < my * BATCH; t += NT) {
         const int ky = t / BATCH, c = t % BATCH;
         const int l = (ky - half) & (S::L - 1);
         const float2 v = lds[c * S::STRIDE + lds_pos<S::PS>(l)];
-        dst[t] = make_float2(v.x * unscale, v.y * unscale);
+        dst[ky * MP + c] = make_float2(v.x * unscale, v.y * unscale);
     }
 }
 
@@ -966,11 +974,12 @@ hipError_t launch1(const FftShape &sh, const float2 *fine, float2 *mid, const fl
         const int xcd_pair = (MP > BATCH && groups % (8 * (MP / BATCH)) == 0) ? 1 : 0;
         hipLaunchKernelGGL(k, dim3(groups), dim3(NT), lds, s, fine, mid, tw, w16, my, lt, xcd_pair);
     } else {
-        static_assert(MP == BATCH, "wider mid panels only with the direct-I/O kernel");
-        auto k = fft_pass1_kernel<LOGL, BATCH, NT, SPLIT>;
+        auto k = fft_pass1_kernel<LOGL, BATCH, NT, SPLIT, MP>;
         hipError_t e = allow_lds((const void *)k, lds, enabled);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k, dim3(nfx / BATCH), dim3(NT), lds, s, fine, mid, tw, w16, my, lt);
+        const int groups = nfx / BATCH;
+        const int xcd_pair = (MP > BATCH && groups % (8 * (MP / BATCH)) == 0) ? 1 : 0;
+        hipLaunchKernelGGL(k, dim3(groups), dim3(NT), lds, s, fine, mid, tw, w16, my, lt, xcd_pair);
     }
     return hipGetLastError();
 }
@@ -1072,10 +1081,11 @@ hipError_t dispatch_adj1(int len, const float2 *mid, float2 *fine, const float2 
 
 // Batch sizes used per length (the same as fft_batch_pass1/2): pass 1 holds up to
 // 70 KB of LDS -- 16 columns up to 512 points, then 8, 4, and one column from 4096
-// up.  At 4096 mid keeps panels of two columns (fft_mid_panel), filled by two
-// one-column workgroups on one XCD: the row pass gathers 16-byte pieces of mid's
-// lines instead of 8 (15 us less at the 4096^2 fine grid) while pass 1 keeps four
-// 35 KB workgroups per CU.  The adjoint's column pass takes two columns at 4096 and
+// up.  At 4096 and 8192 mid keeps panels of two and four columns (fft_mid_panel),
+// each filled by that many one-column workgroups on one XCD: the row pass gathers
+// 16- and 32-byte pieces of mid's lines instead of 8 (15 us less at the 4096^2 fine
+// grid, 35 us at 8192^2, where pass 1 pays 15 us of it back) while pass 1 keeps one
+// column per workgroup.  The adjoint's column pass takes two columns at 4096 and
 // stores them column-major.  Pass 2 uses one row unless the row is shorter than 256.
 template <bool SPLIT>
 hipError_t dispatch1(const FftShape &sh, const float2 *fine, float2 *mid, const float2 *tw,
@@ -1090,7 +1100,7 @@ hipError_t dispatch1(const FftShape &sh, const float2 *fine, float2 *mid, const 
         case 10: return launch1<10, 8, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
         case 11: return launch1<11, 4, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
         case 12: return launch1<12, 1, SPLIT, 2>(sh, fine, mid, tw, w16, nfx, my, lt, s);
-        case 13: return launch1<13, 1, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
+        case 13: return launch1<13, 1, SPLIT, 4>(sh, fine, mid, tw, w16, nfx, my, lt, s);
         case 14: return launch1<14, 1, SPLIT>(sh, fine, mid, tw, w16, nfx, my, lt, s);
         default: return hipErrorInvalidValue;
     }
@@ -1124,7 +1134,8 @@ int fft_batch_pass1(int len) {
 }
 
 int fft_mid_panel(int len) {
-    return __builtin_ctz(len) == 12 ? 2 : fft_batch_pass1(len);
+    const int log = __builtin_ctz(len);
+    return log == 12 ? 2 : log == 13 ? 4 : fft_batch_pass1(len);
 }
 
 int fft_batch_pass2(int len) {
