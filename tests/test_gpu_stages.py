@@ -275,16 +275,23 @@ def _psi(z, wid, beta):
     return np.where(a >= 0.0, np.exp(beta * (np.sqrt(np.maximum(a, 0.0)) - 1.0)), 0.0)
 
 
-def _live_cells(torch, plan, info):
-    """[gy, gx] True in the tiles the binning flags as reached by some record."""
+def _live_cells(torch, plan, info, flags=False):
+    """[gy, gx] True in the tiles the binning flags as reached by some record (flags), or,
+    by default, in the tiles the transforms write: those, in the plan's sparse form, else
+    all (grids too small for cut tiles have no flags)."""
+    if not flags and not plan.info()["skip_empty"]:
+        return np.ones((info["nfy"], info["nfx"]), dtype=bool)
     tx_n, ty_n = info["nfx"] // info["tile_x"], info["nfy"] // info["tile_y"]
     live = _view(torch, plan, info["off_live"], tx_n * ty_n, torch.uint8).reshape(ty_n, tx_n)
     return np.repeat(np.repeat(live != 0, info["tile_y"], axis=0), info["tile_x"], axis=1)
 
 
-def _live_columns(torch, plan, info):
+def _live_columns(torch, plan, info, flags=False):
     """[gx] True in the tile columns holding a tile some record reaches (the others are
-    zeros, which the column passes may skip and the row passes not touch in mid)."""
+    zeros, which the column passes skip and the row passes do not touch in mid in the
+    plan's sparse form); by default all columns outside the sparse form."""
+    if not flags and not plan.info()["skip_empty"]:
+        return np.ones(info["nfx"], dtype=bool)
     tx_n = info["nfx"] // info["tile_x"]
     col = _view(torch, plan, info["off_live"] + info["ntiles"], tx_n, torch.uint8)
     return np.repeat(col != 0, info["tile_x"])
@@ -389,7 +396,7 @@ def test_unwritten_tiles_follow_the_geometry():
 
     def step():
         out = plan.forward(u).cpu().numpy()
-        live = _live_cells(torch, plan, info)
+        live = _live_cells(torch, plan, info, flags=True)
         fine = _fine_natural(torch, plan, info, after_forward=False)
         # the flags name exactly the tiles some record reaches
         _, ranges = _device_bins(torch, plan, plan.info())   # the binning's copy of the counters
@@ -430,22 +437,34 @@ def test_unwritten_tiles_follow_the_geometry():
     assert same((out, adj), want_s)
 
 
-@pytest.mark.parametrize("which", ["even", "crowded"])
+def _skinny(my):
+    """The even points onto a 16-column destination my rows high: columns of 2 my
+    points, whose column pass writes mid in panels wider than its one column."""
+    import dataclasses
+    return dataclasses.replace(_even(), name=f"skinny_{my}", mx=16, my=my)
+
+
+@pytest.mark.parametrize("which", ["even", "crowded", "skinny_2048", "skinny_4096"])
 @pytest.mark.parametrize("fft,bar", [("fp32", 2e-6), ("split_fp16", 1e-4)])
 def test_fft_passes_match_numpy(fft, bar, which):
     """Both passes, each from the device's own input to it.  In the crowded relief most
     tiles are empty: their cells are read as zeros, the columns of tile columns with no
-    reached tile are neither transformed nor read (zeros in the host's check)."""
+    reached tile are neither transformed nor read (zeros in the host's check).  The
+    skinny grids have 4096- and 8192-point columns: one column per column-pass
+    workgroup, mid in panels of two and four columns."""
     torch = torch_gpu()
-    w = {"even": _even, "crowded": _crowded}[which]()
+    w = {"even": _even, "crowded": _crowded, "skinny_2048": lambda: _skinny(2048),
+         "skinny_4096": lambda: _skinny(4096)}[which]()
     plan, u = _plan(torch, w, fft)
     u2 = plan.forward(u).cpu().numpy().astype(np.complex128)
     info = plan.info()
     fine = _fine_natural(torch, plan, info)
     cols = _live_columns(torch, plan, info)
+    if which.startswith("skinny"):
+        assert info["col_batch"] == 1 and info["mid_panel"] == {2048: 2, 4096: 4}[w.my]
     if which == "even":
         assert cols.all()
-    else:
+    elif which == "crowded":
         assert info["skip_empty"] == 1 and not cols.all()
     nfx, nfy, mx, my, P = info["nfx"], info["nfy"], w.mx, w.my, info["mid_panel"]
     raw = _view(torch, plan, info["off_mid"], 2 * my * nfx, torch.float32)
