@@ -97,6 +97,19 @@ __device__ inline PointTiles point_tiles(const GeoParams &g, double x, double y,
     return p;
 }
 
+// The pre-phase of Eq. (8) in revolutions, reduced to [-1/2, 1/2]: phi / (2 pi) =
+// k (|x|^2 / (2 r0) [- d]) / (2 pi) = |x|^2 s / 2 [- d / lambda], and for an off-axis
+// window -k (x x0 + y y0) / r0 = -2 pi (x x0 + y y0) s.  FP64 with contraction off, so
+// that every binning pass forms the same bits for a point; the integer part is removed
+// exactly, then one rounding to FP32.
+__device__ inline float prephase_revolutions(const GeoParams &g, double x, double y, double d, double s) {
+#pragma clang fp contract(off)
+    double rev = 0.5 * s * (x * x + y * y);
+    if (!g.plane) rev -= d * g.inv_lambda;
+    rev -= (x * g.x0 + y * g.y0) * s;
+    return (float)(rev - rint(rev));
+}
+
 // Group the active lanes of a wave by key (no memory traffic).  Every lane gets
 // the lane id of its group's leader (the lowest lane with that key) and its
 // rank within the group; leaders also get the group size.  All lanes of the
@@ -219,14 +232,8 @@ __device__ inline void bin_block(const GeoParams &g, const Binned &b, int64_t n,
     for (int k = 0; k < kBinPoints; ++k) {
         float2 ph = make_float2(0.f, 0.f);
         if (p[k].n > 0) {
-            // phi / (2 pi) = k (|x|^2 / (2 r0) [- d]) / (2 pi) = |x|^2 s / 2 [- d / lambda]
-            double rev = 0.5 * p[k].s * (xv[k] * xv[k] + yv[k] * yv[k]);
-            if (!g.plane) rev -= dv[k] * g.inv_lambda;
-            // off-axis window: -k (x x0 + y y0) / r0 = -2 pi (x x0 + y y0) s
-            rev -= (xv[k] * g.x0 + yv[k] * g.y0) * p[k].s;
-            const float t = (float)(rev - rint(rev));   // exact in FP64, then one rounding
             float sn, cs;
-            sincospif(2.f * t, &sn, &cs);
+            sincospif(2.f * prephase_revolutions(g, xv[k], yv[k], dv[k], p[k].s), &sn, &cs);
             ph = make_float2(cs, sn);
         }
         const uint32_t cell = (uint32_t)p[k].l0x | ((uint32_t)p[k].l0y << 16);

@@ -172,7 +172,8 @@ def test_binning_layout_switches_with_crowding():
     compact binning sizes new slabs from its tile counts, which the next binning
     of the same geometry fills in one pass, and which overflow again when the
     geometry changes back.  Every binning reproduces a fresh plan bit for bit and
-    the oracle."""
+    the oracle, and binnings of one geometry in either layout give the same forward and
+    adjoint bit for bit (the slab and compact passes form the same records)."""
     torch = torch_gpu()
     import dataclasses
     import paper_1203_3583_amd as asf
@@ -191,12 +192,15 @@ def test_binning_layout_switches_with_crowding():
     info = plan.info()
     assert crowd.size > info["slot_cap"] // info["ntiles"]   # crowded tiles cannot fit a slab
     copies = []
+    g2 = torch.from_numpy(synth.random_field(np.random.default_rng(13), even.mx, even.my)).cuda()
+    adjoints = []
 
     def run():
         # binnings alternate between two copies of the status word and cursors
         plan.status()
         at = plan.info()["off_status"]
         copies.append(at)
+        adjoints.append(plan.adjoint(g2).cpu().numpy())
         return int(plan.workspace_view(at, 1, torch.int32).item()), plan.forward(u).cpu().numpy()
 
     seq = [run()]                                    # slabs
@@ -210,6 +214,10 @@ def test_binning_layout_switches_with_crowding():
     f_even, f_crowd = seq[0][1], seq[1][1]
     assert np.array_equal(seq[2][1], f_crowd)
     assert np.array_equal(seq[3][1], f_even) and np.array_equal(seq[4][1], f_even)
+    # the adjoint carries each record's pre-phase in FP32 sums, unrounded: equal bits
+    # mean both binning passes formed the same records
+    assert np.array_equal(adjoints[2], adjoints[1])
+    assert np.array_equal(adjoints[3], adjoints[0]) and np.array_equal(adjoints[4], adjoints[0])
     # the adjoint in the compact layout: <A u, g> = <u, A^H g>
     plan.setpts(xc, yc, dc)
     g = torch.from_numpy(synth.random_field(rng, even.mx, even.my)).cuda()
