@@ -303,8 +303,9 @@ def _fine_natural(torch, plan, info, after_forward=True):
     column pass reads them."""
     nfx, nfy, C = info["nfx"], info["nfy"], info["col_batch"]
     raw = _view(torch, plan, info["off_fine"], 2 * nfx * nfy, torch.float32)
-    # (re, im) pairs as complex without arithmetic: unwritten tiles may hold any bits
-    v = np.ascontiguousarray(raw).view(np.complex64).astype(np.complex128)
+    # (re, im) pairs as complex: unwritten tiles may hold any bits, signalling NaNs too
+    with np.errstate(invalid="ignore"):
+        v = np.ascontiguousarray(raw).view(np.complex64).astype(np.complex128)
     # element (gx, gy) at ((gx / C) nfy + gy) C + gx % C -> [gy, gx]
     fine = v.reshape(nfx // C, nfy, C).transpose(1, 0, 2).reshape(nfy, nfx)
     if after_forward:
